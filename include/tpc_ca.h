@@ -1,0 +1,227 @@
+/*
+ * tpc_ca.h — C ABI of the MI355X (gfx950) cellular-automaton TPC track finder.
+ *
+ * Method: per-sector track finding of the ALICE Run 3 TPC reconstruction
+ * (arXiv:1910.12214, Sec. 2 and Sec. 3: derived from the Run 2 HLT GPU tracker,
+ * same physics on CPU and GPU, no dependence of hit assignment on processing
+ * order).  Steps: row-binned hit grid, neighbour finding and cleaning, start-hit
+ * selection, two-pass Kalman tracklet construction and following in the
+ * sector-local helix model, tracklet selection.  Input clusters are FP32
+ * (Sec. 4, step 2).  Continuous-readout time frames (Sec. 1) are tracked in one
+ * call by tpc_track_timeframe.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked (device) must point to GPU memory of the context's device;
+ *    (host) to CPU memory.  The caller owns every input and output buffer; the
+ *    library never frees caller memory.  The context owns its scratch memory
+ *    (grid, links, tracklets, queues, graphs) and grows it on demand.
+ *  - Work is enqueued on the given HIP stream (hipStream_t passed as void*;
+ *    NULL = the null stream).  Calls return once the work is enqueued unless
+ *    stated otherwise.
+ *  - Return value: TPC_OK (0) or a negative TPC_ERR_* code; tpc_last_error()
+ *    gives a message.  No exception crosses the ABI.
+ *  - Units: cm, Tesla, GeV/c.  Clusters are in each sector's local frame:
+ *    x = pad-row radius, y transverse, z along the drift (mirrored on the
+ *    C side so that z >= 0 in every sector).
+ */
+#ifndef TPC_CA_H
+#define TPC_CA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TPC_OK = 0,
+    TPC_ERR_ARG = -1,      /* invalid argument (null pointer, size, geometry, parameter) */
+    TPC_ERR_CAPACITY = -2, /* outputs too small: counts hold the required sizes */
+    TPC_ERR_HIP = -3,      /* a HIP runtime call failed; see tpc_last_error */
+    TPC_ERR_STATE = -4     /* call not valid in the context's current state */
+};
+
+typedef struct tpc_ctx tpc_ctx_t;
+
+/* Clusters, structure of arrays, cluster id = index.  (device) */
+typedef struct {
+    int64_t n;              /* number of clusters, 0 <= n < 2^31 */
+    const float* y;         /* [n] local y (cm) */
+    const float* z;         /* [n] local z (cm); time frames: z + v_drift * t0 */
+    const uint8_t* row;     /* [n] pad row; clusters with row >= n_rows are ignored */
+    const uint8_t* sector;  /* [n] sector; clusters with sector >= n_sectors are ignored */
+} tpc_clusters_t;
+
+/* Detector geometry.  (host) */
+typedef struct {
+    int32_t n_rows;         /* 3 .. 255 */
+    const float* row_x;     /* [n_rows] pad-row radii, strictly increasing (host) */
+    float tan_half;         /* tan of the sector half-opening angle (10 deg) */
+    int32_t n_sectors;      /* 1 .. 256 */
+    float z_min, z_max;     /* z range covered by the grid */
+} tpc_geometry_t;
+
+/* Method parameters.  Every cut is a value the caller chooses; tpc_params_default
+ * fills the settings the library is validated with. */
+typedef struct {
+    double win_y, win_z;        /* neighbour window: |dy| <= win_y * row pitch, same for z */
+    double nb_chi2_max;         /* straight-line triplet criterion cut */
+    double fol_chi2_max;        /* chi2 cut for link acceptance and following */
+    double sigma_y, sigma_z;    /* cluster errors (cm) */
+    double s_max;               /* propagation fails when |sin phi| >= s_max */
+    double edge_margin;         /* stop when |y| > x * tan_half + edge_margin */
+    int32_t l_min_chain;        /* minimum linked hits of a start chain */
+    int32_t n_miss_max;         /* stop after more consecutive rows without a hit */
+    int32_t n_min_tracklet;     /* minimum hits of a valid tracklet */
+    int32_t n_min_track;        /* minimum owned hits of a track */
+    double c0_sinphi, c0_dzds, c0_qpt; /* initial variances of sin phi, dz/ds, q/pT */
+    float bin_y, bin_z;         /* grid bin size (cm), > 0; never changes results */
+    const float* mlp;           /* (device) 5057 FP32 scorer parameters, or NULL = plain finder */
+    double mlp_tau_logit;       /* keep a candidate pair iff its scorer logit >= this */
+} tpc_params_t;
+
+/* Counters written by the tracking calls.  (device, int32 each) */
+enum {
+    TPC_CNT_TRACKS = 0,       /* tracks found (may exceed cap_tracks) */
+    TPC_CNT_TRACK_HITS,       /* hits of all tracks (may exceed cap_hits) */
+    TPC_CNT_TRACKLETS,        /* start hits = tracklets built */
+    TPC_CNT_VALID_TRACKLETS,
+    TPC_CNT_FIT_FAILURES,
+    TPC_CNT_LINKS_RAW,        /* hits with a neighbour pair */
+    TPC_CNT_LINKS_CLEAN,      /* reciprocal upward links */
+    TPC_CNT_VALID_CLUSTERS,
+    TPC_CNT_PAIRS,            /* candidate (down, up) pairs examined */
+    TPC_CNT_PAIRS_KEPT,       /* pairs passing the scorer (== PAIRS without a scorer) */
+    TPC_N_COUNTS = 16
+};
+
+/* Track output, CSR.  All pointers (device), caller-owned. Track k (k < min(n_tracks,
+ * cap_tracks)) has hits hit_ids[hit_offset[k] .. hit_offset[k] + n_hits[k]) in
+ * ascending row order.  Tracks appear in ascending start cluster id.  A track
+ * whose hits do not fit in cap_hits is not written. */
+typedef struct {
+    int32_t cap_tracks, cap_hits;
+    int32_t* counts;        /* [TPC_N_COUNTS] */
+    int32_t* hit_offset;    /* [cap_tracks] */
+    int32_t* n_hits;        /* [cap_tracks] */
+    int32_t* hit_ids;       /* [cap_hits] cluster ids */
+    int32_t* start_id;      /* [cap_tracks] cluster id of the tracklet's start hit */
+    int32_t* sector;        /* [cap_tracks] */
+    int32_t* row_ref;       /* [cap_tracks] row of the innermost hit */
+    float* x_ref;           /* [cap_tracks] x of the innermost hit */
+    float* state;           /* [cap_tracks * 5] y, z, sin phi, dz/ds, q/pT at x_ref */
+    float* cov;             /* [cap_tracks * 15] lower triangle, row-major */
+    float* chi2;            /* [cap_tracks] */
+    int32_t* ndf;           /* [cap_tracks] */
+} tpc_tracks_t;
+
+/* Create a context on HIP device `device`.  *ctx receives the handle. */
+int tpc_ctx_create(tpc_ctx_t** ctx, int device);
+/* Release a context and its scratch memory (waits for its outstanding work). */
+void tpc_ctx_destroy(tpc_ctx_t* ctx);
+/* Message of the last error on this context (never NULL; "" after success). */
+const char* tpc_last_error(tpc_ctx_t* ctx);
+/* The validated default parameters (mlp = NULL). */
+void tpc_params_default(tpc_params_t* p);
+
+/* Track all sectors of one event (or any cluster set) with one launch per step.
+ * Sec. 3 (TPC GPU tracking).  Enqueues the whole chain on `stream`.  When
+ * `sync_check` is nonzero the call waits for the stream and returns
+ * TPC_ERR_CAPACITY if the outputs were too small (counts hold the sizes). */
+int tpc_track_sectors(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom,
+                      double bz_tesla, const tpc_params_t* params, tpc_tracks_t* out, void* stream,
+                      int sync_check);
+
+/* Track a whole continuous-readout time frame (Sec. 1) in one graph launch:
+ * persistent work-queue kernels, captured as a HIP graph per input shape, with
+ * the grid bin size and queue granularity chosen by the autotuner on the first
+ * call for a shape (that call synchronises).  Results are identical to
+ * tpc_track_sectors on the same clusters and parameters.  params->bin_y/bin_z
+ * are ignored (the tuned values are used). */
+int tpc_track_timeframe(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom,
+                        double bz_tesla, const tpc_params_t* params, tpc_tracks_t* out, void* stream,
+                        int sync_check);
+
+/* The tile choice the time-frame path uses for the last shape it tuned (host). */
+typedef struct {
+    float bin_y, bin_z;
+    int32_t tracklet_chunk;  /* tracklets taken per queue pop (per wave) */
+    int32_t blocks_per_cu;   /* persistent grid size / number of CUs */
+    float best_ms;           /* autotune measurement of the chosen candidate */
+    int32_t n_candidates;
+} tpc_tuning_t;
+int tpc_timeframe_tuning(tpc_ctx_t* ctx, tpc_tuning_t* out);
+/* Force the time-frame tiles (disables tuning) or, with NULL, re-enable tuning. */
+int tpc_timeframe_set_tuning(tpc_ctx_t* ctx, const tpc_tuning_t* tiles);
+
+/* Internal arrays of the last tracking call, for stage-by-stage checks.
+ * Positions refer to the grid's sorted order (see TPC_STAGE_HITS). */
+enum {
+    TPC_STAGE_HITS = 0,      /* [n_valid] {float y, float z, uint32 id, uint32 sector*n_rows+row} */
+    TPC_STAGE_ROW_OFF,       /* [n_sectors*n_rows+1] uint32 first sorted position of each row */
+    TPC_STAGE_BIN_BASE,      /* [n_sectors*n_rows+1] uint32 first bin of each row */
+    TPC_STAGE_BIN_OFF,       /* [n_bins+1] uint32 first sorted position of each bin */
+    TPC_STAGE_UP,            /* [n_valid] int32 raw upward link (sorted position, -1) */
+    TPC_STAGE_DN,            /* [n_valid] int32 raw downward link */
+    TPC_STAGE_UP_CLEAN,      /* [n_valid] int32 */
+    TPC_STAGE_DN_CLEAN,      /* [n_valid] int32 */
+    TPC_STAGE_STARTS,        /* [n_starts] uint32 sorted position of each start hit */
+    TPC_STAGE_TL_NHITS,      /* [n_starts] int32 */
+    TPC_STAGE_TL_HITS,       /* [n_starts * n_rows] int32: hits at the slot's end, ascending rows */
+    TPC_STAGE_TL_STATE,      /* [n_starts * 5] float */
+    TPC_STAGE_TL_COV,        /* [n_starts * 15] float */
+    TPC_STAGE_TL_FLAGS,      /* [n_starts] uint32: bit0 valid, bit1 fit failure */
+    TPC_STAGE_HIT_KEY,       /* [n_valid] uint64 */
+    TPC_STAGE_PAIR_LOGIT,    /* [n_pairs] float scorer logits of the last scored pairs */
+    TPC_N_STAGES
+};
+/* Size in bytes of a stage array of the last call (host out). */
+int tpc_stage_size(tpc_ctx_t* ctx, int stage, size_t* bytes);
+/* Copy a stage array into `dst` (host or device), at most `cap_bytes`.  Synchronous. */
+int tpc_stage_copy(tpc_ctx_t* ctx, int stage, void* dst, size_t cap_bytes);
+
+/* ---- learned triplet scorer: MLP 12-64-64-1, BF16 weights, FP32 accumulation ----
+ * Parameter vector (device, FP32 master values, 5057 floats): W1[12][64], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  Computation uses the weights rounded to BF16
+ * (nearest, ties to even) and the biases in FP32. */
+#define TPC_MLP_N_PARAMS 5057
+#define TPC_MLP_N_FEATURES 12
+
+/* Logits of n feature rows feats[n][12] (device) into logits[n] (device).
+ * BF16 MFMA with the activations carried as three BF16 terms (FP32-exact). */
+int tpc_mlp_infer(tpc_ctx_t* ctx, const float* feats, int64_t n, const float* mlp, float* logits, void* stream);
+
+/* Enumerate every window candidate triplet (down, middle, up) of the clusters,
+ * with its 12 scorer features.  triplets[cap][3] (device, cluster ids d, m, u),
+ * feats[cap][12] (device).  *n_out (host) receives the number of triplets; when it
+ * exceeds cap only the first cap are written, in no particular order.  Synchronous. */
+int tpc_triplets(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom,
+                 const tpc_params_t* params, int32_t* triplets, float* feats, int64_t cap, int64_t* n_out,
+                 void* stream);
+
+/* Mean binary cross-entropy loss and its gradient for one batch (rows idx[0..n_batch)
+ * of feats/labels; device).  grad[5057] and loss[1] (device).  Forward and backward
+ * run on BF16 MFMA with FP32 accumulation. */
+int tpc_mlp_grad(tpc_ctx_t* ctx, const float* feats, const uint8_t* labels, const int32_t* idx,
+                 int32_t n_batch, const float* mlp, float* grad, float* loss, void* stream);
+
+typedef struct {
+    int32_t batch;          /* rows per step, 1 .. 65536 */
+    int32_t n_steps;        /* steps to run; order holds n_steps * batch row indices */
+    int32_t step0;          /* Adam steps already taken (bias correction continues) */
+    float lr, beta1, beta2, eps;
+} tpc_train_cfg_t;
+
+/* Adam training (Kingma & Ba) of the scorer: for each step s, the batch
+ * order[s*batch .. (s+1)*batch), gradient as tpc_mlp_grad, Adam update of the FP32
+ * master parameters `mlp` (in/out) with moments m, v (in/out, device [5057]).
+ * loss[n_steps] (device) receives each step's loss. */
+int tpc_mlp_train(tpc_ctx_t* ctx, const float* feats, const uint8_t* labels, const int32_t* order,
+                  const tpc_train_cfg_t* cfg, float* mlp, float* m, float* v, float* loss, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPC_CA_H */

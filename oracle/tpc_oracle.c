@@ -648,6 +648,7 @@ int or_track(const or_input_t* in, const or_params_t* P, int stages, or_output_t
     memset(o, 0, sizeof *o);
     if (in->n_rows < 3 || in->n_rows > 255 || in->n_sectors < 1 || in->n_sectors > 256 || in->n < 0) return -1;
     if (!(P->bin_y > 0) || !(P->bin_z > 0) || !(in->z_max > in->z_min)) return -1;
+    if (P->l_min_chain < 2) return -1; /* a start needs a first link to seed its direction */
     ctx_t g;
     memset(&g, 0, sizeof g);
     g.in = in; g.prm = P; g.out = o;

@@ -1,0 +1,418 @@
+// C-ABI entry points: validation, scratch management, geometry tables and the
+// enqueue order of the track-finding chain.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tpc_internal.h"
+
+namespace tpc {
+
+int fail(tpc_ctx_t* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+void* buf(tpc_ctx_t* c, const char* name, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    DevBuf& b = c->bufs[name];
+    if (b.bytes >= bytes) return b.p;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    // grow with headroom so that slightly larger inputs do not reallocate
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.p = nullptr;
+        c->err = std::string("hipMalloc failed for scratch buffer ") + name + " (" + std::to_string(want) + " bytes)";
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.p;
+}
+
+void* buf_peek(tpc_ctx_t* c, const char* name, size_t* bytes) {
+    auto it = c->bufs.find(name);
+    if (it == c->bufs.end()) {
+        if (bytes) *bytes = 0;
+        return nullptr;
+    }
+    if (bytes) *bytes = it->second.bytes;
+    return it->second.p;
+}
+
+}  // namespace tpc
+
+using namespace tpc;
+
+namespace {
+
+struct Prepared {
+    GridDesc g{};
+    KParams kp{};
+    int64_t n = 0;
+    int64_t t_max = 0;
+    uint32_t n_bins = 0;
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_params(tpc_ctx_t* c, const tpc_params_t* p) {
+    if (!p) return fail(c, TPC_ERR_ARG, "params is NULL");
+    if (!finite_pos(p->win_y) || !finite_pos(p->win_z)) return fail(c, TPC_ERR_ARG, "window slopes must be > 0");
+    if (!finite_pos(p->nb_chi2_max) || !finite_pos(p->fol_chi2_max)) return fail(c, TPC_ERR_ARG, "cuts must be > 0");
+    if (!finite_pos(p->sigma_y) || !finite_pos(p->sigma_z)) return fail(c, TPC_ERR_ARG, "cluster errors must be > 0");
+    if (!(p->s_max > 0.0 && p->s_max < 1.0)) return fail(c, TPC_ERR_ARG, "s_max must be in (0, 1)");
+    if (!std::isfinite(p->edge_margin)) return fail(c, TPC_ERR_ARG, "edge_margin must be finite");
+    if (p->l_min_chain < 2 || p->l_min_chain > 255) return fail(c, TPC_ERR_ARG, "l_min_chain must be in [2, 255]");
+    if (p->n_miss_max < 0 || p->n_min_tracklet < 1 || p->n_min_track < 1)
+        return fail(c, TPC_ERR_ARG, "n_miss_max >= 0, n_min_tracklet >= 1, n_min_track >= 1 required");
+    if (!finite_pos(p->c0_sinphi) || !finite_pos(p->c0_dzds) || !finite_pos(p->c0_qpt))
+        return fail(c, TPC_ERR_ARG, "initial variances must be > 0");
+    if (!(p->bin_y > 0.f) || !(p->bin_z > 0.f) || !std::isfinite(p->bin_y) || !std::isfinite(p->bin_z))
+        return fail(c, TPC_ERR_ARG, "bin sizes must be > 0");
+    if (p->mlp && !std::isfinite(p->mlp_tau_logit)) return fail(c, TPC_ERR_ARG, "mlp_tau_logit must be finite");
+    return TPC_OK;
+}
+
+int check_geometry(tpc_ctx_t* c, const tpc_geometry_t* g) {
+    if (!g || !g->row_x) return fail(c, TPC_ERR_ARG, "geometry or row_x is NULL");
+    if (g->n_rows < 3 || g->n_rows > kMaxRows) return fail(c, TPC_ERR_ARG, "n_rows must be in [3, 255]");
+    if (g->n_sectors < 1 || g->n_sectors > 256) return fail(c, TPC_ERR_ARG, "n_sectors must be in [1, 256]");
+    for (int r = 0; r < g->n_rows; ++r) {
+        if (!std::isfinite(g->row_x[r]) || !(g->row_x[r] > 0.f)) return fail(c, TPC_ERR_ARG, "row_x must be finite and > 0");
+        if (r && !(g->row_x[r] > g->row_x[r - 1])) return fail(c, TPC_ERR_ARG, "row_x must increase strictly");
+    }
+    if (!std::isfinite(g->tan_half) || !(g->tan_half > 0.f)) return fail(c, TPC_ERR_ARG, "tan_half must be > 0");
+    if (!std::isfinite(g->z_min) || !std::isfinite(g->z_max) || !(g->z_max > g->z_min))
+        return fail(c, TPC_ERR_ARG, "z range must be finite with z_max > z_min");
+    return TPC_OK;
+}
+
+int check_clusters(tpc_ctx_t* c, const tpc_clusters_t* cl) {
+    if (!cl) return fail(c, TPC_ERR_ARG, "clusters is NULL");
+    if (cl->n < 0 || cl->n >= (int64_t(1) << 31)) return fail(c, TPC_ERR_ARG, "cluster count must be in [0, 2^31)");
+    if (cl->n > 0 && (!cl->y || !cl->z || !cl->row || !cl->sector)) return fail(c, TPC_ERR_ARG, "cluster arrays are NULL");
+    return TPC_OK;
+}
+
+int check_out(tpc_ctx_t* c, const tpc_tracks_t* o) {
+    if (!o || !o->counts) return fail(c, TPC_ERR_ARG, "output or counts is NULL");
+    if (o->cap_tracks < 0 || o->cap_hits < 0) return fail(c, TPC_ERR_ARG, "capacities must be >= 0");
+    if (o->cap_tracks > 0 && (!o->hit_offset || !o->n_hits || !o->start_id || !o->sector || !o->row_ref || !o->x_ref ||
+                              !o->state || !o->cov || !o->chi2 || !o->ndf))
+        return fail(c, TPC_ERR_ARG, "track output arrays are NULL");
+    if (o->cap_hits > 0 && !o->hit_ids) return fail(c, TPC_ERR_ARG, "hit_ids is NULL");
+    return TPC_OK;
+}
+
+// Geometry tables on the device (cached while geometry and bin sizes do not change).
+int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
+            float bin_y, float bin_z, Prepared* pr) {
+    const int R = geo->n_rows, S = geo->n_sectors;
+    std::vector<float> ymin(R);
+    std::vector<int32_t> ny(R);
+    for (int r = 0; r < R; ++r) {
+        const float hw = geo->row_x[r] * geo->tan_half;  // fp32 product
+        ymin[r] = -hw;
+        double v = std::ceil((2.0 * (double)hw) / (double)bin_y);
+        ny[r] = v < 1 ? 1 : (v > 65535 ? 65535 : (int32_t)v);
+    }
+    double vz = std::ceil(((double)geo->z_max - (double)geo->z_min) / (double)bin_z);
+    const int32_t nz = vz < 1 ? 1 : (vz > 1048576 ? 1048576 : (int32_t)vz);
+    std::vector<uint32_t> base(S * R + 1);
+    uint64_t nb = 0;
+    for (int s = 0; s < S; ++s)
+        for (int r = 0; r < R; ++r) {
+            base[s * R + r] = (uint32_t)nb;
+            nb += (uint64_t)ny[r] * (uint64_t)nz;
+        }
+    if (nb >= (uint64_t(1) << 31)) return fail(c, TPC_ERR_ARG, "grid too fine: more than 2^31 bins (raise bin_y/bin_z)");
+    base[S * R] = (uint32_t)nb;
+    // upload (small, synchronous)
+    float* d_rowx = (float*)buf(c, "row_x", sizeof(float) * R);
+    float* d_ymin = (float*)buf(c, "row_ymin", sizeof(float) * R);
+    int32_t* d_ny = (int32_t*)buf(c, "row_ny", sizeof(int32_t) * R);
+    uint32_t* d_base = (uint32_t*)buf(c, "bin_base", sizeof(uint32_t) * (S * R + 1));
+    if (!d_rowx || !d_ymin || !d_ny || !d_base) return TPC_ERR_HIP;
+    TPC_HIP(c, hipMemcpy(d_rowx, geo->row_x, sizeof(float) * R, hipMemcpyHostToDevice));
+    TPC_HIP(c, hipMemcpy(d_ymin, ymin.data(), sizeof(float) * R, hipMemcpyHostToDevice));
+    TPC_HIP(c, hipMemcpy(d_ny, ny.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
+    TPC_HIP(c, hipMemcpy(d_base, base.data(), sizeof(uint32_t) * (S * R + 1), hipMemcpyHostToDevice));
+    GridDesc& g = pr->g;
+    g.R = R;
+    g.S = S;
+    g.nz = nz;
+    g.z_min = geo->z_min;
+    g.inv_by = 1.0f / bin_y;
+    g.inv_bz = 1.0f / bin_z;
+    g.n_bins = (uint32_t)nb;
+    g.row_x = d_rowx;
+    g.row_ymin = d_ymin;
+    g.row_ny = d_ny;
+    g.bin_base = d_base;
+    KParams& k = pr->kp;
+    k.win_y = p->win_y;
+    k.win_z = p->win_z;
+    k.nb_cut = p->nb_chi2_max;
+    k.fol_cut = p->fol_chi2_max;
+    k.vy = p->sigma_y * p->sigma_y;
+    k.vz = p->sigma_z * p->sigma_z;
+    k.vy15 = 1.5 * p->sigma_y * p->sigma_y;
+    k.vz15 = 1.5 * p->sigma_z * p->sigma_z;
+    k.s_max = p->s_max;
+    k.edge = p->edge_margin;
+    k.tan_half = (double)geo->tan_half;
+    k.kq = -0.00299792458 * bz;
+    k.c0s = p->c0_sinphi;
+    k.c0t = p->c0_dzds;
+    k.c0q = p->c0_qpt;
+    k.l_min = p->l_min_chain;
+    k.n_miss = p->n_miss_max;
+    k.n_min_tl = p->n_min_tracklet;
+    k.n_min_trk = p->n_min_track;
+    k.tau = p->mlp_tau_logit;
+    pr->n = cl->n;
+    pr->n_bins = (uint32_t)nb;
+    pr->t_max = cl->n / p->l_min_chain + 1;
+    return TPC_OK;
+}
+
+struct Scratch {
+    uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *bin_fill, *bin_off, *row_off, *block_cnt, *starts;
+    uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
+    Hit* hits;
+    int32_t *up, *dn, *upc, *dnc;
+    uint8_t* start_flag;
+    uint64_t* hit_key;
+    void* scan;
+    TrackletOut tl;
+};
+
+int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
+    const int64_t n = pr.n > 0 ? pr.n : 1, T = pr.t_max, NB = pr.n_bins, R = pr.g.R, S = pr.g.S;
+    const int64_t nblk = (n + kBlock - 1) / kBlock + 1;
+    int64_t scan_n = n;
+    if (NB > scan_n) scan_n = NB;
+    if (T > scan_n) scan_n = T;
+    if (nblk > scan_n) scan_n = nblk;
+#define B(field, name, bytes)                                   \
+    s->field = (decltype(s->field))buf(c, name, (size_t)(bytes)); \
+    if (!s->field) return TPC_ERR_HIP;
+    B(counters, "counters", sizeof(uint32_t) * C_N_COUNTERS);
+    B(bin_of, "bin_of", 4 * n);
+    B(pos_of, "pos_of", 4 * n);
+    B(sorted_id, "sorted_id", 4 * n);
+    B(hits, "hits", sizeof(Hit) * n);
+    B(up, "up", 4 * n);
+    B(dn, "dn", 4 * n);
+    B(upc, "upc", 4 * n);
+    B(dnc, "dnc", 4 * n);
+    B(start_flag, "start_flag", 4 * ((n + 3) / 4));
+    B(hit_key, "hit_key", 8 * n);
+    B(bin_cnt, "bin_cnt", 4 * (NB + 1));
+    B(bin_fill, "bin_fill", 4 * (NB + 1));
+    B(bin_off, "bin_off", 4 * (NB + 1));
+    B(row_off, "row_off", 4 * (S * R + 1));
+    B(block_cnt, "block_cnt", 4 * nblk);
+    B(starts, "starts", 4 * T);
+    B(own_cnt, "own_cnt", 4 * T);
+    B(trk_flag, "trk_flag", 4 * T);
+    B(hit_off, "hit_off", 4 * T);
+    B(trk_idx, "trk_idx", 4 * T);
+    B(scan, "scan", scan_scratch_bytes(scan_n));
+    B(tl.nhits, "tl_nhits", 4 * T);
+    B(tl.hits, "tl_hits", 4 * T * R);
+    B(tl.state, "tl_state", 4 * 5 * T);
+    B(tl.cov, "tl_cov", 4 * 15 * T);
+    B(tl.chi2, "tl_chi2", 4 * T);
+    B(tl.ndf, "tl_ndf", 4 * T);
+    B(tl.row_ref, "tl_row_ref", 4 * T);
+    B(tl.flags, "tl_flags", 4 * T);
+#undef B
+    return TPC_OK;
+}
+
+// The whole chain on one stream.  No host synchronisation inside: every count
+// that sizes later work stays in device memory.
+void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
+                   const tpc_tracks_t& out, int tl_blocks, int chunk, hipStream_t st) {
+    const int64_t n = pr.n, T = pr.t_max, NB = pr.n_bins;
+    const GridDesc& g = pr.g;
+    fill_u32(s.counters, 0u, C_N_COUNTERS, st);
+    fill_u32(s.bin_cnt, 0u, NB, st);
+    fill_u32(s.bin_fill, 0u, NB, st);
+    fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
+    // a1 grid
+    grid_count(cl, g, s.bin_of, s.bin_cnt, s.pos_of, st);
+    scan_u32(s.bin_cnt, s.bin_off, NB, nullptr, s.bin_off + NB, s.scan, st);
+    grid_scatter(cl, s.bin_of, s.bin_off, s.bin_fill, s.sorted_id, st);
+    grid_finalize(cl, g, s.bin_off, s.sorted_id, s.hits, s.pos_of, s.row_off, s.counters, st);
+    // a2 neighbours, a4/a5 cleaning and starts
+    find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
+    clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
+    compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
+    // a6 tracklets
+    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.counters, s.tl, tl_blocks, chunk, st);
+    // a7 selection
+    fill_u64(s.hit_key, 0ull, n, st);
+    select_keys(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, T, st);
+    select_own(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag, T, st);
+    scan_u32(s.own_cnt, s.hit_off, T, s.counters + C_N_STARTS, s.counters + C_N_TRACK_HITS, s.scan, st);
+    scan_u32(s.trk_flag, s.trk_idx, T, s.counters + C_N_STARTS, s.counters + C_N_TRACKS, s.scan, st);
+    select_write(s.hits, s.starts, s.tl, g, s.counters, s.hit_key, s.own_cnt, s.trk_flag, s.hit_off, s.trk_idx, out,
+                 T, st);
+    finish_counts(s.counters, out.counts, st);
+    (void)c;
+}
+
+int capacity_check(tpc_ctx_t* c, const tpc_tracks_t* out, hipStream_t st) {
+    TPC_HIP(c, hipStreamSynchronize(st));
+    int32_t cnt[TPC_N_COUNTS];
+    TPC_HIP(c, hipMemcpy(cnt, out->counts, sizeof cnt, hipMemcpyDeviceToHost));
+    if (cnt[TPC_CNT_TRACKS] > out->cap_tracks || cnt[TPC_CNT_TRACK_HITS] > out->cap_hits)
+        return fail(c, TPC_ERR_CAPACITY,
+                    "outputs too small: need " + std::to_string(cnt[TPC_CNT_TRACKS]) + " tracks and " +
+                        std::to_string(cnt[TPC_CNT_TRACK_HITS]) + " hits");
+    return TPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpc_params_default(tpc_params_t* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->win_y = 2.0;
+    p->win_z = 2.0;
+    p->nb_chi2_max = 13.8;
+    p->fol_chi2_max = 13.8;
+    p->sigma_y = 0.06;
+    p->sigma_z = 0.1;
+    p->s_max = 0.999;
+    p->edge_margin = 2.0;
+    p->l_min_chain = 3;
+    p->n_miss_max = 10;
+    p->n_min_tracklet = 10;
+    p->n_min_track = 10;
+    p->c0_sinphi = 1.0;
+    p->c0_dzds = 1.0;
+    p->c0_qpt = 100.0;
+    p->bin_y = 8.0f;
+    p->bin_z = 8.0f;
+    p->mlp = nullptr;
+    p->mlp_tau_logit = 0.0;
+}
+
+int tpc_ctx_create(tpc_ctx_t** out, int device) {
+    if (!out) return TPC_ERR_ARG;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return TPC_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return TPC_ERR_HIP;
+    tpc_ctx_t* c = new tpc_ctx_t();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return TPC_OK;
+}
+
+void tpc_ctx_destroy(tpc_ctx_t* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    for (auto& kv : c->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+const char* tpc_last_error(tpc_ctx_t* c) { return c ? c->err.c_str() : "null context"; }
+
+int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz,
+                      const tpc_params_t* p, tpc_tracks_t* out, void* stream, int sync_check) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p)) ||
+        (rc = check_out(c, out)))
+        return rc;
+    if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
+    if (p->mlp) return fail(c, TPC_ERR_ARG, "learned pruning is not available in this build");
+    TPC_HIP(c, hipSetDevice(c->device));
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
+    Scratch s;
+    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_chain(c, *cl, pr, s, *out, c->n_cu * 8, 1, st);
+    TPC_HIP(c, hipGetLastError());
+    c->last_n = pr.n;
+    c->last_R = pr.g.R;
+    c->last_S = pr.g.S;
+    c->last_n_bins = pr.n_bins;
+    c->last_n_starts_cap = pr.t_max;
+    if (sync_check) return capacity_check(c, out, st);
+    return TPC_OK;
+}
+
+int tpc_stage_size(tpc_ctx_t* c, int stage, size_t* bytes) {
+    if (!c || !bytes || stage < 0 || stage >= TPC_N_STAGES) return TPC_ERR_ARG;
+    TPC_HIP(c, hipSetDevice(c->device));
+    size_t cb = 0;
+    uint32_t* counters = (uint32_t*)buf_peek(c, "counters", &cb);
+    if (!counters) return fail(c, TPC_ERR_STATE, "no tracking call yet");
+    uint32_t cnt[C_N_COUNTERS];
+    TPC_HIP(c, hipDeviceSynchronize());
+    TPC_HIP(c, hipMemcpy(cnt, counters, sizeof cnt, hipMemcpyDeviceToHost));
+    const size_t nv = cnt[C_N_VALID_CLU], ns = cnt[C_N_STARTS], R = c->last_R, S = c->last_S;
+    switch (stage) {
+        case TPC_STAGE_HITS: *bytes = nv * sizeof(Hit); break;
+        case TPC_STAGE_ROW_OFF:
+        case TPC_STAGE_BIN_BASE: *bytes = 4 * (S * R + 1); break;
+        case TPC_STAGE_BIN_OFF: *bytes = 4 * ((size_t)c->last_n_bins + 1); break;
+        case TPC_STAGE_UP:
+        case TPC_STAGE_DN:
+        case TPC_STAGE_UP_CLEAN:
+        case TPC_STAGE_DN_CLEAN: *bytes = 4 * nv; break;
+        case TPC_STAGE_STARTS:
+        case TPC_STAGE_TL_NHITS:
+        case TPC_STAGE_TL_FLAGS: *bytes = 4 * ns; break;
+        case TPC_STAGE_TL_HITS: *bytes = 4 * ns * R; break;
+        case TPC_STAGE_TL_STATE: *bytes = 4 * 5 * ns; break;
+        case TPC_STAGE_TL_COV: *bytes = 4 * 15 * ns; break;
+        case TPC_STAGE_HIT_KEY: *bytes = 8 * nv; break;
+        case TPC_STAGE_PAIR_LOGIT: *bytes = 4 * (size_t)c->last_n_pairs; break;
+        default: return TPC_ERR_ARG;
+    }
+    return TPC_OK;
+}
+
+int tpc_stage_copy(tpc_ctx_t* c, int stage, void* dst, size_t cap_bytes) {
+    size_t bytes = 0;
+    int rc = tpc_stage_size(c, stage, &bytes);
+    if (rc) return rc;
+    if (!dst && bytes) return fail(c, TPC_ERR_ARG, "dst is NULL");
+    if (bytes > cap_bytes) return fail(c, TPC_ERR_CAPACITY, "destination too small for stage " + std::to_string(stage));
+    static const char* names[TPC_N_STAGES] = {"hits",     "row_off",  "bin_base", "bin_off",   "up",
+                                              "dn",       "upc",      "dnc",      "starts",    "tl_nhits",
+                                              "tl_hits",  "tl_state", "tl_cov",   "tl_flags",  "hit_key",
+                                              "pair_logit"};
+    if (bytes == 0) return TPC_OK;
+    void* src = buf_peek(c, names[stage], nullptr);
+    if (!src) return fail(c, TPC_ERR_STATE, "stage not computed");
+    TPC_HIP(c, hipMemcpy(dst, src, bytes, hipMemcpyDefault));
+    return TPC_OK;
+}
+
+}  // extern "C"

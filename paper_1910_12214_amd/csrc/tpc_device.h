@@ -1,0 +1,61 @@
+// Device helpers shared by the HIP kernels.
+#pragma once
+
+#include "tpc_internal.h"
+
+namespace tpc {
+
+// Bins of row-sector (s, r) overlapping [y0,y1] x [z0,z1], widened by one bin on
+// every side (the FP32 bin index of a hit may round across a bin edge); the
+// caller's window tests are exact, so the widening only adds candidates.
+struct BinRange {
+    int iy0, iy1, iz0, iz1, ny;
+    uint32_t base;
+    bool empty;
+};
+
+__device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0, double y1, double z0, double z1) {
+    BinRange b;
+    b.ny = g.row_ny[r];
+    const double ymin = g.row_ymin[r], iby = g.inv_by, ibz = g.inv_bz, zmin = g.z_min;
+    const double fy0 = floor((y0 - ymin) * iby) - 1.0, fy1 = floor((y1 - ymin) * iby) + 1.0;
+    const double fz0 = floor((z0 - zmin) * ibz) - 1.0, fz1 = floor((z1 - zmin) * ibz) + 1.0;
+    b.empty = !(fy1 >= 0.0) || !(fz1 >= 0.0) || !(fy0 <= (double)(b.ny - 1)) || !(fz0 <= (double)(g.nz - 1));
+    b.iy0 = fy0 < 0.0 ? 0 : (int)fy0;
+    b.iy1 = fy1 > (double)(b.ny - 1) ? b.ny - 1 : (int)fy1;
+    b.iz0 = fz0 < 0.0 ? 0 : (int)fz0;
+    b.iz1 = fz1 > (double)(g.nz - 1) ? g.nz - 1 : (int)fz1;
+    b.base = g.bin_base[s * g.R + r];
+    return b;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Block-wide sums of two per-thread values, one atomic per block each.
+// Every thread of the block must call it.
+__device__ inline void block_add2(uint32_t a, uint32_t b, uint32_t* pa, uint32_t* pb) {
+    __shared__ uint32_t sa[kBlock / 64], sb[kBlock / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ta = 0, tb = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            ta += sa[k];
+            tb += sb[k];
+        }
+        if (pa && ta) atomicAdd(pa, ta);
+        if (pb && tb) atomicAdd(pb, tb);
+    }
+}
+
+}  // namespace tpc

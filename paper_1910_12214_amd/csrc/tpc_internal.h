@@ -1,0 +1,186 @@
+// Internal declarations of the HIP track finder (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tpc_ca.h"
+
+namespace tpc {
+
+constexpr int kMaxRows = 255;
+constexpr int kBlock = 256;
+
+// One grid hit, 16 bytes: a single coalescable load per candidate.
+struct alignas(16) Hit {
+    float y, z;
+    uint32_t id;  // cluster id
+    uint32_t rs;  // sector * n_rows + row
+};
+
+// Grid description handed to kernels by value.
+struct GridDesc {
+    int R, S, nz;
+    float z_min, inv_by, inv_bz;
+    uint32_t n_bins;
+    const float* row_x;      // [R]
+    const float* row_ymin;   // [R] fp32 -(x * tan_half)
+    const int32_t* row_ny;   // [R]
+    const uint32_t* bin_base;  // [S*R+1]
+};
+
+// Method parameters in the form kernels use them (FP64 decisions).
+struct KParams {
+    double win_y, win_z, nb_cut, fol_cut;
+    double vy, vz, vy15, vz15;
+    double s_max, edge, tan_half, kq;
+    double c0s, c0t, c0q;
+    int32_t l_min, n_miss, n_min_tl, n_min_trk;
+    double tau;  // scorer logit threshold
+};
+
+// Growable device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+enum Counter {  // device scratch counters (uint32)
+    C_N_STARTS = 0,
+    C_QUEUE_TL,
+    C_QUEUE_SEL,
+    C_N_PAIRS,
+    C_N_FAIL,
+    C_N_VALID_TL,
+    C_N_LINKS_RAW,
+    C_N_LINKS_CLEAN,
+    C_N_TRACKS,
+    C_N_TRACK_HITS,
+    C_N_PAIRS_KEPT,
+    C_N_VALID_CLU,
+    C_N_COUNTERS = 32
+};
+
+struct Tuning {
+    float bin_y = 8.f, bin_z = 8.f;
+    int chunk = 1;         // queue pops of 64 tracklets per wave
+    int blocks_per_cu = 8;
+    float best_ms = 0.f;
+    int n_candidates = 0;
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace tpc
+
+struct tpc_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    // scratch
+    std::map<std::string, tpc::DevBuf> bufs;
+    // shapes of the last tracking call (for stage export)
+    int64_t last_n = 0, last_nvalid_cap = 0, last_n_starts_cap = 0;
+    int last_R = 0, last_S = 0;
+    uint32_t last_n_bins = 0;
+    int64_t last_n_pairs = 0;
+    uint32_t* counters_host = nullptr;  // pinned mirror used for synchronous reads
+    // time-frame path
+    bool tune_forced = false;
+    bool tuned = false;
+    std::string tuned_key;
+    tpc::Tuning tuning;
+    std::map<std::string, tpc::GraphEntry> graphs;
+    hipStream_t own_stream = nullptr;
+};
+
+namespace tpc {
+
+int fail(tpc_ctx_t* c, int code, const std::string& msg);
+#define TPC_HIP(c, call)                                                                          \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::tpc::fail((c), TPC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// returns nullptr on allocation failure (error recorded)
+void* buf(tpc_ctx_t* c, const char* name, size_t bytes);
+void* buf_peek(tpc_ctx_t* c, const char* name, size_t* bytes);
+
+// ---------------------------------------------------------------- launchers
+// scan.hip
+size_t scan_scratch_bytes(int64_t n_max);
+// exclusive scan of n (device count if n_dev != nullptr, else n_max) uint32 values,
+// out may alias in; total written to *total_dev if non-null.
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* n_dev, uint32_t* total_dev,
+              void* scratch, hipStream_t s);
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+
+// grid.hip
+void grid_count(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* bin_of, uint32_t* bin_cnt, uint32_t* pos_of,
+                hipStream_t s);
+void grid_scatter(const tpc_clusters_t& cl, const uint32_t* bin_of, const uint32_t* bin_off, uint32_t* bin_fill,
+                  uint32_t* sorted_id, hipStream_t s);
+void grid_finalize(const tpc_clusters_t& cl, const GridDesc& g, const uint32_t* bin_off, uint32_t* sorted_id,
+                   Hit* hits, uint32_t* pos_of, uint32_t* row_off, uint32_t* counters, hipStream_t s);
+
+// links.hip
+void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
+                     const uint32_t* row_off, int64_t n_max, const uint32_t* counters, int32_t* up, int32_t* dn,
+                     const float* mlp_q, uint32_t* cnt, hipStream_t s);
+void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uint32_t* counters, const int32_t* up,
+                    const int32_t* dn, int32_t* upc, int32_t* dnc, uint8_t* start_flag, uint32_t* cnt,
+                    hipStream_t s);
+void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
+                    uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s);
+
+// tracklets.hip
+struct TrackletOut {
+    int32_t* nhits;
+    int32_t* hits;       // [T * R]
+    float* state;        // [T * 5]
+    float* cov;          // [T * 15]
+    float* chi2;
+    int32_t* ndf;
+    int32_t* row_ref;
+    uint32_t* flags;     // bit0 valid, bit1 fail
+};
+void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
+                     const int32_t* upc, const uint32_t* starts, uint32_t* counters, const TrackletOut& o,
+                     int grid_blocks, int chunk, hipStream_t s);
+
+// select.hip
+void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
+                 uint64_t* hit_key, int64_t t_max, hipStream_t s);
+void select_own(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, const uint32_t* counters,
+                const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt, uint32_t* trk_flag, int64_t t_max,
+                hipStream_t s);
+void select_write(const Hit* hits, const uint32_t* starts, const TrackletOut& o, const GridDesc& g,
+                  const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
+                  const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
+                  const tpc_tracks_t& out, int64_t t_max, hipStream_t s);
+void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s);
+
+// mlp.hip
+void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
+size_t mlp_q_floats();
+void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s);
+void triplet_enumerate(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
+                       int64_t n_max, const uint32_t* counters, int32_t* trip, float* feats, int64_t cap,
+                       uint32_t* n_trip, hipStream_t s);
+void mlp_grad(const float* q, const float* master, const float* feats, const uint8_t* labels,
+              const int32_t* idx, int n_batch, float* partial, float* grad, float* loss, hipStream_t s);
+size_t mlp_grad_partial_floats(int n_batch);
+void mlp_adam(float* master, float* m, float* v, const float* grad, int step, float lr, float b1, float b2,
+              float eps, float* q, hipStream_t s);
+
+}  // namespace tpc

@@ -1,0 +1,137 @@
+// Tracklet selection and track output.
+//
+// key(t) = (n_hits << 32) | (0xFFFFFFFF - start cluster id): longer tracklets win,
+// equal lengths go to the lower start id.  hitKey[c] = max over valid tracklets
+// containing c, by 64-bit atomicMax; the maximum does not depend on the order
+// in which lanes apply their atomics, so hit ownership is independent of
+// processing order.  A tracklet owns the hits whose key equals its own and
+// becomes a track with at least n_min_track owned hits.  Track and hit offsets
+// come from exclusive scans in start order, so the output is in ascending
+// start id.
+#include "tpc_device.h"
+#include "tpc_internal.h"
+
+namespace tpc {
+
+namespace {
+
+__device__ inline uint64_t tl_key(uint32_t nh, uint32_t start_id) {
+    return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - start_id);
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
+                                                 TrackletOut o, int R, const uint32_t* __restrict__ counters,
+                                                 uint64_t* __restrict__ hit_key) {
+    const uint32_t n = counters[C_N_STARTS];
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+        if (!(o.flags[k] & 1u)) continue;
+        const uint32_t nh = (uint32_t)o.nhits[k];
+        const uint64_t key = tl_key(nh, hits[starts[k]].id);
+        const int32_t* slot = o.hits + (size_t)k * R;
+        for (int j = R - (int)nh; j < R; ++j) atomicMax((unsigned long long*)&hit_key[slot[j]], (unsigned long long)key);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
+                                                TrackletOut o, int R, const uint32_t* __restrict__ counters,
+                                                const uint64_t* __restrict__ hit_key, int n_min_trk,
+                                                uint32_t* __restrict__ own_cnt, uint32_t* __restrict__ trk_flag) {
+    const uint32_t n = counters[C_N_STARTS];
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+        uint32_t owned = 0;
+        if (o.flags[k] & 1u) {
+            const uint32_t nh = (uint32_t)o.nhits[k];
+            const uint64_t key = tl_key(nh, hits[starts[k]].id);
+            const int32_t* slot = o.hits + (size_t)k * R;
+            for (int j = R - (int)nh; j < R; ++j) owned += hit_key[slot[j]] == key;
+            if ((int)owned < n_min_trk) owned = 0;
+        }
+        own_cnt[k] = owned;
+        trk_flag[k] = owned ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
+                                                  TrackletOut o, GridDesc g, const uint32_t* __restrict__ counters,
+                                                  const uint64_t* __restrict__ hit_key,
+                                                  const uint32_t* __restrict__ own_cnt,
+                                                  const uint32_t* __restrict__ hit_off,
+                                                  const uint32_t* __restrict__ trk_idx, tpc_tracks_t out) {
+    const uint32_t n = counters[C_N_STARTS];
+    const int R = g.R;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+        const uint32_t cnt = own_cnt[k];
+        if (!cnt) continue;
+        const uint32_t t = trk_idx[k], off = hit_off[k];
+        if (t >= (uint32_t)out.cap_tracks || (uint64_t)off + cnt > (uint64_t)out.cap_hits) continue;
+        const uint32_t nh = (uint32_t)o.nhits[k];
+        const Hit hs = hits[starts[k]];
+        const uint64_t key = tl_key(nh, hs.id);
+        const int32_t* slot = o.hits + (size_t)k * R;
+        uint32_t w = off;
+        for (int j = R - (int)nh; j < R; ++j) {
+            const int32_t pos = slot[j];
+            if (hit_key[pos] == key) out.hit_ids[w++] = (int32_t)hits[pos].id;
+        }
+        out.hit_offset[t] = (int32_t)off;
+        out.n_hits[t] = (int32_t)cnt;
+        out.start_id[t] = (int32_t)hs.id;
+        out.sector[t] = (int32_t)(hs.rs / (uint32_t)R);
+        const int rr = o.row_ref[k];
+        out.row_ref[t] = rr;
+        out.x_ref[t] = g.row_x[rr];
+        for (int i = 0; i < 5; ++i) out.state[(size_t)t * 5 + i] = o.state[(size_t)k * 5 + i];
+        for (int i = 0; i < 15; ++i) out.cov[(size_t)t * 15 + i] = o.cov[(size_t)k * 15 + i];
+        out.chi2[t] = o.chi2[k];
+        out.ndf[t] = o.ndf[k];
+    }
+}
+
+__global__ void k_finish(const uint32_t* __restrict__ c, int32_t* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    out[TPC_CNT_TRACKS] = (int32_t)c[C_N_TRACKS];
+    out[TPC_CNT_TRACK_HITS] = (int32_t)c[C_N_TRACK_HITS];
+    out[TPC_CNT_TRACKLETS] = (int32_t)c[C_N_STARTS];
+    out[TPC_CNT_VALID_TRACKLETS] = (int32_t)c[C_N_VALID_TL];
+    out[TPC_CNT_FIT_FAILURES] = (int32_t)c[C_N_FAIL];
+    out[TPC_CNT_LINKS_RAW] = (int32_t)c[C_N_LINKS_RAW];
+    out[TPC_CNT_LINKS_CLEAN] = (int32_t)c[C_N_LINKS_CLEAN];
+    out[TPC_CNT_VALID_CLUSTERS] = (int32_t)c[C_N_VALID_CLU];
+    out[TPC_CNT_PAIRS] = (int32_t)c[C_N_PAIRS];
+    out[TPC_CNT_PAIRS_KEPT] = (int32_t)c[C_N_PAIRS_KEPT];
+}
+
+inline unsigned sel_blocks(int64_t t_max) {
+    int64_t b = (t_max + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
+                 uint64_t* hit_key, int64_t t_max, hipStream_t s) {
+    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, R, counters, hit_key);
+}
+
+void select_own(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, const uint32_t* counters,
+                const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt, uint32_t* trk_flag, int64_t t_max,
+                hipStream_t s) {
+    k_own<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, R, counters, hit_key, n_min_trk, own_cnt, trk_flag);
+}
+
+void select_write(const Hit* hits, const uint32_t* starts, const TrackletOut& o, const GridDesc& g,
+                  const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
+                  const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
+                  const tpc_tracks_t& out, int64_t t_max, hipStream_t s) {
+    (void)trk_flag;
+    k_write<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, g, counters, hit_key, own_cnt, hit_off, trk_idx,
+                                                 out);
+}
+
+void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s) {
+    k_finish<<<1, 64, 0, s>>>(counters, out_counts);
+}
+
+}  // namespace tpc

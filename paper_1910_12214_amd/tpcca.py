@@ -1,0 +1,316 @@
+"""Python binding of ``libtpcca.so`` (argument marshalling only).
+
+PyTorch provides device memory and the HIP stream; every step of the track finding runs in
+the library's HIP kernels.  Importing this module on a machine without the built library
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpcca.so")
+
+TPC_OK, TPC_ERR_ARG, TPC_ERR_CAPACITY, TPC_ERR_HIP, TPC_ERR_STATE = 0, -1, -2, -3, -4
+(CNT_TRACKS, CNT_TRACK_HITS, CNT_TRACKLETS, CNT_VALID_TRACKLETS, CNT_FIT_FAILURES, CNT_LINKS_RAW,
+ CNT_LINKS_CLEAN, CNT_VALID_CLUSTERS, CNT_PAIRS, CNT_PAIRS_KEPT) = range(10)
+N_COUNTS = 16
+(STAGE_HITS, STAGE_ROW_OFF, STAGE_BIN_BASE, STAGE_BIN_OFF, STAGE_UP, STAGE_DN, STAGE_UP_CLEAN, STAGE_DN_CLEAN,
+ STAGE_STARTS, STAGE_TL_NHITS, STAGE_TL_HITS, STAGE_TL_STATE, STAGE_TL_COV, STAGE_TL_FLAGS, STAGE_HIT_KEY,
+ STAGE_PAIR_LOGIT) = range(16)
+MLP_N_PARAMS = 5057
+
+_vp = ctypes.c_void_p
+
+
+class Clusters(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("y", _vp), ("z", _vp), ("row", _vp), ("sector", _vp)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("row_x", ctypes.POINTER(ctypes.c_float)), ("tan_half", ctypes.c_float),
+                ("n_sectors", ctypes.c_int32), ("z_min", ctypes.c_float), ("z_max", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("win_y", ctypes.c_double), ("win_z", ctypes.c_double), ("nb_chi2_max", ctypes.c_double),
+                ("fol_chi2_max", ctypes.c_double), ("sigma_y", ctypes.c_double), ("sigma_z", ctypes.c_double),
+                ("s_max", ctypes.c_double), ("edge_margin", ctypes.c_double), ("l_min_chain", ctypes.c_int32),
+                ("n_miss_max", ctypes.c_int32), ("n_min_tracklet", ctypes.c_int32), ("n_min_track", ctypes.c_int32),
+                ("c0_sinphi", ctypes.c_double), ("c0_dzds", ctypes.c_double), ("c0_qpt", ctypes.c_double),
+                ("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("mlp", _vp), ("mlp_tau_logit", ctypes.c_double)]
+
+
+class Tracks(ctypes.Structure):
+    _fields_ = [("cap_tracks", ctypes.c_int32), ("cap_hits", ctypes.c_int32), ("counts", _vp), ("hit_offset", _vp),
+                ("n_hits", _vp), ("hit_ids", _vp), ("start_id", _vp), ("sector", _vp), ("row_ref", _vp),
+                ("x_ref", _vp), ("state", _vp), ("cov", _vp), ("chi2", _vp), ("ndf", _vp)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("tracklet_chunk", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("best_ms", ctypes.c_float), ("n_candidates", ctypes.c_int32)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("step0", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_default", "tpc_track_sectors",
+           "tpc_track_timeframe", "tpc_timeframe_tuning", "tpc_timeframe_set_tuning", "tpc_stage_size",
+           "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train")
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1910_12214_amd/build.py "
+                           "(the track finder has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.tpc_ctx_create.argtypes = [P(_vp), ctypes.c_int]
+    lib.tpc_ctx_create.restype = ctypes.c_int
+    lib.tpc_ctx_destroy.argtypes = [_vp]
+    lib.tpc_ctx_destroy.restype = None
+    lib.tpc_last_error.argtypes = [_vp]
+    lib.tpc_last_error.restype = ctypes.c_char_p
+    lib.tpc_params_default.argtypes = [P(Params)]
+    lib.tpc_params_default.restype = None
+    for f in ("tpc_track_sectors", "tpc_track_timeframe"):
+        getattr(lib, f).argtypes = [_vp, P(Clusters), P(Geometry), ctypes.c_double, P(Params), P(Tracks), _vp,
+                                    ctypes.c_int]
+        getattr(lib, f).restype = ctypes.c_int
+    lib.tpc_timeframe_tuning.argtypes = [_vp, P(Tuning)]
+    lib.tpc_timeframe_tuning.restype = ctypes.c_int
+    lib.tpc_timeframe_set_tuning.argtypes = [_vp, P(Tuning)]
+    lib.tpc_timeframe_set_tuning.restype = ctypes.c_int
+    lib.tpc_stage_size.argtypes = [_vp, ctypes.c_int, P(ctypes.c_size_t)]
+    lib.tpc_stage_size.restype = ctypes.c_int
+    lib.tpc_stage_copy.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_size_t]
+    lib.tpc_stage_copy.restype = ctypes.c_int
+    lib.tpc_mlp_infer.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.tpc_mlp_infer.restype = ctypes.c_int
+    lib.tpc_triplets.argtypes = [_vp, P(Clusters), P(Geometry), P(Params), _vp, _vp, ctypes.c_int64,
+                                 P(ctypes.c_int64), _vp]
+    lib.tpc_triplets.restype = ctypes.c_int
+    lib.tpc_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+    lib.tpc_mlp_grad.restype = ctypes.c_int
+    lib.tpc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, P(TrainCfg), _vp, _vp, _vp, _vp, _vp]
+    lib.tpc_mlp_train.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class TpcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tpc error {code}: {msg}")
+        self.code = code
+
+
+def default_params() -> dict:
+    p = Params()
+    load().tpc_params_default(ctypes.byref(p))
+    return {f: getattr(p, f) for f, _ in Params._fields_ if f not in ("mlp",)}
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_params(params: dict | None = None, mlp=None, tau_logit: float = 0.0) -> Params:
+    p = Params()
+    load().tpc_params_default(ctypes.byref(p))
+    for k, v in (params or {}).items():
+        if k in ("mlp", "tie_rel", "mlp_flag_abs"):
+            continue
+        if any(k == f for f, _ in Params._fields_):
+            setattr(p, k, v)
+    p.mlp = _ptr(mlp) if mlp is not None else None
+    p.mlp_tau_logit = float(tau_logit) if mlp is not None else float((params or {}).get("mlp_tau_logit", 0.0))
+    return p
+
+
+def make_geometry(geom: dict):
+    rx = np.ascontiguousarray(geom["row_x"], dtype=np.float32)
+    g = Geometry()
+    g.n_rows = int(geom["n_rows"])
+    g.row_x = rx.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    g.tan_half = float(geom["tan_half"])
+    g.n_sectors = int(geom["n_sectors"])
+    g.z_min = float(geom["z_min"])
+    g.z_max = float(geom["z_max"])
+    return g, rx  # keep rx alive
+
+
+class Context:
+    """A library context on one HIP device; owns the scratch memory."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = _vp()
+        rc = self.lib.tpc_ctx_create(ctypes.byref(h), device)
+        if rc != TPC_OK:
+            raise TpcError(rc, f"tpc_ctx_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != TPC_OK:
+            raise TpcError(rc, self.lib.tpc_last_error(self.h).decode())
+
+    # ------------------------------------------------------------------ tracking
+    def alloc_tracks(self, cap_tracks: int, cap_hits: int):
+        import torch
+
+        dev = torch.device("cuda", self.device)
+        i32 = dict(dtype=torch.int32, device=dev)
+        f32 = dict(dtype=torch.float32, device=dev)
+        ct = max(1, cap_tracks)
+        return dict(counts=torch.zeros(N_COUNTS, **i32), hit_offset=torch.empty(ct, **i32),
+                    n_hits=torch.empty(ct, **i32), hit_ids=torch.empty(max(1, cap_hits), **i32),
+                    start_id=torch.empty(ct, **i32), sector=torch.empty(ct, **i32), row_ref=torch.empty(ct, **i32),
+                    x_ref=torch.empty(ct, **f32), state=torch.empty(ct, 5, **f32), cov=torch.empty(ct, 15, **f32),
+                    chi2=torch.empty(ct, **f32), ndf=torch.empty(ct, **i32), cap_tracks=cap_tracks, cap_hits=cap_hits)
+
+    @staticmethod
+    def _tracks_struct(o: dict) -> Tracks:
+        t = Tracks()
+        t.cap_tracks = o["cap_tracks"]
+        t.cap_hits = o["cap_hits"]
+        for k in ("counts", "hit_offset", "n_hits", "hit_ids", "start_id", "sector", "row_ref", "x_ref", "state",
+                  "cov", "chi2", "ndf"):
+            setattr(t, k, _ptr(o[k]))
+        return t
+
+    @staticmethod
+    def _clusters(y, z, row, sector) -> Clusters:
+        c = Clusters()
+        c.n = int(y.shape[0])
+        c.y, c.z, c.row, c.sector = _ptr(y), _ptr(z), _ptr(row), _ptr(sector)
+        return c
+
+    def track(self, y, z, row, sector, geom: dict, bz: float, params: dict | None = None, mlp=None,
+              tau_logit: float = 0.0, out: dict | None = None, stream=None, sync_check: bool = True,
+              timeframe: bool = False) -> dict:
+        """Track clusters given as CUDA tensors (float32 y, z; uint8 row, sector)."""
+        n = int(y.shape[0])
+        if out is None:
+            out = self.alloc_tracks(max(16, n // 8), max(16, n))
+        cl = self._clusters(y, z, row, sector)
+        g, _keep = make_geometry(geom)
+        p = make_params(params, mlp, tau_logit)
+        t = self._tracks_struct(out)
+        fn = self.lib.tpc_track_timeframe if timeframe else self.lib.tpc_track_sectors
+        rc = fn(self.h, ctypes.byref(cl), ctypes.byref(g), float(bz), ctypes.byref(p), ctypes.byref(t),
+                _stream(stream), 1 if sync_check else 0)
+        self._check(rc)
+        return out
+
+    def stage(self, stage: int, dtype) -> np.ndarray:
+        nb = ctypes.c_size_t(0)
+        self._check(self.lib.tpc_stage_size(self.h, stage, ctypes.byref(nb)))
+        a = np.empty(nb.value // np.dtype(dtype).itemsize, dtype=dtype)
+        self._check(self.lib.tpc_stage_copy(self.h, stage, a.ctypes.data, nb.value))
+        return a
+
+    # --------------------------------------------------------------- time frames
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.tpc_timeframe_tuning(self.h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    def set_tuning(self, tiles: dict | None):
+        if tiles is None:
+            self._check(self.lib.tpc_timeframe_set_tuning(self.h, None))
+            return
+        t = Tuning()
+        for k, v in tiles.items():
+            setattr(t, k, v)
+        self._check(self.lib.tpc_timeframe_set_tuning(self.h, ctypes.byref(t)))
+
+    # ------------------------------------------------------------- learned scorer
+    def mlp_infer(self, feats, mlp, logits=None, stream=None):
+        import torch
+
+        n = int(feats.shape[0])
+        if logits is None:
+            logits = torch.empty(max(1, n), dtype=torch.float32, device=feats.device)
+        self._check(self.lib.tpc_mlp_infer(self.h, _ptr(feats), n, _ptr(mlp), _ptr(logits), _stream(stream)))
+        return logits[:n]
+
+    def triplets(self, y, z, row, sector, geom: dict, params: dict | None = None, cap: int | None = None,
+                 stream=None):
+        import torch
+
+        n = int(y.shape[0])
+        cap = cap or max(64, 4 * n)
+        dev = y.device
+        trip = torch.empty(cap, 3, dtype=torch.int32, device=dev)
+        feats = torch.empty(cap, 12, dtype=torch.float32, device=dev)
+        cl = self._clusters(y, z, row, sector)
+        g, _keep = make_geometry(geom)
+        p = make_params(params)
+        nout = ctypes.c_int64(0)
+        self._check(self.lib.tpc_triplets(self.h, ctypes.byref(cl), ctypes.byref(g), ctypes.byref(p), _ptr(trip),
+                                          _ptr(feats), cap, ctypes.byref(nout), _stream(stream)))
+        if nout.value > cap:
+            return self.triplets(y, z, row, sector, geom, params, cap=int(nout.value), stream=stream)
+        return trip[:nout.value], feats[:nout.value]
+
+    def mlp_grad(self, feats, labels, idx, mlp, stream=None):
+        import torch
+
+        grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        self._check(self.lib.tpc_mlp_grad(self.h, _ptr(feats), _ptr(labels), _ptr(idx), int(idx.shape[0]), _ptr(mlp),
+                                          _ptr(grad), _ptr(loss), _stream(stream)))
+        return grad, loss
+
+    def mlp_train(self, feats, labels, order, mlp, m, v, batch: int, n_steps: int, step0: int = 0,
+                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        import torch
+
+        loss = torch.empty(max(1, n_steps), dtype=torch.float32, device=feats.device)
+        cfg = TrainCfg(batch=batch, n_steps=n_steps, step0=step0, lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        self._check(self.lib.tpc_mlp_train(self.h, _ptr(feats), _ptr(labels), _ptr(order), ctypes.byref(cfg),
+                                           _ptr(mlp), _ptr(m), _ptr(v), _ptr(loss), _stream(stream)))
+        return loss
+
+
+def tracks_to_host(out: dict) -> dict:
+    """Counts and the filled part of a track output, as numpy arrays (synchronises)."""
+    counts = out["counts"].cpu().numpy()
+    nt = min(int(counts[CNT_TRACKS]), out["cap_tracks"])
+    nh = min(int(counts[CNT_TRACK_HITS]), out["cap_hits"])
+    res = {"counts": counts}
+    for k in ("hit_offset", "n_hits", "start_id", "sector", "row_ref", "x_ref", "state", "cov", "chi2", "ndf"):
+        res[k] = out[k][:nt].cpu().numpy()
+    res["hit_ids"] = out["hit_ids"][:nh].cpu().numpy()
+    return res

@@ -1,0 +1,212 @@
+"""Stage-by-stage comparison of the HIP path with the FP64 oracle.
+
+Rules (near-ties):
+* grid: identical order, bin offsets and row offsets (integer work, bit-exact);
+* links, cleaned links, start hits, tracklet hit sets, hit keys and track hit lists:
+  identical, except where an oracle-flagged near-tie could change them — a flagged neighbour
+  decision taints its hit, cleaning taints through the partners, a chain through a tainted
+  link taints its start and tracklet, a flagged tracklet taints its hits, and a track that
+  touches a tainted hit is excluded; every exclusion is counted and reported;
+* track parameters: |a - b| <= 1e-4 max(|b|, floor) with floors (1 cm, 1 cm, 1e-2, 1e-2, 1e-2);
+* efficiency, fake and clone rates: within 0.1% absolute.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from synth import metrics
+
+FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 1e-2])
+HIT_DTYPE = np.dtype([("y", "<f4"), ("z", "<f4"), ("id", "<u4"), ("rs", "<u4")])
+
+
+def gpu_stages(ctx, R):
+    from paper_1910_12214_amd import tpcca as T
+
+    st = {}
+    st["hits"] = ctx.stage(T.STAGE_HITS, np.uint8).view(HIT_DTYPE)
+    st["row_off"] = ctx.stage(T.STAGE_ROW_OFF, np.uint32)
+    st["bin_base"] = ctx.stage(T.STAGE_BIN_BASE, np.uint32)
+    st["bin_off"] = ctx.stage(T.STAGE_BIN_OFF, np.uint32)
+    for k, s in (("up", T.STAGE_UP), ("dn", T.STAGE_DN), ("up_c", T.STAGE_UP_CLEAN), ("dn_c", T.STAGE_DN_CLEAN)):
+        st[k] = ctx.stage(s, np.int32)
+    st["starts"] = ctx.stage(T.STAGE_STARTS, np.uint32)
+    st["tl_nhits"] = ctx.stage(T.STAGE_TL_NHITS, np.int32)
+    ns = st["tl_nhits"].size
+    st["tl_hits"] = ctx.stage(T.STAGE_TL_HITS, np.int32).reshape(ns, R)
+    st["tl_state"] = ctx.stage(T.STAGE_TL_STATE, np.float32).reshape(ns, 5)
+    st["tl_cov"] = ctx.stage(T.STAGE_TL_COV, np.float32).reshape(ns, 15)
+    st["tl_flags"] = ctx.stage(T.STAGE_TL_FLAGS, np.uint32)
+    st["hit_key"] = ctx.stage(T.STAGE_HIT_KEY, np.uint64)
+    return st
+
+
+def to_id_space(st, n):
+    """Convert sorted-position arrays to cluster-id space."""
+    ids = st["hits"]["id"].astype(np.int64)
+    out = {}
+    for k in ("up", "dn", "up_c", "dn_c"):
+        a = np.full(n, -1, dtype=np.int64)
+        v = st[k].astype(np.int64)
+        a[ids] = np.where(v >= 0, ids[np.maximum(v, 0)], -1)
+        out[k] = a
+    out["start_id"] = ids[st["starts"].astype(np.int64)]
+    key = np.zeros(n, dtype=np.uint64)
+    key[ids] = st["hit_key"]
+    out["hit_key"] = key
+    R = st["tl_hits"].shape[1]
+    tl = []
+    for k in range(st["tl_nhits"].size):
+        nh = st["tl_nhits"][k]
+        tl.append(ids[st["tl_hits"][k, R - nh:].astype(np.int64)] if nh > 0 else np.zeros(0, np.int64))
+    out["tl_hits"] = tl
+    out["ids"] = ids
+    return out
+
+
+class Report(dict):
+    def line(self) -> str:
+        return " ".join(f"{k}={v}" for k, v in self.items() if not isinstance(v, (list, np.ndarray)))
+
+
+def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: int = 3,
+            check_rates: bool = True, sectors=None, sector_of=None) -> Report:
+    """Assert GPU == oracle under the near-tie rules; return the counts of exclusions.
+
+    ``sectors`` restricts the comparison to clusters/tracks of those sectors (sampled
+    comparison at full size: sectors are independent in every step)."""
+    rep = Report()
+    g = to_id_space(st, n)
+    if sectors is None:
+        # ---- grid: bit-exact
+        assert np.array_equal(g["ids"], o["sorted_id"].astype(np.int64)), "grid order differs"
+        assert np.array_equal(st["bin_off"], o["bin_off"]), "bin offsets differ"
+        assert np.array_equal(st["row_off"], o["row_off"]), "row offsets differ"
+        assert np.array_equal(st["bin_base"], o["bin_base"]), "bin bases differ"
+        sel = np.ones(n, dtype=bool)
+    else:
+        sel = np.isin(sector_of, np.asarray(sectors))
+    valid = np.zeros(n, dtype=bool)
+    valid[g["ids"]] = True
+    # ---- links
+    flag = o["nb_flag"] != 0
+    cmp = sel & valid & ~flag
+    bad = np.nonzero(cmp & ((g["up"] != o["up"]) | (g["dn"] != o["dn"])))[0]
+    assert bad.size == 0, f"{bad.size} unflagged link mismatches, e.g. id {bad[:5]}"
+    rep["links"] = int((o["up"][sel] >= 0).sum())
+    rep["link_near_ties"] = int((sel & flag).sum())
+    # ---- cleaning
+    up_o, dn_o = o["up"], o["dn"]
+
+    def nbr_flag(a):
+        return np.where(a >= 0, flag[np.maximum(a, 0)], False)
+
+    taint_c = flag | nbr_flag(up_o) | nbr_flag(dn_o)
+    cmp = sel & valid & ~taint_c
+    bad = np.nonzero(cmp & ((g["up_c"] != o["up_c"]) | (g["dn_c"] != o["dn_c"])))[0]
+    assert bad.size == 0, f"{bad.size} unflagged cleaned-link mismatches"
+    # ---- starts: taint along the oracle chain (l_min hits), and through its head
+    upc = o["up_c"]
+    taint_s = taint_c.copy()
+    cur = np.arange(n)
+    alive = np.ones(n, dtype=bool)
+    for _ in range(l_min - 1):
+        nxt = np.where(alive, upc[cur], -1)
+        alive = nxt >= 0
+        taint_s |= np.where(alive, taint_c[np.maximum(nxt, 0)], False)
+        cur = np.maximum(nxt, 0)
+    so = set(int(x) for x in o["start_id"] if sel[x] and not taint_s[x])
+    sg = set(int(x) for x in g["start_id"] if sel[x] and not taint_s[x])
+    assert so == sg, f"start hits differ: {len(so ^ sg)}"
+    rep["starts"] = len(so)
+    rep["start_near_ties"] = int(sum(1 for x in o["start_id"] if sel[x] and taint_s[x]))
+    # ---- tracklets, aligned by start id; taint = oracle decision flags or a tainted link on its chain
+    chain_taint = np.zeros(n, dtype=bool)  # any tainted cleaned link from h upward along the whole chain
+    for h in o["start_id"]:
+        c = int(h)
+        t = False
+        while c >= 0:
+            t |= bool(taint_c[c])
+            c = int(upc[c])
+        chain_taint[int(h)] = t
+    gi = {int(s): k for k, s in enumerate(g["start_id"])}
+    tainted_hits = np.zeros(n, dtype=bool)
+    n_cmp = n_tl_ex = 0
+    worst = 0.0
+    for k, s in enumerate(o["start_id"]):
+        s = int(s)
+        if not sel[s]:
+            continue
+        oh = o["tl_hits"][k][o["tl_hits"][k] >= 0]
+        kg = gi.get(s)
+        bad_tl = o["tl_flag"][k] != 0 or chain_taint[s] or taint_s[s]
+        if bad_tl:
+            tainted_hits[oh] = True
+            if kg is not None:
+                tainted_hits[g["tl_hits"][kg]] = True
+            n_tl_ex += 1
+            continue
+        assert kg is not None, f"tracklet of start {s} missing on GPU"
+        gh = g["tl_hits"][kg]
+        assert np.array_equal(np.sort(oh), np.sort(gh)), f"tracklet {s}: hit sets differ ({oh.size} vs {gh.size})"
+        gv = bool(st["tl_flags"][kg] & 1)
+        assert gv == bool(o["tl_valid"][k]), f"tracklet {s}: validity differs"
+        if gv:
+            b = o["tl_state"][k]
+            a = st["tl_state"][kg].astype(np.float64)
+            err = np.abs(a - b) / np.maximum(np.abs(b), FLOORS)
+            worst = max(worst, float(err.max()))
+            assert np.all(err <= 1e-4), f"tracklet {s}: state differs {a} vs {b}"
+        n_cmp += 1
+    rep["tracklets_compared"] = n_cmp
+    rep["tracklet_near_ties"] = n_tl_ex
+    rep["tracklet_state_worst_rel"] = worst
+    # ---- hit keys of untainted hits
+    cmp = sel & valid & ~tainted_hits
+    assert np.array_equal(g["hit_key"][cmp], o["hit_key"][cmp]), "hit keys differ"
+    # ---- tracks
+    nt = len(tracks["start_id"])
+    gtr = {int(tracks["start_id"][k]): k for k in range(nt)}
+    n_tr = n_tr_ex = 0
+    worst = 0.0
+    for k in range(o["n_tracks"]):
+        t = int(o["trk_tl"][k])
+        s = int(o["start_id"][t])
+        if not sel[s]:
+            continue
+        oh = o["trk_hits"][o["trk_off"][k]:o["trk_off"][k + 1]]
+        if tainted_hits[oh].any():
+            n_tr_ex += 1
+            continue
+        kg = gtr.get(s)
+        assert kg is not None, f"track of start {s} missing on GPU"
+        gh = tracks["hit_ids"][tracks["hit_offset"][kg]:tracks["hit_offset"][kg] + tracks["n_hits"][kg]]
+        assert np.array_equal(oh, gh), f"track {s}: hit lists differ"
+        b = o["tl_state"][t]
+        a = tracks["state"][kg].astype(np.float64)
+        err = np.abs(a - b) / np.maximum(np.abs(b), FLOORS)
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= 1e-4), f"track {s}: parameters differ {a} vs {b}"
+        c = tracks["cov"][kg].astype(np.float64)
+        co = o["tl_cov"][t]
+        assert np.all(np.abs(c - co) <= 1e-4 * np.maximum(np.abs(co), 1e-9)), f"track {s}: covariance differs"
+        n_tr += 1
+    # GPU tracks that the oracle does not have must all touch tainted hits
+    o_starts = {int(o["start_id"][int(t)]) for t in o["trk_tl"]}
+    for s, kg in gtr.items():
+        if not sel[s] or s in o_starts:
+            continue
+        gh = tracks["hit_ids"][tracks["hit_offset"][kg]:tracks["hit_offset"][kg] + tracks["n_hits"][kg]]
+        assert tainted_hits[gh].any(), f"extra GPU track at start {s} without a near-tie"
+    rep["tracks_compared"] = n_tr
+    rep["track_near_ties"] = n_tr_ex
+    rep["track_state_worst_rel"] = worst
+    # ---- rates
+    if check_rates and leg is not None and sectors is None:
+        mo = metrics.match(leg, o["trk_off"], o["trk_hits"])
+        goff = np.concatenate([[0], np.cumsum(tracks["n_hits"])])
+        mg = metrics.match(leg, goff, tracks["hit_ids"])
+        for key in ("efficiency", "fake_rate", "clone_rate"):
+            assert abs(mo[key] - mg[key]) <= 1e-3, (key, mo[key], mg[key])
+            rep[key] = round(mg[key], 5)
+    return rep
