@@ -15,18 +15,22 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libtpcoracle.so")
+# The same source compiled with FMA contraction: only the rounding differs.  Parity checks use
+# the difference between the two builds as the oracle's own sensitivity to rounding.
+_LIB_FMA_PATH = os.path.join(_HERE, "libtpcoracle_fma.so")
 
 F_ARGMIN, F_CUT, F_WINDOW, F_SMAX, F_EDGE, F_MLP = 1, 2, 4, 8, 16, 32
 N_MLP_PARAMS = 5057
 
 
 def build() -> None:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (no fast-math, no FMA contraction), and its FMA-contracted twin."""
     src = os.path.join(_HERE, "tpc_oracle.c")
-    tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                           "-o", tmp, src, "-lm", "-lpthread"])
-    os.replace(tmp, _LIB_PATH)
+    for path, fl in ((_LIB_PATH, ["-ffp-contract=off"]), (_LIB_FMA_PATH, ["-ffp-contract=fast", "-mfma"])):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O2", *fl, "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, src, "-lm",
+                               "-lpthread"])
+        os.replace(tmp, path)
 
 
 class _Params(ctypes.Structure):
@@ -81,15 +85,15 @@ class _Output(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs: dict = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def _load(path: str = _LIB_PATH):
+    lib = _libs.get(path)
+    if lib is None:
+        if not os.path.exists(path):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         d = ctypes.POINTER(ctypes.c_double)
         lib.or_track.argtypes = [ctypes.POINTER(_Input), ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(_Output)]
         lib.or_track.restype = ctypes.c_int
@@ -106,8 +110,8 @@ def _load():
         lib.or_mlp_logit.restype = ctypes.c_double
         lib.or_features.argtypes = [ctypes.c_double] * 11 + [ctypes.c_int, ctypes.c_int, d]
         lib.or_features.restype = None
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return lib
 
 
 def _dptr(a: np.ndarray):
@@ -178,14 +182,15 @@ ALL_STAGES = 31
 
 
 def track(y, z, row, sector, geometry: dict, params: dict, bz: float, mlp: np.ndarray | None = None,
-          stages: int = ALL_STAGES, n_threads: int = 1) -> dict:
+          stages: int = ALL_STAGES, n_threads: int = 1, fma: bool = False) -> dict:
     """Run the oracle on host arrays.  Returns a dict of numpy arrays (copies).
 
     geometry: n_rows, row_x (float32 array), tan_half, n_sectors, z_min, z_max.
     params: the tracker settings (see ``_Params``); tie_rel defaults to 1e-5.
     mlp: 5057 BF16-valued parameters (float64 array) or None for the plain finder.
+    fma: run the FMA-contracted build (same arithmetic, different rounding).
     """
-    lib = _load()
+    lib = _load(_LIB_FMA_PATH if fma else _LIB_PATH)
     y = np.ascontiguousarray(y, dtype=np.float32)
     z = np.ascontiguousarray(z, dtype=np.float32)
     row = np.ascontiguousarray(row, dtype=np.uint8)

@@ -17,6 +17,10 @@ import numpy as np
 from synth import metrics
 
 FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 1e-2])
+# packed lower triangle (row-major): element k is (COV_I[k], COV_J[k]); DIAG are the (i, i) slots
+COV_I = np.array([i for i in range(5) for j in range(i + 1)])
+COV_J = np.array([j for i in range(5) for j in range(i + 1)])
+DIAG = np.array([i * (i + 1) // 2 + i for i in range(5)])
 HIT_DTYPE = np.dtype([("y", "<f4"), ("z", "<f4"), ("id", "<u4"), ("rs", "<u4")])
 
 
@@ -69,9 +73,23 @@ class Report(dict):
         return " ".join(f"{k}={v}" for k, v in self.items() if not isinstance(v, (list, np.ndarray)))
 
 
+def cov_scale_err(c, co):
+    """Per-element |c - co| in units of sqrt(C_ii C_jj) (correlation units); rows = tracks."""
+    co = np.atleast_2d(co)
+    c = np.atleast_2d(c)
+    d = np.sqrt(np.abs(co[:, DIAG]))
+    scale = d[:, COV_I] * d[:, COV_J]
+    return np.abs(c - co) / np.maximum(scale, 1e-300)
+
+
 def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: int = 3,
-            check_rates: bool = True, sectors=None, sector_of=None) -> Report:
+            check_rates: bool = True, sectors=None, sector_of=None, o_fma: dict | None = None) -> Report:
     """Assert GPU == oracle under the near-tie rules; return the counts of exclusions.
+
+    Covariances must agree within 1e-4 of their scale sqrt(C_ii C_jj), widened for a track to
+    10x the change of the oracle's own result between its plain and FMA-contracted builds
+    (``o_fma``): near a looper's turning point (|sin phi| -> 1) the x-parametrised model
+    amplifies rounding, and no FP64 implementation can be closer than the oracle is to itself.
 
     ``sectors`` restricts the comparison to clusters/tracks of those sectors (sampled
     comparison at full size: sectors are independent in every step)."""
@@ -167,8 +185,8 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
     # ---- tracks
     nt = len(tracks["start_id"])
     gtr = {int(tracks["start_id"][k]): k for k in range(nt)}
-    n_tr = n_tr_ex = 0
-    worst = 0.0
+    n_tr = n_tr_ex = n_widened = 0
+    worst = worst_cov = 0.0
     for k in range(o["n_tracks"]):
         t = int(o["trk_tl"][k])
         s = int(o["start_id"][t])
@@ -187,9 +205,18 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
         err = np.abs(a - b) / np.maximum(np.abs(b), FLOORS)
         worst = max(worst, float(err.max()))
         assert np.all(err <= 1e-4), f"track {s}: parameters differ {a} vs {b}"
+        # covariance: each element within 1e-4 of its natural scale sqrt(C_ii C_jj) (correlation units)
         c = tracks["cov"][kg].astype(np.float64)
         co = o["tl_cov"][t]
-        assert np.all(np.abs(c - co) <= 1e-4 * np.maximum(np.abs(co), 1e-9)), f"track {s}: covariance differs"
+        cerr = cov_scale_err(c, co)[0]
+        tol = 1e-4
+        if o_fma is not None:
+            self_err = float(cov_scale_err(o_fma["tl_cov"][t], co)[0].max())
+            if 10 * self_err > tol:
+                tol = 10 * self_err
+                n_widened += 1
+        worst_cov = max(worst_cov, float(cerr.max()))
+        assert np.all(cerr <= tol), f"track {s}: covariance differs, element {int(np.argmax(cerr))}: {c} vs {co}"
         n_tr += 1
     # GPU tracks that the oracle does not have must all touch tainted hits
     o_starts = {int(o["start_id"][int(t)]) for t in o["trk_tl"]}
@@ -201,6 +228,8 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
     rep["tracks_compared"] = n_tr
     rep["track_near_ties"] = n_tr_ex
     rep["track_state_worst_rel"] = worst
+    rep["track_cov_worst"] = worst_cov
+    rep["track_cov_tol_widened"] = n_widened
     # ---- rates
     if check_rates and leg is not None and sectors is None:
         mo = metrics.match(leg, o["trk_off"], o["trk_hits"])

@@ -55,7 +55,8 @@ def check(ctx, w, ev, params=None, label=""):
     trk = run_gpu(ctx, ev, geom, params)
     st = parity.gpu_stages(ctx, synth.N_ROWS)
     o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, params, synth.BZ, n_threads=THREADS)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, l_min=params["l_min_chain"])
+    o_fma = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, params, synth.BZ, n_threads=THREADS, fma=True)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, l_min=params["l_min_chain"], o_fma=o_fma)
     c = trk["counts"]
     assert c[0] == o["n_tracks"] or rep["track_near_ties"] > 0
     say(f"[parity] {label or w.name}: {rep.line()} gpu_tracks={c[0]} oracle_tracks={o['n_tracks']}")
