@@ -1,0 +1,167 @@
+"""Throughput of the MI355X CA track finder: TPC clusters tracked per second on one GPU.
+
+One step = one full pass of the hot path (row grid, neighbour finding, cleaning, start hits,
+tracklet construction, selection and output) over one synthetic workload already resident
+in HBM.  Prints one JSON line.  Also times, live with HIP events on the library's stream,
+each step of the chain; the dominant step is reported against the HBM roofline, and the FP64
+oracle is timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Algorithmic HBM bytes per cluster of each step (minimum traffic with 32-bit indices and
+# 16-byte hit records, each stage reading its inputs and writing its outputs once).
+ALG_BYTES_PER_CLUSTER = {"grid": 32.0, "neighbours": 32.0, "clean_starts": 24.0, "tracklets": 31.0,
+                         "selection": 34.0}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pbpb_event_5000")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    return ap.parse_args()
+
+
+def traffic_from_profile(kernel_src: str, stage: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on this kernel."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src_hash = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()
+    if rec.get("kernel_src_sha256") != src_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(ev, geom, params, budget_s: float):
+    """The oracle as it stands, on the host: single thread on a sector sample, then all cores."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    # sample: whole sectors of the workload (sectors are independent), enough for ~budget/2 s per mode
+    order = np.argsort(ev.sector, kind="stable")
+    counts = np.bincount(ev.sector, minlength=synth.N_SECTORS)
+    t0 = time.perf_counter()
+    sel = ev.sector == 0
+    oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=1)
+    per_cluster = (time.perf_counter() - t0) / max(1, sel.sum())
+    want = int(0.5 * budget_s / max(per_cluster, 1e-9))
+    n_sec = 1
+    while n_sec < synth.N_SECTORS and counts[:n_sec + 1].sum() <= want:
+        n_sec += 1
+    sel = ev.sector < n_sec
+    n_sample = int(sel.sum())
+    t0 = time.perf_counter()
+    oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=1)
+    t1 = time.perf_counter() - t0
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=cores)
+    tn = time.perf_counter() - t0
+    del order
+    return {"value": n_sample / t1, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": f"sectors 0..{n_sec - 1} of {ev.workload.name} ({n_sample} clusters), FP64 C oracle, 1 thread",
+            "value_all_cores": n_sample / tn, "cores_all": cores}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.WORKLOADS[args.workload]
+    log("generating", w.name)
+    ev = synth.generate(w)
+    log("generated", ev.n, "clusters")
+    geom = synth.geometry(w)
+    params = dict(synth.TRACKER_PARAMS)
+    if w.t_frame_us > 0:
+        params.update(bin_y=8.0, bin_z=16.0)
+    dev = torch.device("cuda", 0)
+    y = torch.from_numpy(ev.y).to(dev)
+    z = torch.from_numpy(ev.z).to(dev)
+    r = torch.from_numpy(ev.row).to(dev)
+    s = torch.from_numpy(ev.sector).to(dev)
+    ctx = tpcca.Context(0)
+    out = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
+    stream = torch.cuda.current_stream()
+    ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=True)  # sizes scratch
+    log("warmup")
+    for _ in range(args.warmup):
+        ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=False)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    log("timed", args.steps, "steps")
+    stage_ms, n_calls = ctx.profile_read()
+    counts = out["counts"].cpu().numpy()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = ev.n / (ms_step * 1e-3)
+    per_stage = {k: v / max(1, n_calls) for k, v in stage_ms.items()}
+    dom = max(per_stage, key=per_stage.get)
+    alg_bytes = ALG_BYTES_PER_CLUSTER[dom] * ev.n
+    achieved = alg_bytes / (per_stage[dom] * 1e-3) / 1e9
+    src = {"grid": "paper_1910_12214_amd/csrc/tpc_grid.hip", "neighbours": "paper_1910_12214_amd/csrc/tpc_links.hip",
+           "clean_starts": "paper_1910_12214_amd/csrc/tpc_links.hip",
+           "tracklets": "paper_1910_12214_amd/csrc/tpc_tracklets.hip",
+           "selection": "paper_1910_12214_amd/csrc/tpc_select.hip"}[dom]
+    traffic = traffic_from_profile(src, dom, w.name)
+    total_alg = sum(ALG_BYTES_PER_CLUSTER.values()) * ev.n
+    line = {
+        "metric": "TPC clusters tracked/s on 1 MI355X (plain CA finder)",
+        "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "clusters": ev.n, "tracks": int(counts[tpcca.CNT_TRACKS]),
+                   "tracklets": int(counts[tpcca.CNT_TRACKLETS]), "input_sha256": ev.sha256()[:16],
+                   "bin_cm": [params["bin_y"], params["bin_z"]]},
+        "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom]},
+        "path_roofline_frac": total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cb = cpu_baseline(ev, geom, params, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["gpu_over_oracle_1core"] = value / cb["value"]
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

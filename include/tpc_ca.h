@@ -155,6 +155,15 @@ int tpc_timeframe_tuning(tpc_ctx_t* ctx, tpc_tuning_t* out);
 /* Force the time-frame tiles (disables tuning) or, with NULL, re-enable tuning. */
 int tpc_timeframe_set_tuning(tpc_ctx_t* ctx, const tpc_tuning_t* tiles);
 
+/* Stage timing.  While enabled, every tracking call records HIP events on its
+ * stream between its steps: [0] grid, [1] neighbours (+ scorer), [2] cleaning and
+ * start hits, [3] tracklet construction, [4] selection and output.  tpc_profile_read
+ * waits for the recorded work, returns per-step sums in milliseconds (ms[TPC_N_PROF]),
+ * the number of calls summed, and resets the sums.  For measurement tools. */
+#define TPC_N_PROF 5
+int tpc_profile_enable(tpc_ctx_t* ctx, int on);
+int tpc_profile_read(tpc_ctx_t* ctx, double* ms, int* n_calls);
+
 /* Internal arrays of the last tracking call, for stage-by-stage checks.
  * Positions refer to the grid's sorted order (see TPC_STAGE_HITS). */
 enum {

@@ -23,6 +23,7 @@ void* buf(tpc_ctx_t* c, const char* name, size_t bytes) {
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+    c->geo_key.clear();
     // grow with headroom so that slightly larger inputs do not reallocate
     size_t want = bytes + bytes / 8;
     if (hipMalloc(&b.p, want) != hipSuccess) {
@@ -132,16 +133,25 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
         }
     if (nb >= (uint64_t(1) << 31)) return fail(c, TPC_ERR_ARG, "grid too fine: more than 2^31 bins (raise bin_y/bin_z)");
     base[S * R] = (uint32_t)nb;
-    // upload (small, synchronous)
+    // upload (small, synchronous) only when the tables change
     float* d_rowx = (float*)buf(c, "row_x", sizeof(float) * R);
     float* d_ymin = (float*)buf(c, "row_ymin", sizeof(float) * R);
     int32_t* d_ny = (int32_t*)buf(c, "row_ny", sizeof(int32_t) * R);
     uint32_t* d_base = (uint32_t*)buf(c, "bin_base", sizeof(uint32_t) * (S * R + 1));
     if (!d_rowx || !d_ymin || !d_ny || !d_base) return TPC_ERR_HIP;
-    TPC_HIP(c, hipMemcpy(d_rowx, geo->row_x, sizeof(float) * R, hipMemcpyHostToDevice));
-    TPC_HIP(c, hipMemcpy(d_ymin, ymin.data(), sizeof(float) * R, hipMemcpyHostToDevice));
-    TPC_HIP(c, hipMemcpy(d_ny, ny.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
-    TPC_HIP(c, hipMemcpy(d_base, base.data(), sizeof(uint32_t) * (S * R + 1), hipMemcpyHostToDevice));
+    std::string key((const char*)geo->row_x, sizeof(float) * R);
+    key.append((const char*)ymin.data(), sizeof(float) * R);
+    key.append((const char*)ny.data(), sizeof(int32_t) * R);
+    key.append((const char*)base.data(), sizeof(uint32_t) * (S * R + 1));
+    if (key != c->geo_key) {
+        // earlier calls on any stream may still read the old tables
+        TPC_HIP(c, hipDeviceSynchronize());
+        TPC_HIP(c, hipMemcpy(d_rowx, geo->row_x, sizeof(float) * R, hipMemcpyHostToDevice));
+        TPC_HIP(c, hipMemcpy(d_ymin, ymin.data(), sizeof(float) * R, hipMemcpyHostToDevice));
+        TPC_HIP(c, hipMemcpy(d_ny, ny.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
+        TPC_HIP(c, hipMemcpy(d_base, base.data(), sizeof(uint32_t) * (S * R + 1), hipMemcpyHostToDevice));
+        c->geo_key.swap(key);
+    }
     GridDesc& g = pr->g;
     g.R = R;
     g.S = S;
@@ -238,10 +248,31 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
 
 // The whole chain on one stream.  No host synchronisation inside: every count
 // that sizes later work stays in device memory.
+// Stage timing events (only while profiling is enabled).
+struct Marks {
+    tpc_ctx_t* c;
+    hipStream_t st;
+    std::vector<hipEvent_t> ev;
+    void mark() {
+        if (!c->prof_on) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, st);
+        ev.push_back(e);
+    }
+    void done() {
+        if (c->prof_on && ev.size() == TPC_N_PROF + 1) c->prof_events.push_back(ev);
+        else
+            for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
                    const tpc_tracks_t& out, int tl_blocks, int chunk, hipStream_t st) {
     const int64_t n = pr.n, T = pr.t_max, NB = pr.n_bins;
     const GridDesc& g = pr.g;
+    Marks mk{c, st, {}};
+    mk.mark();
     fill_u32(s.counters, 0u, C_N_COUNTERS, st);
     fill_u32(s.bin_cnt, 0u, NB, st);
     fill_u32(s.bin_fill, 0u, NB, st);
@@ -251,12 +282,16 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     scan_u32(s.bin_cnt, s.bin_off, NB, nullptr, s.bin_off + NB, s.scan, st);
     grid_scatter(cl, s.bin_of, s.bin_off, s.bin_fill, s.sorted_id, st);
     grid_finalize(cl, g, s.bin_off, s.sorted_id, s.hits, s.pos_of, s.row_off, s.counters, st);
+    mk.mark();
     // a2 neighbours, a4/a5 cleaning and starts
     find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
+    mk.mark();
     clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
     compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
+    mk.mark();
     // a6 tracklets
     build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.counters, s.tl, tl_blocks, chunk, st);
+    mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);
     select_keys(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, T, st);
@@ -266,7 +301,8 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     select_write(s.hits, s.starts, s.tl, g, s.counters, s.hit_key, s.own_cnt, s.trk_flag, s.hit_off, s.trk_idx, out,
                  T, st);
     finish_counts(s.counters, out.counts, st);
-    (void)c;
+    mk.mark();
+    mk.done();
 }
 
 int capacity_check(tpc_ctx_t* c, const tpc_tracks_t* out, hipStream_t st) {
@@ -363,6 +399,32 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     c->last_n_bins = pr.n_bins;
     c->last_n_starts_cap = pr.t_max;
     if (sync_check) return capacity_check(c, out, st);
+    return TPC_OK;
+}
+
+int tpc_profile_enable(tpc_ctx_t* c, int on) {
+    if (!c) return TPC_ERR_ARG;
+    c->prof_on = on != 0;
+    return TPC_OK;
+}
+
+int tpc_profile_read(tpc_ctx_t* c, double* ms, int* n_calls) {
+    if (!c || !ms) return TPC_ERR_ARG;
+    TPC_HIP(c, hipSetDevice(c->device));
+    for (int i = 0; i < TPC_N_PROF; ++i) ms[i] = 0.0;
+    int n = 0;
+    for (auto& ev : c->prof_events) {
+        TPC_HIP(c, hipEventSynchronize(ev.back()));
+        for (int i = 0; i < TPC_N_PROF; ++i) {
+            float t = 0.f;
+            TPC_HIP(c, hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            ms[i] += t;
+        }
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ++n;
+    }
+    c->prof_events.clear();
+    if (n_calls) *n_calls = n;
     return TPC_OK;
 }
 

@@ -99,6 +99,11 @@ struct tpc_ctx {
     tpc::Tuning tuning;
     std::map<std::string, tpc::GraphEntry> graphs;
     hipStream_t own_stream = nullptr;
+    // geometry tables already on the device (key of the last upload)
+    std::string geo_key;
+    // stage timing
+    bool prof_on = false;
+    std::vector<std::vector<hipEvent_t>> prof_events;  // per call: TPC_N_PROF + 1 events
 };
 
 namespace tpc {

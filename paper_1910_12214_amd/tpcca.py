@@ -62,7 +62,10 @@ class TrainCfg(ctypes.Structure):
 
 EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_default", "tpc_track_sectors",
            "tpc_track_timeframe", "tpc_timeframe_tuning", "tpc_timeframe_set_tuning", "tpc_stage_size",
-           "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train")
+           "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train",
+           "tpc_profile_enable", "tpc_profile_read")
+N_PROF = 5
+PROF_STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "selection")
 
 _lib = None
 
@@ -106,6 +109,10 @@ def load():
     lib.tpc_mlp_grad.restype = ctypes.c_int
     lib.tpc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, P(TrainCfg), _vp, _vp, _vp, _vp, _vp]
     lib.tpc_mlp_train.restype = ctypes.c_int
+    lib.tpc_profile_enable.argtypes = [_vp, ctypes.c_int]
+    lib.tpc_profile_enable.restype = ctypes.c_int
+    lib.tpc_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.tpc_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -239,6 +246,15 @@ class Context:
         a = np.empty(nb.value // np.dtype(dtype).itemsize, dtype=dtype)
         self._check(self.lib.tpc_stage_copy(self.h, stage, a.ctypes.data, nb.value))
         return a
+
+    def profile(self, on: bool):
+        self._check(self.lib.tpc_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self) -> tuple[dict, int]:
+        ms = (ctypes.c_double * N_PROF)()
+        n = ctypes.c_int(0)
+        self._check(self.lib.tpc_profile_read(self.h, ms, ctypes.byref(n)))
+        return {k: ms[i] for i, k in enumerate(PROF_STAGES)}, n.value
 
     # --------------------------------------------------------------- time frames
     def tuning(self) -> dict:
