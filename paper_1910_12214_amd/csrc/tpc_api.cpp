@@ -267,24 +267,33 @@ struct Marks {
     }
 };
 
-void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
-                   const tpc_tracks_t& out, int tl_blocks, int chunk, hipStream_t st) {
-    const int64_t n = pr.n, T = pr.t_max, NB = pr.n_bins;
+// a1: counting sort into the row grids (counters reset first).
+void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s, hipStream_t st) {
+    const int64_t n = pr.n, NB = pr.n_bins;
     const GridDesc& g = pr.g;
-    Marks mk{c, st, {}};
-    mk.mark();
     fill_u32(s.counters, 0u, C_N_COUNTERS, st);
     fill_u32(s.bin_cnt, 0u, NB, st);
     fill_u32(s.bin_fill, 0u, NB, st);
     fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
-    // a1 grid
     grid_count(cl, g, s.bin_of, s.bin_cnt, s.pos_of, st);
     scan_u32(s.bin_cnt, s.bin_off, NB, nullptr, s.bin_off + NB, s.scan, st);
     grid_scatter(cl, s.bin_of, s.bin_off, s.bin_fill, s.sorted_id, st);
     grid_finalize(cl, g, s.bin_off, s.sorted_id, s.hits, s.pos_of, s.row_off, s.counters, st);
+}
+
+void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
+                   const tpc_tracks_t& out, const float* mlp_q, int tl_blocks, int chunk, hipStream_t st) {
+    const int64_t n = pr.n, T = pr.t_max;
+    const GridDesc& g = pr.g;
+    Marks mk{c, st, {}};
     mk.mark();
-    // a2 neighbours, a4/a5 cleaning and starts
-    find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
+    enqueue_grid(cl, pr, s, st);
+    mk.mark();
+    // a2 neighbours (a3: with the learned scorer fused), a4/a5 cleaning and starts
+    if (mlp_q)
+        neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.counters, st);
+    else
+        find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
     clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
     compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
@@ -384,14 +393,19 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
         (rc = check_out(c, out)))
         return rc;
     if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
-    if (p->mlp) return fail(c, TPC_ERR_ARG, "learned pruning is not available in this build");
     TPC_HIP(c, hipSetDevice(c->device));
     Prepared pr;
     if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
     Scratch s;
     if ((rc = alloc_scratch(c, pr, &s))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    enqueue_chain(c, *cl, pr, s, *out, c->n_cu * 8, 1, st);
+    float* q = nullptr;
+    if (p->mlp) {
+        q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+        if (!q) return TPC_ERR_HIP;
+        mlp_quantize(p->mlp, q, st);
+    }
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * 8, 1, st);
     TPC_HIP(c, hipGetLastError());
     c->last_n = pr.n;
     c->last_R = pr.g.R;
@@ -425,6 +439,93 @@ int tpc_profile_read(tpc_ctx_t* c, double* ms, int* n_calls) {
     }
     c->prof_events.clear();
     if (n_calls) *n_calls = n;
+    return TPC_OK;
+}
+
+int tpc_mlp_infer(tpc_ctx_t* c, const float* feats, int64_t n, const float* mlp, float* logits, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!feats || !logits)) || !mlp) return fail(c, TPC_ERR_ARG, "bad scorer arguments");
+    TPC_HIP(c, hipSetDevice(c->device));
+    float* q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+    if (!q) return TPC_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    mlp_quantize(mlp, q, st);
+    mlp_infer(q, feats, n, logits, st);
+    TPC_HIP(c, hipGetLastError());
+    return TPC_OK;
+}
+
+int tpc_triplets(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, const tpc_params_t* p,
+                 int32_t* trip, float* feats, int64_t cap, int64_t* n_out, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p))) return rc;
+    if (!n_out || cap < 0 || (cap > 0 && (!trip || !feats))) return fail(c, TPC_ERR_ARG, "bad triplet outputs");
+    TPC_HIP(c, hipSetDevice(c->device));
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, 0.0, p, p->bin_y, p->bin_z, &pr))) return rc;
+    Scratch s;
+    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_grid(*cl, pr, s, st);
+    const int64_t n = pr.n;
+    // per-hit pair counts (reuse the link arrays as scratch), then offsets
+    uint32_t* cnt = (uint32_t*)s.up;
+    uint32_t* off = (uint32_t*)s.dn;
+    triplet_count(pr.g, pr.kp, s.hits, s.bin_off, n, s.counters, cnt, st);
+    uint32_t* total = s.counters + C_N_PAIRS;
+    scan_u32(cnt, off, n, s.counters + C_N_VALID_CLU, total, s.scan, st);
+    uint32_t tot = 0;
+    TPC_HIP(c, hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, st));
+    TPC_HIP(c, hipStreamSynchronize(st));
+    *n_out = tot;
+    if (tot > 0 && cap > 0) triplet_write(pr.g, pr.kp, s.hits, s.bin_off, n, s.counters, off, trip, feats, cap, st);
+    TPC_HIP(c, hipGetLastError());
+    TPC_HIP(c, hipStreamSynchronize(st));
+    return TPC_OK;
+}
+
+int tpc_mlp_grad(tpc_ctx_t* c, const float* feats, const uint8_t* labels, const int32_t* idx, int32_t n_batch,
+                 const float* mlp, float* grad, float* loss, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    if (n_batch < 1 || n_batch > 65536 || !feats || !labels || !idx || !mlp || !grad || !loss)
+        return fail(c, TPC_ERR_ARG, "bad gradient arguments");
+    TPC_HIP(c, hipSetDevice(c->device));
+    float* q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+    float* part = (float*)buf(c, "mlp_part", sizeof(float) * (size_t)mlp_grad_blocks(n_batch) * (TPC_MLP_N_PARAMS + 1));
+    if (!q || !part) return TPC_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    mlp_quantize(mlp, q, st);
+    mlp_grad_step(q, feats, labels, idx, n_batch, part, st);
+    mlp_reduce(part, n_batch, grad, loss, nullptr, nullptr, nullptr, 1, 0.f, 0.f, 0.f, 0.f, st);
+    TPC_HIP(c, hipGetLastError());
+    return TPC_OK;
+}
+
+int tpc_mlp_train(tpc_ctx_t* c, const float* feats, const uint8_t* labels, const int32_t* order,
+                  const tpc_train_cfg_t* cfg, float* mlp, float* m, float* v, float* loss, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    if (!cfg || cfg->batch < 1 || cfg->batch > 65536 || cfg->n_steps < 0 || cfg->step0 < 0 || !feats || !labels ||
+        !order || !mlp || !m || !v || !loss || !(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) ||
+        !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps > 0.f))
+        return fail(c, TPC_ERR_ARG, "bad training arguments");
+    TPC_HIP(c, hipSetDevice(c->device));
+    float* q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+    float* part = (float*)buf(c, "mlp_part", sizeof(float) * (size_t)mlp_grad_blocks(cfg->batch) * (TPC_MLP_N_PARAMS + 1));
+    if (!q || !part) return TPC_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    mlp_quantize(mlp, q, st);
+    for (int k = 0; k < cfg->n_steps; ++k) {
+        mlp_grad_step(q, feats, labels, order + (size_t)k * cfg->batch, cfg->batch, part, st);
+        mlp_reduce(part, cfg->batch, nullptr, loss + k, mlp, m, v, cfg->step0 + k + 1, cfg->lr, cfg->beta1, cfg->beta2,
+                   cfg->eps, st);
+        mlp_quantize(mlp, q, st);
+    }
+    TPC_HIP(c, hipGetLastError());
     return TPC_OK;
 }
 

@@ -176,16 +176,20 @@ void select_write(const Hit* hits, const uint32_t* starts, const TrackletOut& o,
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s);
 
 // mlp.hip
-void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
 size_t mlp_q_floats();
+void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
 void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s);
-void triplet_enumerate(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                       int64_t n_max, const uint32_t* counters, int32_t* trip, float* feats, int64_t cap,
-                       uint32_t* n_trip, hipStream_t s);
-void mlp_grad(const float* q, const float* master, const float* feats, const uint8_t* labels,
-              const int32_t* idx, int n_batch, float* partial, float* grad, float* loss, hipStream_t s);
-size_t mlp_grad_partial_floats(int n_batch);
-void mlp_adam(float* master, float* m, float* v, const float* grad, int step, float lr, float b1, float b2,
-              float eps, float* q, hipStream_t s);
+void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                    const uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* cnt, hipStream_t s);
+void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                   const uint32_t* counters, uint32_t* cnt, hipStream_t s);
+void triplet_write(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                   const uint32_t* counters, const uint32_t* off, int32_t* trip, float* feats, int64_t cap,
+                   hipStream_t s);
+int mlp_grad_blocks(int batch);
+void mlp_grad_step(const float* q, const float* feats, const uint8_t* labels, const int32_t* idx, int batch,
+                   float* part, hipStream_t s);
+void mlp_reduce(const float* part, int batch, float* grad, float* loss, float* master, float* m, float* v, int step,
+                float lr, float b1, float b2, float eps, hipStream_t s);
 
 }  // namespace tpc

@@ -1,0 +1,734 @@
+// Learned triplet scorer: MLP 12-64-64-1 on BF16 MFMA (v_mfma_f32_16x16x32_bf16).
+//
+// Layout.  Every layer is computed transposed, Out[unit][triplet] = W^T In, so a
+// wave's 16 x 16 accumulator tile holds units 4g..4g+3 (g = lane / 16) of triplet
+// lane % 16.  Those are exactly the eight k-values the next layer's B operand
+// needs from that lane when the k order of the weight fragments is permuted to
+// match (a dot product does not care about k order), so activations never leave
+// the registers between layers.
+//
+// Precision.  Weights are BF16 (round to nearest even of the FP32 master values),
+// biases FP32, products accumulate in FP32.  Activations are carried into the
+// next MFMA as three BF16 terms (hi + mid + lo represents the FP32 value to
+// ~2^-24), so the logits are FP32-faithful and a pruning decision logit >= tau
+// agrees with an FP64 evaluation of the same BF16-weight network except within
+// ~1e-5 of tau.  Training's backward pass uses single BF16 operands (its result
+// is a gradient, compared at BF16 tolerance).
+//
+// Fused pruning (neighbour finding with a scorer): each wave enumerates the
+// candidate (down, up) pairs of its 64 hits, stages their features in LDS
+// (ballot-free: slots from a wave prefix sum of per-lane pair counts), scores
+// 16 pairs per MFMA tile, and each lane then chooses its best surviving pair.
+#include "tpc_device.h"
+#include "tpc_internal.h"
+
+namespace tpc {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f4;
+
+// packed weight layout (bytes offsets in the q buffer)
+constexpr int kW1A = 0;                  // [T=4][j=2][lane=64][8] bf16
+constexpr int kW2A = kW1A + 4096 * 2;    // [T2=4][pair=2][lane=64][8] bf16 (forward)
+constexpr int kW2B = kW2A + 4096 * 2;    // [T1=4][pair=2][lane=64][8] bf16 (backward dh1 = W2 dz2)
+constexpr int kB1 = kW2B + 4096 * 2;     // [64] f32
+constexpr int kB2 = kB1 + 64 * 4;        // [64] f32
+constexpr int kW3 = kB2 + 64 * 4;        // [64] f32 (BF16-valued)
+constexpr int kB3 = kW3 + 64 * 4;        // [1] f32
+constexpr int kQBytes = kB3 + 16;
+
+// master layout (floats)
+constexpr int mW1 = 0, mB1 = 768, mW2 = 832, mB2 = 4928, mW3 = 4992, mB3 = 5056;
+constexpr int kNP = 5057;
+
+__device__ inline uint16_t bf16_bits(float f) {  // round to nearest, ties to even
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_val(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+__device__ inline __bf16 as_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// three-term split of an FP32 value into BF16 terms
+__device__ inline void split3(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+    h = bf16_bits(x);
+    const float r1 = x - bf16_val(h);
+    m = bf16_bits(r1);
+    const float r2 = r1 - bf16_val(m);
+    l = bf16_bits(r2);
+}
+
+__device__ inline f4 mfma(const bf16x8& a, const bf16x8& b, const f4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Per-lane copy of the forward weights.
+struct Frag {
+    bf16x8 w1[4][2];
+    bf16x8 w2[4][2];
+    float b1[4][4], b2[4][4], w3[4][4];
+    float b3;
+};
+
+__device__ inline void load_frag(const uint8_t* __restrict__ q, Frag& F) {
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    const bf16x8* w1 = (const bf16x8*)(q + kW1A);
+    const bf16x8* w2 = (const bf16x8*)(q + kW2A);
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            F.w1[T][j] = w1[(T * 2 + j) * 64 + lane];
+            F.w2[T][j] = w2[(T * 2 + j) * 64 + lane];
+        }
+    const float* b1 = (const float*)(q + kB1);
+    const float* b2 = (const float*)(q + kB2);
+    const float* w3 = (const float*)(q + kW3);
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            F.b1[T][i] = b1[16 * T + 4 * g + i];
+            F.b2[T][i] = b2[16 * T + 4 * g + i];
+            F.w3[T][i] = w3[16 * T + 4 * g + i];
+        }
+    F.b3 = *(const float*)(q + kB3);
+}
+
+// Activations of one 16-triplet tile in accumulator layout.
+struct Act {
+    f4 z1[4], z2[4];
+    float z3;  // logit of triplet lane % 16 (same in all four lane groups)
+};
+
+// Layer-1 B operand for K-step j from an LDS row of 40 BF16 (36 split features + zero pad).
+__device__ inline bf16x8 x_frag(const uint16_t* __restrict__ row, int j, int g) {
+    const int k0 = 32 * j + 8 * g;
+    bf16x8 b;
+    if (k0 >= 40) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i] = as_bf16(0);
+    } else {
+        const uint4 v = *(const uint4*)(row + k0);
+        b = __builtin_bit_cast(bf16x8, v);
+    }
+    return b;
+}
+
+// Forward pass of one tile; xs points to the tile's 16 LDS rows (stride 40 BF16).
+__device__ inline void forward_tile(const Frag& F, const uint16_t* __restrict__ xs, Act& A) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    const uint16_t* row = xs + n * 40;
+    const bf16x8 x0 = x_frag(row, 0, g), x1 = x_frag(row, 1, g);
+#pragma unroll
+    for (int T = 0; T < 4; ++T) {
+        f4 c = {F.b1[T][0], F.b1[T][1], F.b1[T][2], F.b1[T][3]};
+        c = mfma(F.w1[T][0], x0, c);
+        c = mfma(F.w1[T][1], x1, c);
+        A.z1[T] = c;
+    }
+    // layer 2: the lane's 16 hidden values, three BF16 terms each
+    uint16_t hs[3][4][4];
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float h = A.z1[T][i] > 0.f ? A.z1[T][i] : 0.f;
+            split3(h, hs[0][T][i], hs[1][T][i], hs[2][T][i]);
+        }
+    f4 c2[4];
+#pragma unroll
+    for (int T2 = 0; T2 < 4; ++T2) c2[T2] = f4{F.b2[T2][0], F.b2[T2][1], F.b2[T2][2], F.b2[T2][3]};
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+            bf16x8 b;
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) b[4 * t + i] = as_bf16(hs[s][2 * pr + t][i]);
+#pragma unroll
+            for (int T2 = 0; T2 < 4; ++T2) c2[T2] = mfma(F.w2[T2][pr], b, c2[T2]);
+        }
+    float part = 0.f;
+#pragma unroll
+    for (int T2 = 0; T2 < 4; ++T2) {
+        A.z2[T2] = c2[T2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part += F.w3[T2][i] * (c2[T2][i] > 0.f ? c2[T2][i] : 0.f);
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    A.z3 = part + F.b3;
+}
+
+// Features of a triplet (down d, middle m, up u), FP32.
+__device__ inline void features(float xd, float yd, float zd, float xm, float ym, float zm, float xu, float yu, float zu,
+                                float wy, float wz, int nu, int nd, float f[12]) {
+    const float dxd = xm - xd, dxu = xu - xm, dxt = xu - xd;
+    f[0] = (xd - 166.0f) / 81.0f;
+    f[1] = (xm - 166.0f) / 81.0f;
+    f[2] = (xu - 166.0f) / 81.0f;
+    f[3] = (yd - ym) / (wy * dxd);
+    f[4] = (yu - ym) / (wy * dxu);
+    f[5] = (zd - zm) / (wz * dxd);
+    f[6] = (zu - zm) / (wz * dxu);
+    f[7] = (yu - yd) / dxt;
+    f[8] = (zu - zd) / dxt;
+    const float ax = dxd, ay = ym - yd, bx = dxu, by = yu - ym, cx = dxt, cy = yu - yd;
+    const float cross = ax * cy - ay * cx;
+    const float la = sqrtf(ax * ax + ay * ay), lb = sqrtf(bx * bx + by * by), lc = sqrtf(cx * cx + cy * cy);
+    f[9] = 20.0f * cross / (la * lb * lc);
+    f[10] = 0.25f * (float)nu;
+    f[11] = 0.25f * (float)nd;
+}
+
+// write the 36 split terms (+4 zeros) of 12 features into an LDS row of 40 BF16
+__device__ inline void stage_row(uint16_t* __restrict__ row, const float f[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        uint16_t h, m, l;
+        split3(f[k], h, m, l);
+        row[k] = h;
+        row[12 + k] = m;
+        row[24 + k] = l;
+    }
+#pragma unroll
+    for (int k = 36; k < 40; ++k) row[k] = 0;
+}
+
+// ------------------------------------------------------------ weight packing
+__global__ void k_quantize(const float* __restrict__ m, uint8_t* __restrict__ q) {
+    uint16_t* w1a = (uint16_t*)(q + kW1A);
+    uint16_t* w2a = (uint16_t*)(q + kW2A);
+    uint16_t* w2b = (uint16_t*)(q + kW2B);
+    for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+        const int i = e & 7, lane = (e >> 3) & 63, j = (e >> 9) & 1, T = e >> 10;
+        const int row = lane & 15, g = lane >> 4;
+        // W1: A[unit][k], k = 32 j + 8 g + i -> feature k % 12 of split k / 12 (zero for k >= 36)
+        const int k = 32 * j + 8 * g + i;
+        const int unit = 16 * T + row;
+        w1a[e] = k < 36 ? bf16_bits(m[mW1 + (k % 12) * 64 + unit]) : 0;
+        // W2 forward: A[unit2][k1], k1 = 16 (2 pair + t) + 4 g + i' with i = 4 t + i'
+        const int t = i >> 2, ii = i & 3;
+        const int k1 = 16 * (2 * j + t) + 4 * g + ii;
+        w2a[e] = bf16_bits(m[mW2 + k1 * 64 + unit]);
+        // W2 backward: A[hidden1 unit][hidden2 u], u = 16 (2 pair + t) + 4 g + i'
+        w2b[e] = bf16_bits(m[mW2 + unit * 64 + k1]);
+    }
+    float* b1 = (float*)(q + kB1);
+    float* b2 = (float*)(q + kB2);
+    float* w3 = (float*)(q + kW3);
+    for (int e = threadIdx.x; e < 64; e += blockDim.x) {
+        b1[e] = m[mB1 + e];
+        b2[e] = m[mB2 + e];
+        w3[e] = bf16_val(bf16_bits(m[mW3 + e]));
+    }
+    if (threadIdx.x == 0) *(float*)(q + kB3) = m[mB3];
+}
+
+// ------------------------------------------------------------ inference
+constexpr int kInferWaves = 4;
+
+__global__ __launch_bounds__(64 * kInferWaves) void k_infer(const uint8_t* __restrict__ q, const float* __restrict__ feats,
+                                                            int64_t n, float* __restrict__ logits) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kInferWaves][16 * 40];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, nn = lane & 15;
+    uint16_t* xs = xs_all[w];
+    Frag F;
+    load_frag(q, F);
+    const int64_t n_tiles = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + w; tile < n_tiles; tile += (int64_t)gridDim.x * kInferWaves) {
+        const int64_t t = tile * 16 + nn;
+        if (g == 0) {
+            float f[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) f[k] = t < n ? feats[t * 12 + k] : 0.f;
+            stage_row(xs + nn * 40, f);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Act A;
+        forward_tile(F, xs, A);
+        if (g == 0 && t < n) logits[t] = A.z3;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// ------------------------------------------------- triplet enumeration (training data)
+__device__ inline int count_window(const GridDesc& g, const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+                                   const BinRange& B, double ym, double zm, double wy, double wz) {
+    int c = 0;
+    if (B.empty) return 0;
+    for (int iz = B.iz0; iz <= B.iz1; ++iz) {
+        const uint32_t k1 = bin_off[B.base + iz * B.ny + B.iy1 + 1];
+        for (uint32_t k = bin_off[B.base + iz * B.ny + B.iy0]; k < k1; ++k) {
+            const Hit h = hits[k];
+            c += (fabs((double)h.y - ym) <= wy) && (fabs((double)h.z - zm) <= wz);
+        }
+    }
+    return c;
+}
+
+// Calls fn(pos, hit) for each window candidate of range B (exact FP64 window test).
+template <typename Fn>
+__device__ inline void for_window(const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off, const BinRange& B,
+                                  double ym, double zm, double wy, double wz, Fn fn) {
+    if (B.empty) return;
+    for (int iz = B.iz0; iz <= B.iz1; ++iz) {
+        const uint32_t k1 = bin_off[B.base + iz * B.ny + B.iy1 + 1];
+        for (uint32_t k = bin_off[B.base + iz * B.ny + B.iy0]; k < k1; ++k) {
+            const Hit h = hits[k];
+            if (fabs((double)h.y - ym) <= wy && fabs((double)h.z - zm) <= wz) fn(k, h);
+        }
+    }
+}
+
+struct Win {
+    bool ok;
+    int r, s;
+    double xm, xu, xd, wyu, wzu, wyd, wzd;
+    BinRange U, D;
+};
+
+__device__ inline Win window_of(const GridDesc& g, const KParams& kp, const Hit& m) {
+    Win w;
+    w.r = (int)(m.rs % (uint32_t)g.R);
+    w.s = (int)(m.rs / (uint32_t)g.R);
+    w.ok = w.r > 0 && w.r < g.R - 1;
+    if (!w.ok) return w;
+    w.xm = g.row_x[w.r];
+    w.xu = g.row_x[w.r + 1];
+    w.xd = g.row_x[w.r - 1];
+    const double ym = m.y, zm = m.z;
+    w.wyu = kp.win_y * (w.xu - w.xm);
+    w.wzu = kp.win_z * (w.xu - w.xm);
+    w.wyd = kp.win_y * (w.xm - w.xd);
+    w.wzd = kp.win_z * (w.xm - w.xd);
+    w.U = bin_range(g, w.s, w.r + 1, ym - w.wyu, ym + w.wyu, zm - w.wzu, zm + w.wzu);
+    w.D = bin_range(g, w.s, w.r - 1, ym - w.wyd, ym + w.wyd, zm - w.wzd, zm + w.wzd);
+    w.ok = !w.U.empty && !w.D.empty;
+    return w;
+}
+
+__global__ __launch_bounds__(kBlock) void k_trip_count(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                       const uint32_t* __restrict__ bin_off,
+                                                       const uint32_t* __restrict__ counters, uint32_t* __restrict__ cnt) {
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const Hit m = hits[p];
+    const Win w = window_of(g, kp, m);
+    uint32_t c = 0;
+    if (w.ok) {
+        const int nu = count_window(g, hits, bin_off, w.U, m.y, m.z, w.wyu, w.wzu);
+        const int nd = count_window(g, hits, bin_off, w.D, m.y, m.z, w.wyd, w.wzd);
+        c = (uint32_t)(nu * nd);
+    }
+    cnt[p] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_trip_write(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                       const uint32_t* __restrict__ bin_off,
+                                                       const uint32_t* __restrict__ counters,
+                                                       const uint32_t* __restrict__ off, int32_t* __restrict__ trip,
+                                                       float* __restrict__ feats, int64_t cap) {
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const Hit m = hits[p];
+    const Win w = window_of(g, kp, m);
+    if (!w.ok) return;
+    const int nu = count_window(g, hits, bin_off, w.U, m.y, m.z, w.wyu, w.wzu);
+    const int nd = count_window(g, hits, bin_off, w.D, m.y, m.z, w.wyd, w.wzd);
+    int64_t slot = off[p];
+    const float wy = (float)kp.win_y, wz = (float)kp.win_z;
+    for_window(hits, bin_off, w.U, m.y, m.z, w.wyu, w.wzu, [&](uint32_t, const Hit& u) {
+        for_window(hits, bin_off, w.D, m.y, m.z, w.wyd, w.wzd, [&](uint32_t, const Hit& d) {
+            if (slot < cap) {
+                trip[slot * 3 + 0] = (int32_t)d.id;
+                trip[slot * 3 + 1] = (int32_t)m.id;
+                trip[slot * 3 + 2] = (int32_t)u.id;
+                float f[12];
+                features((float)w.xd, d.y, d.z, (float)w.xm, m.y, m.z, (float)w.xu, u.y, u.z, wy, wz, nu, nd, f);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) feats[slot * 12 + k] = f[k];
+            }
+            ++slot;
+        });
+    });
+}
+
+// ------------------------------------------------- fused neighbour finding with pruning
+constexpr int kNbWaves = 4;
+constexpr int kCap = 128;  // staged pairs per wave and round
+
+__global__ __launch_bounds__(64 * kNbWaves) void k_neighbours_mlp(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                                  const uint32_t* __restrict__ bin_off,
+                                                                  const uint32_t* __restrict__ counters,
+                                                                  const uint8_t* __restrict__ q,
+                                                                  int32_t* __restrict__ up, int32_t* __restrict__ dn,
+                                                                  uint32_t* __restrict__ cnt) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kNbWaves][kCap * 40];
+    __shared__ float lg_all[kNbWaves][kCap];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t* xs = xs_all[w];
+    float* lg = lg_all[w];
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t p = (blockIdx.x * kNbWaves + w) * 64 + lane;
+    const bool act = p < n;
+    Hit m;
+    Win win;
+    win.ok = false;
+    int nu = 0, nd = 0;
+    if (act) {
+        m = hits[p];
+        win = window_of(g, kp, m);
+        if (win.ok) {
+            nu = count_window(g, hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu);
+            nd = count_window(g, hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd);
+        }
+    }
+    const uint32_t np = (uint32_t)(nu * nd);
+    // wave prefix sum of the pair counts
+    uint32_t incl = np;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    const uint32_t slot0 = incl - np;
+    const uint32_t total = __shfl(incl, 63, 64);
+    Frag F;
+    if (total) load_frag(q, F);
+    double best = 1e300;
+    uint32_t bu_id = 0xFFFFFFFFu, bd_id = 0xFFFFFFFFu;
+    int32_t bu = -1, bd = -1;
+    uint32_t kept = 0;
+    const float wy = (float)kp.win_y, wz = (float)kp.win_z;
+    for (uint32_t base = 0; base < total; base += kCap) {
+        const uint32_t lim = total - base < (uint32_t)kCap ? total - base : (uint32_t)kCap;
+        // stage features of the pairs whose slots fall in this round
+        if (np && slot0 < base + lim && slot0 + np > base) {
+            uint32_t j = 0;
+            for_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu, [&](uint32_t, const Hit& u) {
+                for_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd, [&](uint32_t, const Hit& d) {
+                    const uint32_t sl = slot0 + j++;
+                    if (sl >= base && sl < base + lim) {
+                        float f[12];
+                        features((float)win.xd, d.y, d.z, (float)win.xm, m.y, m.z, (float)win.xu, u.y, u.z, wy, wz, nu,
+                                 nd, f);
+                        stage_row(xs + (sl - base) * 40, f);
+                    }
+                });
+            });
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t t0 = 0; t0 < lim; t0 += 16) {
+            Act A;
+            forward_tile(F, xs + t0 * 40, A);
+            const int nn = lane & 15;
+            if (lane < 16 && t0 + nn < lim) lg[t0 + nn] = A.z3;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // choose among the kept pairs of this round
+        if (np && slot0 < base + lim && slot0 + np > base) {
+            const double xm = win.xm, xd = win.xd, xu = win.xu;
+            const double ym = m.y, zm = m.z;
+            const double wgt = (xm - xd) / (xu - xd);
+            uint32_t j = 0;
+            for_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu, [&](uint32_t ku, const Hit& u) {
+                for_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd, [&](uint32_t kd, const Hit& d) {
+                    const uint32_t sl = slot0 + j++;
+                    if (sl < base || sl >= base + lim) return;
+                    if (!((double)lg[sl - base] >= kp.tau)) return;
+                    ++kept;
+                    const double yu = u.y, zu = u.z, yd = d.y, zd = d.z;
+                    const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
+                    const double Dv = (ym - py) * (ym - py) / kp.vy15 + (zm - pz) * (zm - pz) / kp.vz15;
+                    if (!(Dv <= kp.nb_cut)) return;
+                    if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
+                        best = Dv;
+                        bu = (int32_t)ku;
+                        bd = (int32_t)kd;
+                        bu_id = u.id;
+                        bd_id = d.id;
+                    }
+                });
+            });
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (act) {
+        up[p] = bu;
+        dn[p] = bd;
+    }
+    const uint32_t linked = bu >= 0;
+    // per-wave sums (no block barrier needed: one atomic per wave)
+    uint32_t a = wave_sum(np), b = wave_sum(kept), c = wave_sum(linked);
+    if (lane == 0) {
+        if (a) atomicAdd(&cnt[C_N_PAIRS], a);
+        if (b) atomicAdd(&cnt[C_N_PAIRS_KEPT], b);
+        if (c) atomicAdd(&cnt[C_N_LINKS_RAW], c);
+    }
+}
+
+// ------------------------------------------------------------ training
+constexpr int kTrainChunk = 256;  // triplets per block (one wave) and step
+
+__device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// One wave per block; block b handles rows [b*chunk, (b+1)*chunk) of the batch.
+// Writes the block's gradient contribution (master layout) and loss sum to part[b].
+__global__ __launch_bounds__(64) void k_train_grad(const uint8_t* __restrict__ q, const float* __restrict__ feats,
+                                                   const uint8_t* __restrict__ labels, const int32_t* __restrict__ idx,
+                                                   int batch, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[16 * 40];
+    // transposed BF16 stages for the weight gradients: [unit][32 triplets]
+    __shared__ __attribute__((aligned(16))) uint16_t h1s[64 * 32], dz2s[64 * 32], dz1s[64 * 32], xts[16 * 32];
+    const int lane = threadIdx.x, g = lane >> 4, nn = lane & 15;
+    Frag F;
+    load_frag(q, F);
+    const bf16x8* w2b = (const bf16x8*)(q + kW2B);
+    bf16x8 wb[4][2];
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) wb[T][j] = w2b[(T * 2 + j) * 64 + lane];
+    f4 gW2[4][4], gW1[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = f4{0, 0, 0, 0};
+    }
+    float gb1[4][4], gb2[4][4], gw3[4][4];
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gb1[T][i] = gb2[T][i] = gw3[T][i] = 0.f;
+    float gb3 = 0.f, loss = 0.f;
+    const float inv_b = 1.0f / (float)batch;
+    const int r0 = blockIdx.x * kTrainChunk;
+    const int r1 = min(batch, r0 + kTrainChunk);
+    for (int base = r0; base < r1; base += 32) {
+        // two 16-triplet tiles fill 32 columns of the transposed stages
+        for (int half = 0; half < 2; ++half) {
+            const int row = base + 16 * half + nn;
+            const bool valid = row < r1;
+            const int id = valid ? idx[row] : 0;
+            float f[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) f[k] = valid ? feats[(int64_t)id * 12 + k] : 0.f;
+            if (g == 0) stage_row(xs + nn * 40, f);
+            __syncthreads();
+            Act A;
+            forward_tile(F, xs, A);
+            const float y = valid ? (float)labels[id] : 0.f;
+            const float dz3 = valid ? (sigmoidf_(A.z3) - y) * inv_b : 0.f;
+            if (g == 0 && valid) {
+                // BCE = softplus(z) - y z, stable form
+                const float z = A.z3;
+                loss += fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - y * z;
+                gb3 += dz3;
+            }
+            // dz2 = w3 * dz3 * (z2 > 0); bias and w3 gradients
+            float dz2[4][4];
+            uint16_t dz2b[4][4];
+#pragma unroll
+            for (int T = 0; T < 4; ++T)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z2 = A.z2[T][i];
+                    const float h2 = z2 > 0.f ? z2 : 0.f;
+                    gw3[T][i] += h2 * dz3;
+                    dz2[T][i] = z2 > 0.f ? F.w3[T][i] * dz3 : 0.f;
+                    gb2[T][i] += dz2[T][i];
+                    dz2b[T][i] = bf16_bits(dz2[T][i]);
+                }
+            // dh1 = W2 dz2 (MFMA, K = hidden-2 units in the lane-held order)
+            f4 dh1[4];
+#pragma unroll
+            for (int T = 0; T < 4; ++T) dh1[T] = f4{0, 0, 0, 0};
+#pragma unroll
+            for (int pr = 0; pr < 2; ++pr) {
+                bf16x8 b;
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) b[4 * t + i] = as_bf16(dz2b[2 * pr + t][i]);
+#pragma unroll
+                for (int T = 0; T < 4; ++T) dh1[T] = mfma(wb[T][pr], b, dh1[T]);
+            }
+            // stage h1, dz2, dz1 (unit-major) and x (feature-major) for the batch contractions
+            const int col = 16 * half + nn;
+#pragma unroll
+            for (int T = 0; T < 4; ++T)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int u = 16 * T + 4 * g + i;
+                    const float z1 = A.z1[T][i];
+                    const float dz1 = z1 > 0.f ? dh1[T][i] : 0.f;
+                    gb1[T][i] += dz1;
+                    h1s[u * 32 + col] = bf16_bits(z1 > 0.f ? z1 : 0.f);
+                    dz2s[u * 32 + col] = dz2b[T][i];
+                    dz1s[u * 32 + col] = bf16_bits(dz1);
+                }
+            if (g == 0) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) xts[k * 32 + col] = bf16_bits(f[k]);
+#pragma unroll
+                for (int k = 12; k < 16; ++k) xts[k * 32 + col] = 0;
+            }
+            __syncthreads();
+        }
+        // dW2[k1][u] += sum_n h1[k1][n] dz2[u][n];  dW1[f][k1] += sum_n x[f][n] dz1[k1][n]
+        bf16x8 ah[4], bz[4], bz1[4];
+#pragma unroll
+        for (int T = 0; T < 4; ++T) {
+            ah[T] = __builtin_bit_cast(bf16x8, *(const uint4*)(h1s + (16 * T + nn) * 32 + 8 * g));
+            bz[T] = __builtin_bit_cast(bf16x8, *(const uint4*)(dz2s + (16 * T + nn) * 32 + 8 * g));
+            bz1[T] = __builtin_bit_cast(bf16x8, *(const uint4*)(dz1s + (16 * T + nn) * 32 + 8 * g));
+        }
+        const bf16x8 ax = __builtin_bit_cast(bf16x8, *(const uint4*)(xts + nn * 32 + 8 * g));
+#pragma unroll
+        for (int Tk = 0; Tk < 4; ++Tk)
+#pragma unroll
+            for (int Tu = 0; Tu < 4; ++Tu) gW2[Tk][Tu] = mfma(ah[Tk], bz[Tu], gW2[Tk][Tu]);
+#pragma unroll
+        for (int T = 0; T < 4; ++T) gW1[T] = mfma(ax, bz1[T], gW1[T]);
+        __syncthreads();
+    }
+    // reduce the per-lane vectors over the 16 triplet lanes of each group
+    float* out = part + (size_t)blockIdx.x * (kNP + 1);
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float a = gb1[T][i], b = gb2[T][i], c = gw3[T][i];
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                a += __shfl_xor(a, d, 64);
+                b += __shfl_xor(b, d, 64);
+                c += __shfl_xor(c, d, 64);
+            }
+            if (nn == 0) {
+                const int u = 16 * T + 4 * g + i;
+                out[mB1 + u] = a;
+                out[mB2 + u] = b;
+                out[mW3 + u] = c;
+            }
+        }
+    // accumulator tiles: lane (g, col) holds rows 4g+i of column col
+#pragma unroll
+    for (int Tk = 0; Tk < 4; ++Tk)
+#pragma unroll
+        for (int Tu = 0; Tu < 4; ++Tu)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[mW2 + (16 * Tk + 4 * g + i) * 64 + 16 * Tu + nn] = gW2[Tk][Tu][i];
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 4 * g + i;
+            if (f < 12) out[mW1 + f * 64 + 16 * T + nn] = gW1[T][i];
+        }
+    float s3 = gb3, sl = loss;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        s3 += __shfl_xor(s3, d, 64);
+        sl += __shfl_xor(sl, d, 64);
+    }
+    if (lane == 0) {
+        out[mB3] = s3;
+        out[kNP] = sl;
+    }
+}
+
+// Sum the block partials in a fixed order; optionally apply Adam and repack the weights.
+__global__ __launch_bounds__(256) void k_reduce_adam(const float* __restrict__ part, int n_part, int batch,
+                                                     float* __restrict__ grad, float* __restrict__ loss, float* master,
+                                                     float* m, float* v, int step, float lr, float b1, float b2,
+                                                     float eps) {
+    for (int i = threadIdx.x; i <= kNP; i += blockDim.x) {
+        float s = 0.f;
+        for (int b = 0; b < n_part; ++b) s += part[(size_t)b * (kNP + 1) + i];
+        if (i == kNP) {
+            if (loss) *loss = s / (float)batch;
+            continue;
+        }
+        if (grad) grad[i] = s;
+        if (master) {
+            const float mi = b1 * m[i] + (1.f - b1) * s;
+            const float vi = b2 * v[i] + (1.f - b2) * s * s;
+            m[i] = mi;
+            v[i] = vi;
+            const float mh = mi / (1.f - powf(b1, (float)step));
+            const float vh = vi / (1.f - powf(b2, (float)step));
+            master[i] -= lr * mh / (sqrtf(vh) + eps);
+        }
+    }
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1); }
+
+}  // namespace
+
+size_t mlp_q_floats() { return (kQBytes + 3) / 4; }
+
+void mlp_quantize(const float* master, float* q, hipStream_t s) {
+    k_quantize<<<1, 256, 0, s>>>(master, (uint8_t*)q);
+}
+
+void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t tiles = (n + 15) / 16;
+    int64_t nb = (tiles + kInferWaves - 1) / kInferWaves;
+    if (nb > 8192) nb = 8192;
+    k_infer<<<(unsigned)nb, 64 * kInferWaves, 0, s>>>((const uint8_t*)q, feats, n, logits);
+}
+
+void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                    const uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* cnt, hipStream_t s) {
+    const int64_t waves = (n_max + 63) / 64;
+    const unsigned nb = (unsigned)((waves + kNbWaves - 1) / kNbWaves > 0 ? (waves + kNbWaves - 1) / kNbWaves : 1);
+    k_neighbours_mlp<<<nb, 64 * kNbWaves, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, up, dn, cnt);
+}
+
+void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                   const uint32_t* counters, uint32_t* cnt, hipStream_t s) {
+    k_trip_count<<<blocks(n_max), kBlock, 0, s>>>(g, kp, hits, bin_off, counters, cnt);
+}
+
+void triplet_write(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
+                   const uint32_t* counters, const uint32_t* off, int32_t* trip, float* feats, int64_t cap,
+                   hipStream_t s) {
+    k_trip_write<<<blocks(n_max), kBlock, 0, s>>>(g, kp, hits, bin_off, counters, off, trip, feats, cap);
+}
+
+int mlp_grad_blocks(int batch) { return (batch + kTrainChunk - 1) / kTrainChunk; }
+
+void mlp_grad_step(const float* q, const float* feats, const uint8_t* labels, const int32_t* idx, int batch,
+                   float* part, hipStream_t s) {
+    k_train_grad<<<mlp_grad_blocks(batch), 64, 0, s>>>((const uint8_t*)q, feats, labels, idx, batch, part);
+}
+
+void mlp_reduce(const float* part, int batch, float* grad, float* loss, float* master, float* m, float* v, int step,
+                float lr, float b1, float b2, float eps, hipStream_t s) {
+    k_reduce_adam<<<1, 256, 0, s>>>(part, mlp_grad_blocks(batch), batch, grad, loss, master, m, v, step, lr, b1, b2,
+                                    eps);
+}
+
+}  // namespace tpc
