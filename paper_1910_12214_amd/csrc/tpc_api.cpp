@@ -24,6 +24,7 @@ void* buf(tpc_ctx_t* c, const char* name, size_t bytes) {
     b.p = nullptr;
     b.bytes = 0;
     c->geo_key.clear();
+    ++c->buf_gen;
     // grow with headroom so that slightly larger inputs do not reallocate
     size_t want = bytes + bytes / 8;
     if (hipMalloc(&b.p, want) != hipSuccess) {
@@ -413,6 +414,198 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     c->last_n_bins = pr.n_bins;
     c->last_n_starts_cap = pr.t_max;
     if (sync_check) return capacity_check(c, out, st);
+    return TPC_OK;
+}
+
+// ------------------------------------------------------------ time frames
+namespace {
+
+std::string bytes_of(const void* p, size_t n) { return std::string((const char*)p, n); }
+
+// One eager run of the chain with the given tiles; returns its time in ms (synchronises).
+int timed_run(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
+              tpc_tracks_t* out, hipStream_t st, const Tuning& t, float* ms) {
+    tpc_params_t p2 = *p;
+    p2.bin_y = t.bin_y;
+    p2.bin_z = t.bin_z;
+    Prepared pr;
+    int rc;
+    if ((rc = prepare(c, cl, geo, bz, &p2, t.bin_y, t.bin_z, &pr))) return rc;
+    Scratch s;
+    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    float* q = nullptr;
+    if (p->mlp) {
+        q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+        if (!q) return TPC_ERR_HIP;
+        mlp_quantize(p->mlp, q, st);
+    }
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, st);  // warm (sizes, caches)
+    hipEvent_t e0, e1;
+    TPC_HIP(c, hipEventCreate(&e0));
+    TPC_HIP(c, hipEventCreate(&e1));
+    TPC_HIP(c, hipEventRecord(e0, st));
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, st);
+    TPC_HIP(c, hipEventRecord(e1, st));
+    TPC_HIP(c, hipEventSynchronize(e1));
+    TPC_HIP(c, hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof_on = prof;
+    TPC_HIP(c, hipGetLastError());
+    return TPC_OK;
+}
+
+// Two-stage search: grid bin size first, then queue chunk x persistent blocks per CU.
+int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
+             tpc_tracks_t* out, hipStream_t st) {
+    static const float bins[][2] = {{8.f, 8.f}, {8.f, 16.f}, {12.f, 24.f}, {16.f, 32.f}};
+    static const int chunks[] = {1, 2, 4};
+    static const int bpcs[] = {4, 8, 16};
+    Tuning best;
+    best.best_ms = 1e30f;
+    int n = 0, rc;
+    for (auto& b : bins) {
+        Tuning t;
+        t.bin_y = b[0];
+        t.bin_z = b[1];
+        t.chunk = 1;
+        t.blocks_per_cu = 8;
+        float ms = 0.f;
+        if ((rc = timed_run(c, cl, geo, bz, p, out, st, t, &ms))) return rc;
+        ++n;
+        if (ms < best.best_ms) {
+            best = t;
+            best.best_ms = ms;
+        }
+    }
+    const Tuning base = best;
+    for (int ch : chunks)
+        for (int bp : bpcs) {
+            if (ch == base.chunk && bp == base.blocks_per_cu) continue;
+            Tuning t = base;
+            t.chunk = ch;
+            t.blocks_per_cu = bp;
+            float ms = 0.f;
+            if ((rc = timed_run(c, cl, geo, bz, p, out, st, t, &ms))) return rc;
+            ++n;
+            if (ms < best.best_ms) {
+                best = t;
+                best.best_ms = ms;
+            }
+        }
+    best.n_candidates = n;
+    c->tuning = best;
+    return TPC_OK;
+}
+
+}  // namespace
+
+int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz,
+                        const tpc_params_t* p, tpc_tracks_t* out, void* stream, int sync_check) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p)) ||
+        (rc = check_out(c, out)))
+        return rc;
+    if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
+    TPC_HIP(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    // tiles: forced, or tuned once per shape (cluster count bucket, geometry)
+    int lg = 0;
+    while ((int64_t(1) << lg) < cl->n) ++lg;
+    std::string shape = std::to_string(lg) + "|" + bytes_of(geo->row_x, sizeof(float) * geo->n_rows) +
+                        bytes_of(&geo->z_min, sizeof(float)) + bytes_of(&geo->z_max, sizeof(float)) +
+                        std::to_string(geo->n_sectors) + (p->mlp ? "|mlp" : "");
+    if (!c->tune_forced && (!c->tuned || c->tuned_key != shape)) {
+        if ((rc = autotune(c, cl, geo, bz, p, out, st))) return rc;
+        c->tuned = true;
+        c->tuned_key = shape;
+    }
+    const Tuning t = c->tuning;
+    tpc_params_t p2 = *p;
+    p2.bin_y = t.bin_y;
+    p2.bin_z = t.bin_z;
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, bz, &p2, t.bin_y, t.bin_z, &pr))) return rc;
+    Scratch s;
+    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    float* q = nullptr;
+    if (p->mlp) {
+        q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
+        if (!q) return TPC_ERR_HIP;
+    }
+    const int blocks = c->n_cu * t.blocks_per_cu;
+    c->last_n = pr.n;
+    c->last_R = pr.g.R;
+    c->last_S = pr.g.S;
+    c->last_n_bins = pr.n_bins;
+    c->last_n_starts_cap = pr.t_max;
+    if (c->prof_on) {  // stage timing needs eager launches
+        if (q) mlp_quantize(p->mlp, q, st);
+        enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, st);
+        TPC_HIP(c, hipGetLastError());
+    } else {
+        // every kernel argument is part of the key: a replay runs exactly the captured chain
+        std::string key = bytes_of(cl, sizeof *cl) + bytes_of(&p2, sizeof p2) + bytes_of(out, sizeof *out) +
+                          bytes_of(&bz, sizeof bz) + bytes_of(&t, sizeof t) + bytes_of(&c->buf_gen, sizeof c->buf_gen) +
+                          c->geo_key;
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (c->graphs.size() >= 8) {  // bounded cache
+                for (auto& kv : c->graphs) {
+                    (void)hipGraphExecDestroy(kv.second.exec);
+                    (void)hipGraphDestroy(kv.second.graph);
+                }
+                c->graphs.clear();
+            }
+            if (!c->own_stream) TPC_HIP(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+            TPC_HIP(c, hipStreamSynchronize(st));
+            GraphEntry ge;
+            TPC_HIP(c, hipStreamBeginCapture(c->own_stream, hipStreamCaptureModeThreadLocal));
+            if (q) mlp_quantize(p->mlp, q, c->own_stream);
+            enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, c->own_stream);
+            TPC_HIP(c, hipStreamEndCapture(c->own_stream, &ge.graph));
+            TPC_HIP(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+            it = c->graphs.emplace(key, ge).first;
+        }
+        TPC_HIP(c, hipGraphLaunch(it->second.exec, st));
+    }
+    if (sync_check) return capacity_check(c, out, st);
+    return TPC_OK;
+}
+
+int tpc_timeframe_tuning(tpc_ctx_t* c, tpc_tuning_t* o) {
+    if (!c || !o) return TPC_ERR_ARG;
+    if (!c->tuned && !c->tune_forced) return fail(c, TPC_ERR_STATE, "no time frame tuned yet");
+    o->bin_y = c->tuning.bin_y;
+    o->bin_z = c->tuning.bin_z;
+    o->tracklet_chunk = c->tuning.chunk;
+    o->blocks_per_cu = c->tuning.blocks_per_cu;
+    o->best_ms = c->tuning.best_ms;
+    o->n_candidates = c->tuning.n_candidates;
+    return TPC_OK;
+}
+
+int tpc_timeframe_set_tuning(tpc_ctx_t* c, const tpc_tuning_t* t) {
+    if (!c) return TPC_ERR_ARG;
+    if (!t) {
+        c->tune_forced = false;
+        c->tuned = false;
+        return TPC_OK;
+    }
+    if (!(t->bin_y > 0.f) || !(t->bin_z > 0.f) || t->tracklet_chunk < 1 || t->tracklet_chunk > 64 ||
+        t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
+        return fail(c, TPC_ERR_ARG, "bad tiles");
+    c->tuning.bin_y = t->bin_y;
+    c->tuning.bin_z = t->bin_z;
+    c->tuning.chunk = t->tracklet_chunk;
+    c->tuning.blocks_per_cu = t->blocks_per_cu;
+    c->tuning.best_ms = 0.f;
+    c->tuning.n_candidates = 0;
+    c->tune_forced = true;
     return TPC_OK;
 }
 

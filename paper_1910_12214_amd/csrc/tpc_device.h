@@ -5,9 +5,11 @@
 
 namespace tpc {
 
-// Bins of row-sector (s, r) overlapping [y0,y1] x [z0,z1], widened by one bin on
-// every side (the FP32 bin index of a hit may round across a bin edge); the
-// caller's window tests are exact, so the widening only adds candidates.
+// Bins of row-sector (s, r) overlapping [y0,y1] x [z0,z1].  A hit's bin index is
+// floor(fl32(fl32(y - ymin) * inv_bin)), within a relative 2^-23 of the exact
+// coordinate V(y) = (y - ymin) * inv_bin that this range is computed from, so a
+// margin of 1e-6 |V| + 1e-6 (bin units) keeps every hit inside [y0, y1] in the
+// range; the caller's window tests are exact, so the margin only adds candidates.
 struct BinRange {
     int iy0, iy1, iz0, iz1, ny;
     uint32_t base;
@@ -18,8 +20,10 @@ __device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0,
     BinRange b;
     b.ny = g.row_ny[r];
     const double ymin = g.row_ymin[r], iby = g.inv_by, ibz = g.inv_bz, zmin = g.z_min;
-    const double fy0 = floor((y0 - ymin) * iby) - 1.0, fy1 = floor((y1 - ymin) * iby) + 1.0;
-    const double fz0 = floor((z0 - zmin) * ibz) - 1.0, fz1 = floor((z1 - zmin) * ibz) + 1.0;
+    const double vy0 = (y0 - ymin) * iby, vy1 = (y1 - ymin) * iby;
+    const double vz0 = (z0 - zmin) * ibz, vz1 = (z1 - zmin) * ibz;
+    const double fy0 = floor(vy0 - (1e-6 * fabs(vy0) + 1e-6)), fy1 = floor(vy1 + (1e-6 * fabs(vy1) + 1e-6));
+    const double fz0 = floor(vz0 - (1e-6 * fabs(vz0) + 1e-6)), fz1 = floor(vz1 + (1e-6 * fabs(vz1) + 1e-6));
     b.empty = !(fy1 >= 0.0) || !(fz1 >= 0.0) || !(fy0 <= (double)(b.ny - 1)) || !(fz0 <= (double)(g.nz - 1));
     b.iy0 = fy0 < 0.0 ? 0 : (int)fy0;
     b.iy1 = fy1 > (double)(b.ny - 1) ? b.ny - 1 : (int)fy1;

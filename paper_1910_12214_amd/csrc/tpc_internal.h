@@ -101,6 +101,7 @@ struct tpc_ctx {
     hipStream_t own_stream = nullptr;
     // geometry tables already on the device (key of the last upload)
     std::string geo_key;
+    uint64_t buf_gen = 0;  // bumped whenever a scratch buffer moves (invalidates captured graphs)
     // stage timing
     bool prof_on = false;
     std::vector<std::vector<hipEvent_t>> prof_events;  // per call: TPC_N_PROF + 1 events

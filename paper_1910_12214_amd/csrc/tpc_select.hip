@@ -28,7 +28,11 @@ __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, c
         const uint32_t nh = (uint32_t)o.nhits[k];
         const uint64_t key = tl_key(nh, hits[starts[k]].id);
         const int32_t* slot = o.hits + (size_t)k * R;
-        for (int j = R - (int)nh; j < R; ++j) atomicMax((unsigned long long*)&hit_key[slot[j]], (unsigned long long)key);
+        for (int j = R - (int)nh; j < R; ++j) {
+            const int32_t pos = slot[j];
+            // keys only grow: a plain read at or above ours makes the atomic unnecessary
+            if (hit_key[pos] < key) atomicMax((unsigned long long*)&hit_key[pos], (unsigned long long)key);
+        }
     }
 }
 

@@ -13,9 +13,11 @@
 // FP64 makes every arg-min and cut decision agree with an FP64 reference except
 // at genuine near-ties.
 //
-// Work distribution: a persistent grid; each wave pops `chunk` x 64 tracklets
-// from an atomic queue, so long tracklets do not stall a statically assigned
-// block.  Results do not depend on which lane builds which tracklet.
+// Work distribution: a persistent grid of waves; each lane runs its tracklet as a
+// small state machine (pass A row, pass B row, finished) and takes a new
+// tracklet from an atomic queue as soon as its current one ends, so the wave
+// stays busy until the queue is empty.  Results do not depend on which lane
+// builds which tracklet.
 //
 // Per-tracklet hit slot of n_rows entries: pass A appends ascending from the
 // front, pass B writes its hits from the back (descending rows), so the final
@@ -175,156 +177,207 @@ __device__ inline void c0_init(double C[15], const KParams& kp) {
     C[14] = kp.c0q;
 }
 
-// Builds tracklet k; returns bit0 = valid, bit1 = fit failure.
-__device__ uint32_t build_one(uint32_t k, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                              const uint32_t* __restrict__ bin_off, const int32_t* __restrict__ upc,
-                              const uint32_t* __restrict__ starts, const TrackletOut& o) {
+// Per-lane tracklet state between row steps.
+struct Lane {
+    int phase;  // 0 needs work, 1 pass A, 2 pass B, 3 retired
+    uint32_t k;
+    int s, r0, r, last, inner, nA, nB, ia, miss, ndf;
+    int32_t next;
+    bool on, fail;
+    double x, chi2, pl2, pl3, pl4;
+    double p[5], C[15];
+    float pin[5], cin[15];
+};
+
+__device__ inline void save_inner(Lane& L) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) L.pin[i] = (float)L.p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) L.cin[i] = (float)L.C[i];
+}
+
+__device__ inline void start_pass_a(Lane& L, uint32_t k, const GridDesc& g, const KParams& kp,
+                                    const Hit* __restrict__ hits, const int32_t* __restrict__ upc,
+                                    const uint32_t* __restrict__ starts, const TrackletOut& o) {
     const int R = g.R;
+    L.k = k;
     const uint32_t p0 = starts[k];
     const Hit h0 = hits[p0];
-    const int s = (int)(h0.rs / (uint32_t)R), r0 = (int)(h0.rs % (uint32_t)R);
-    int32_t* slot = o.hits + (size_t)k * R;
-    const double tanh_ = kp.tan_half;
-    // ---- pass A
+    L.s = (int)(h0.rs / (uint32_t)R);
+    L.r0 = (int)(h0.rs % (uint32_t)R);
     const int32_t p1 = upc[p0];
     const Hit h1 = hits[p1];
-    const double x0 = g.row_x[r0], x1 = g.row_x[h1.rs % (uint32_t)R];
+    const double x0 = g.row_x[L.r0], x1 = g.row_x[h1.rs % (uint32_t)R];
     const double ty = ((double)h1.y - (double)h0.y) / (x1 - x0);
     const double tz = ((double)h1.z - (double)h0.z) / (x1 - x0);
-    double p[5], C[15];
-    p[0] = h0.y;
-    p[1] = h0.z;
-    p[2] = ty / sqrt(1.0 + ty * ty);
-    p[3] = tz * sqrt(1.0 - p[2] * p[2]);
-    p[4] = 0.0;
-    c0_init(C, kp);
-    slot[0] = (int32_t)p0;
-    int nA = 1, last = r0;
-    double pl2 = p[2], pl3 = p[3], pl4 = p[4];
-    int32_t next = p1;
-    bool on = true, fail = false;
-    int miss = 0;
-    double x = x0;
-    for (int r = r0 + 1; r < R; ++r) {
-        const double xr = g.row_x[r];
-        if (!propagate(p, C, x, xr, kp)) break;
-        x = xr;
-        if (fabs(p[0]) > x * tanh_ + kp.edge) break;
-        int32_t acc = -1;
-        Hit ha;
-        if (on) {
-            if (next >= 0) {
-                const Hit hn = hits[next];
-                if ((int)(hn.rs % (uint32_t)R) == r && chi2_of(p, C, hn.y, hn.z, kp) <= kp.fol_cut) {
-                    acc = next;
-                    ha = hn;
-                    next = upc[next];
-                } else {
-                    on = false;
-                }
-            } else {
-                on = false;
-            }
-        }
-        if (acc < 0) {
-            acc = search_row(g, kp, hits, bin_off, s, r, p, C);
-            if (acc >= 0) ha = hits[acc];
-        }
-        if (acc >= 0) {
-            double c2;
-            if (!kf_update(p, C, ha.y, ha.z, kp, c2)) {
-                fail = true;
-                break;
-            }
-            slot[nA++] = acc;
-            last = r;
-            pl2 = p[2];
-            pl3 = p[3];
-            pl4 = p[4];
-            miss = 0;
-        } else if (++miss > kp.n_miss) {
-            break;
-        }
-    }
-    // ---- pass B
-    int nB = 0, inner = last, ndf = 0;
-    double chi2 = 0.0;
-    double pin[5], cin[15];
-    if (!fail) {
-        const int32_t pb = slot[nA - 1];
-        const Hit hb = hits[pb];
-        p[0] = hb.y;
-        p[1] = hb.z;
-        p[2] = pl2;
-        p[3] = pl3;
-        p[4] = pl4;
-        c0_init(C, kp);
-        slot[R - 1] = pb;
-        nB = 1;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) pin[i] = p[i];
-#pragma unroll
-        for (int i = 0; i < 15; ++i) cin[i] = C[i];
-        x = g.row_x[last];
-        miss = 0;
-        int ia = nA - 2;
-        for (int r = last - 1; r >= 0; --r) {
-            const double xr = g.row_x[r];
-            if (!propagate(p, C, x, xr, kp)) break;
-            x = xr;
-            if (fabs(p[0]) > x * tanh_ + kp.edge) break;
-            int32_t acc = -1;
-            Hit ha;
-            if (r >= r0) {
-                if (ia >= 0) {
-                    const int32_t pa = slot[ia];
-                    const Hit hp = hits[pa];
-                    if ((int)(hp.rs % (uint32_t)R) == r) {
-                        acc = pa;
-                        ha = hp;
-                        --ia;
-                    }
-                }
-            } else {
-                acc = search_row(g, kp, hits, bin_off, s, r, p, C);
-                if (acc >= 0) ha = hits[acc];
-            }
-            if (acc >= 0) {
-                double c2;
-                if (!kf_update(p, C, ha.y, ha.z, kp, c2)) {
-                    fail = true;
-                    break;
-                }
-                chi2 += c2;
-                ndf += 2;
-                slot[R - 1 - nB] = acc;
-                ++nB;
-                inner = r;
-#pragma unroll
-                for (int i = 0; i < 5; ++i) pin[i] = p[i];
-#pragma unroll
-                for (int i = 0; i < 15; ++i) cin[i] = C[i];
-                miss = 0;
-            } else if (++miss > kp.n_miss) {
-                break;
-            }
-        }
-    }
+    L.p[0] = h0.y;
+    L.p[1] = h0.z;
+    L.p[2] = ty / sqrt(1.0 + ty * ty);
+    L.p[3] = tz * sqrt(1.0 - L.p[2] * L.p[2]);
+    L.p[4] = 0.0;
+    c0_init(L.C, kp);
+    o.hits[(size_t)k * R] = (int32_t)p0;
+    L.nA = 1;
+    L.last = L.r0;
+    L.pl2 = L.p[2];
+    L.pl3 = L.p[3];
+    L.pl4 = L.p[4];
+    L.next = p1;
+    L.on = true;
+    L.fail = false;
+    L.miss = 0;
+    L.x = x0;
+    L.r = L.r0 + 1;
+    L.phase = 1;
+}
+
+__device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+                                    const TrackletOut& o) {
+    const int R = g.R;
+    int32_t* slot = o.hits + (size_t)L.k * R;
+    const int32_t pb = slot[L.nA - 1];
+    const Hit hb = hits[pb];
+    L.p[0] = hb.y;
+    L.p[1] = hb.z;
+    L.p[2] = L.pl2;
+    L.p[3] = L.pl3;
+    L.p[4] = L.pl4;
+    c0_init(L.C, kp);
+    slot[R - 1] = pb;
+    L.nB = 1;
+    L.inner = L.last;
+    L.chi2 = 0.0;
+    L.ndf = 0;
+    save_inner(L);
+    L.x = g.row_x[L.last];
+    L.miss = 0;
+    L.ia = L.nA - 2;
+    L.r = L.last - 1;
+    L.phase = 2;
+}
+
+// Writes the tracklet's outputs; returns bit0 = valid, bit1 = fit failure.
+__device__ inline uint32_t finish(Lane& L, const KParams& kp, const TrackletOut& o) {
+    const bool fail = L.fail;
+    const int nB = fail ? 0 : L.nB;
     const bool valid = !fail && nB >= kp.n_min_tl;
-    o.nhits[k] = fail ? 0 : nB;
-    o.chi2[k] = (float)chi2;
-    o.ndf[k] = ndf;
-    o.row_ref[k] = inner;
+    const uint32_t k = L.k;
+    o.nhits[k] = nB;
+    o.chi2[k] = fail ? 0.f : (float)L.chi2;
+    o.ndf[k] = fail ? 0 : L.ndf;
+    o.row_ref[k] = L.phase == 2 ? L.inner : L.last;
     o.flags[k] = (valid ? 1u : 0u) | (fail ? 2u : 0u);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) o.state[(size_t)k * 5 + i] = fail ? 0.f : (float)pin[i];
+    for (int i = 0; i < 5; ++i) o.state[(size_t)k * 5 + i] = fail ? 0.f : L.pin[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) o.cov[(size_t)k * 15 + i] = fail ? 0.f : (float)cin[i];
+    for (int i = 0; i < 15; ++i) o.cov[(size_t)k * 15 + i] = fail ? 0.f : L.cin[i];
+    L.phase = 0;
     return (valid ? 1u : 0u) | (fail ? 2u : 0u);
+}
+
+// One row of pass A; returns true when pass A has ended.
+__device__ inline bool step_a(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+                              const uint32_t* __restrict__ bin_off, const int32_t* __restrict__ upc,
+                              const TrackletOut& o) {
+    const int R = g.R;
+    const int r = L.r;
+    if (r >= R) return true;
+    const double xr = g.row_x[r];
+    if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
+    L.x = xr;
+    if (fabs(L.p[0]) > xr * kp.tan_half + kp.edge) return true;
+    int32_t acc = -1;
+    Hit ha;
+    if (L.on) {
+        if (L.next >= 0) {
+            const Hit hn = hits[L.next];
+            if ((int)(hn.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hn.y, hn.z, kp) <= kp.fol_cut) {
+                acc = L.next;
+                ha = hn;
+                L.next = upc[L.next];
+            } else {
+                L.on = false;
+            }
+        } else {
+            L.on = false;
+        }
+    }
+    if (acc < 0) {
+        acc = search_row(g, kp, hits, bin_off, L.s, r, L.p, L.C);
+        if (acc >= 0) ha = hits[acc];
+    }
+    L.r = r + 1;
+    if (acc >= 0) {
+        double c2;
+        if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
+            L.fail = true;
+            return true;
+        }
+        o.hits[(size_t)L.k * R + L.nA] = acc;
+        ++L.nA;
+        L.last = r;
+        L.pl2 = L.p[2];
+        L.pl3 = L.p[3];
+        L.pl4 = L.p[4];
+        L.miss = 0;
+        return false;
+    }
+    return ++L.miss > kp.n_miss;
+}
+
+// One row of pass B; returns true when pass B has ended.
+__device__ inline bool step_b(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+                              const uint32_t* __restrict__ bin_off, const TrackletOut& o) {
+    const int R = g.R;
+    const int r = L.r;
+    if (r < 0) return true;
+    const double xr = g.row_x[r];
+    if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
+    L.x = xr;
+    if (fabs(L.p[0]) > xr * kp.tan_half + kp.edge) return true;
+    int32_t* slot = o.hits + (size_t)L.k * R;
+    int32_t acc = -1;
+    Hit ha;
+    if (r >= L.r0) {
+        if (L.ia >= 0) {
+            const int32_t pa = slot[L.ia];
+            const Hit hp = hits[pa];
+            if ((int)(hp.rs % (uint32_t)R) == r) {
+                acc = pa;
+                ha = hp;
+                --L.ia;
+            }
+        }
+    } else {
+        acc = search_row(g, kp, hits, bin_off, L.s, r, L.p, L.C);
+        if (acc >= 0) ha = hits[acc];
+    }
+    L.r = r - 1;
+    if (acc >= 0) {
+        double c2;
+        if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
+            L.fail = true;
+            return true;
+        }
+        L.chi2 += c2;
+        L.ndf += 2;
+        slot[R - 1 - L.nB] = acc;
+        ++L.nB;
+        L.inner = r;
+        save_inner(L);
+        L.miss = 0;
+        return false;
+    }
+    return ++L.miss > kp.n_miss;
 }
 
 constexpr int kTlBlock = 128;
 
+// Persistent kernel.  Every lane advances its own tracklet by one row per
+// iteration; a lane whose tracklet is finished takes the next one from the
+// queue at once (one atomic per wave for all idle lanes), so long and short
+// tracklets share a wave without idling it.  `chunk` scales how many queue
+// entries an idle lane reserves at a time (1 = one tracklet).
 __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, const Hit* __restrict__ hits,
                                                         const uint32_t* __restrict__ bin_off,
                                                         const int32_t* __restrict__ upc,
@@ -333,15 +386,45 @@ __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, 
     const uint32_t n = counters[C_N_STARTS];
     const int lane = threadIdx.x & 63;
     uint32_t n_valid = 0, n_fail = 0;
+    Lane L;
+    L.phase = 0;
+    uint32_t res_next = 0, res_end = 0;  // this lane's reserved queue range
     while (true) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&counters[C_QUEUE_TL], 64u * (uint32_t)chunk);
-        base = __shfl(base, 0, 64);
-        if (base >= n) break;
-        for (int c = 0; c < chunk; ++c) {
-            const uint32_t k = base + (uint32_t)c * 64u + (uint32_t)lane;
-            if (k < n) {
-                const uint32_t f = build_one(k, g, kp, hits, bin_off, upc, starts, o);
+        // refill lanes without work
+        if (L.phase == 0 && res_next < res_end) {
+            start_pass_a(L, res_next++, g, kp, hits, upc, starts, o);
+        }
+        const uint64_t need = __ballot(L.phase == 0);
+        if (need) {
+            const uint32_t cnt = (uint32_t)__popcll(need) * (uint32_t)chunk;
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&counters[C_QUEUE_TL], cnt);
+            base = __shfl(base, 0, 64);
+            if (L.phase == 0) {
+                const uint64_t below = lane ? (need & (~0ull >> (64 - lane))) : 0ull;
+                const uint32_t mine = base + (uint32_t)__popcll(below) * (uint32_t)chunk;
+                res_next = mine;
+                res_end = mine + (uint32_t)chunk < n ? mine + (uint32_t)chunk : n;
+                if (res_next < res_end)
+                    start_pass_a(L, res_next++, g, kp, hits, upc, starts, o);
+                else
+                    L.phase = 3;
+            }
+        }
+        if (!__ballot(L.phase == 1 || L.phase == 2)) break;
+        if (L.phase == 1) {
+            if (step_a(L, g, kp, hits, bin_off, upc, o)) {
+                if (L.fail) {
+                    const uint32_t f = finish(L, kp, o);
+                    n_valid += f & 1u;
+                    n_fail += (f >> 1) & 1u;
+                } else {
+                    start_pass_b(L, g, kp, hits, o);
+                }
+            }
+        } else if (L.phase == 2) {
+            if (step_b(L, g, kp, hits, bin_off, o)) {
+                const uint32_t f = finish(L, kp, o);
                 n_valid += f & 1u;
                 n_fail += (f >> 1) & 1u;
             }

@@ -78,6 +78,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1910_12214_amd/build.py "
                            "(the track finder has no CPU fallback)")
+    # Import torch first.  torch bundles its own HIP runtime with the same soname
+    # (libamdhip64.so.7) as the system one this library links; whichever loads first serves
+    # the whole process.  Loading torch's first gives one runtime, so torch's allocations
+    # and streams are native to the library's calls.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     lib.tpc_ctx_create.argtypes = [P(_vp), ctypes.c_int]

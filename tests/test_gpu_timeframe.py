@@ -1,0 +1,170 @@
+"""Continuous-readout time frames: graph-captured, autotuned path vs the per-sector path and the
+oracle (needs an MI355X)."""
+import dataclasses
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+KEYS = ("hit_offset", "n_hits", "hit_ids", "start_id", "sector", "row_ref", "x_ref", "state", "cov", "chi2", "ndf")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1910_12214_amd import tpcca
+
+    c = tpcca.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def same(a, b):
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["counts"][:8], b["counts"][:8])
+
+
+@pytest.fixture(scope="module")
+def small_tf():
+    w = synth.scaled(synth.PBPB_TIMEFRAME, 0.02)
+    return w, synth.generate(w)
+
+
+def test_timeframe_equals_sector_path(ctx, small_tf):
+    from paper_1910_12214_amd import tpcca
+
+    w, ev = small_tf
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    ctx.set_tuning(None)
+    a = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))
+    tun = ctx.tuning()
+    say(f"[tf] tuned: {tun}")
+    assert tun["n_candidates"] >= 4
+    b = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, dict(synth.TRACKER_PARAMS, bin_y=3.0, bin_z=7.0)))
+    same(a, b)
+    c = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))  # graph replay
+    same(a, c)
+
+
+@pytest.mark.parametrize("tiles", [dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=4),
+                                   dict(bin_y=16.0, bin_z=32.0, tracklet_chunk=4, blocks_per_cu=16),
+                                   dict(bin_y=5.0, bin_z=11.0, tracklet_chunk=2, blocks_per_cu=1)])
+def test_every_tile_choice_gives_identical_tracks(ctx, small_tf, tiles):
+    from paper_1910_12214_amd import tpcca
+
+    w, ev = small_tf
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    ref = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS))
+    ctx.set_tuning(tiles)
+    got = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))
+    ctx.set_tuning(None)
+    same(ref, got)
+
+
+def test_graph_replay_sees_new_data_in_the_same_buffers(ctx):
+    """The captured graph bakes pointers, not data: refill the same tensors with another frame."""
+    import torch
+
+    from paper_1910_12214_amd import tpcca
+
+    w1 = synth.scaled(synth.PBPB_TIMEFRAME, 0.01)
+    w2 = dataclasses.replace(w1, seed=w1.seed + 99)
+    e1, e2 = synth.generate(w1), synth.generate(w2)
+    n = min(e1.n, e2.n)
+    geom = synth.geometry(w1)
+    ten = [dev(a[:n]) for a in (e1.y, e1.z, e1.row, e1.sector)]
+    out = ctx.alloc_tracks(n // 4, n)
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=8))
+    ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True)
+    r1 = tpcca.tracks_to_host(out)
+    for t, a in zip(ten, (e2.y, e2.z, e2.row, e2.sector)):
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a[:n])))
+    torch.cuda.synchronize()
+    for rep in range(3):  # several replays, eager work in between
+        _ = torch.ones(1000, device="cuda:0").sum().item()
+        ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True)
+        r2 = tpcca.tracks_to_host(out)
+        ref = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0)))
+        same(r2, ref)
+    ctx.set_tuning(None)
+    assert r1["counts"][0] != r2["counts"][0] or not np.array_equal(r1["hit_ids"], r2["hit_ids"])
+
+
+def test_full_pbpb_timeframe_sampled_sectors(ctx):
+    """The full 570-collision frame in one graph launch; the oracle checks two whole sectors."""
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.PBPB_TIMEFRAME
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    say(f"[tf] full frame: {ev.n} clusters")
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    out = ctx.alloc_tracks(ev.n // 8, ev.n)
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=8))
+    ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True)
+    ctx.set_tuning(None)
+    trk = tpcca.tracks_to_host(out)
+    st = parity.gpu_stages(ctx, synth.N_ROWS)
+    sectors = [3, 22]
+    sel = np.isin(ev.sector, sectors)
+    ids = np.nonzero(sel)[0]
+    prm = dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0)
+    # the oracle runs on the two sectors only (every step is per sector); map its ids back
+    o = oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, prm, synth.BZ, n_threads=THREADS)
+    o_fma = oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, prm, synth.BZ, n_threads=THREADS,
+                         fma=True)
+    o = lift(o, ids, ev.n)
+    o_fma = lift(o_fma, ids, ev.n)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma)
+    say(f"[tf] full frame sectors {sectors}: {rep.line()}")
+    assert rep["tracks_compared"] > 20000
+
+
+def lift(o, ids, n):
+    """Re-index an oracle result computed on a subset of clusters to the full cluster ids."""
+    ids = ids.astype(np.int64)
+    r = dict(o)
+    for k in ("up", "dn", "up_c", "dn_c"):
+        a = np.full(n, -1, dtype=np.int64)
+        v = o[k].astype(np.int64)
+        a[ids] = np.where(v >= 0, ids[np.maximum(v, 0)], -1)
+        r[k] = a
+    f = np.zeros(n, dtype=np.uint8)
+    f[ids] = o["nb_flag"]
+    r["nb_flag"] = f
+    r["start_id"] = ids[o["start_id"].astype(np.int64)]
+    th = o["tl_hits"].astype(np.int64)
+    r["tl_hits"] = np.where(th >= 0, ids[np.maximum(th, 0)], -1)
+    # hit keys carry the start id: rebuild them with the global ids (the id map is monotonic,
+    # so which tracklet owns a hit does not change)
+    key = np.zeros(n, dtype=np.uint64)
+    for t in np.nonzero(o["tl_valid"])[0]:
+        k = (np.uint64(o["tl_nhits"][t]) << np.uint64(32)) | np.uint64(0xFFFFFFFF - int(r["start_id"][t]))
+        hs = r["tl_hits"][t][r["tl_hits"][t] >= 0]
+        key[hs] = np.maximum(key[hs], k)
+    r["hit_key"] = key
+    r["trk_hits"] = ids[o["trk_hits"].astype(np.int64)]
+    return r
