@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pbpb_event_5000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     return ap.parse_args()
 
@@ -126,6 +127,7 @@ def main():
     t1 = time.perf_counter()
     ctx.profile(False)
     log("timed", args.steps, "steps")
+    timed_done = time.perf_counter()
     stage_ms, n_calls = ctx.profile_read()
     counts = out["counts"].cpu().numpy()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -141,7 +143,7 @@ def main():
     traffic = traffic_from_profile(src, dom, w.name)
     total_alg = sum(ALG_BYTES_PER_CLUSTER.values()) * ev.n
     line = {
-        "metric": "TPC clusters tracked/s on 1 MI355X (plain CA finder)",
+        "metric": "TPC clusters tracked/s on 1 MI355X, plain vs MLP-pruned, at matched efficiency",
         "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
@@ -154,6 +156,39 @@ def main():
                      "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom]},
         "path_roofline_frac": total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
+    # learned pruning (scorer trained on one-sector events; tau from its validation seeds)
+    if not args.no_mlp:
+        from paper_1910_12214_amd import scorer as sc
+        from synth import metrics
+
+        params_mlp, tau = sc.load()
+        mlp = torch.from_numpy(params_mlp).to(dev)
+        out_m = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
+        ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream)
+        for _ in range(args.warmup):
+            ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
+                      sync_check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
+                      sync_check=False)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
+        log("timed pruned")
+        hp = tpcca.tracks_to_host(out)
+        hm = tpcca.tracks_to_host(out_m)
+        mp = metrics.match(ev.leg, np.concatenate([[0], np.cumsum(hp["n_hits"])]), hp["hit_ids"])
+        mm = metrics.match(ev.leg, np.concatenate([[0], np.cumsum(hm["n_hits"])]), hm["hit_ids"])
+        cm = hm["counts"]
+        line["plain"] = {"value": value, "efficiency": mp["efficiency"], "fake_rate": mp["fake_rate"],
+                         "clone_rate": mp["clone_rate"], "tracklets": int(counts[tpcca.CNT_TRACKLETS])}
+        line["mlp_pruned"] = {"value": ev.n / (ms_m * 1e-3), "ms_per_step": ms_m, "tau_logit": tau,
+                              "efficiency": mm["efficiency"], "fake_rate": mm["fake_rate"],
+                              "clone_rate": mm["clone_rate"], "tracklets": int(cm[tpcca.CNT_TRACKLETS]),
+                              "pairs": int(cm[tpcca.CNT_PAIRS]), "pairs_kept": int(cm[tpcca.CNT_PAIRS_KEPT]),
+                              "efficiency_loss": mp["efficiency"] - mm["efficiency"],
+                              "matched": bool(mp["efficiency"] - mm["efficiency"] <= 0.005)}
     if not args.no_cpu_baseline:
         log("cpu baseline")
         cb = cpu_baseline(ev, geom, params, args.cpu_seconds)
