@@ -127,7 +127,6 @@ def main():
     t1 = time.perf_counter()
     ctx.profile(False)
     log("timed", args.steps, "steps")
-    timed_done = time.perf_counter()
     stage_ms, n_calls = ctx.profile_read()
     counts = out["counts"].cpu().numpy()
     ms_step = (t1 - t0) * 1e3 / args.steps
