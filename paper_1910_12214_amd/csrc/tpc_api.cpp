@@ -194,6 +194,7 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
 
 struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *bin_fill, *bin_off, *row_off, *block_cnt, *starts;
+    uint32_t *kidx, *proc;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
     int32_t *up, *dn, *upc, *dnc;
@@ -230,6 +231,8 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(row_off, "row_off", 4 * (S * R + 1));
     B(block_cnt, "block_cnt", 4 * nblk);
     B(starts, "starts", 4 * T);
+    B(kidx, "kidx", 4 * n);
+    B(proc, "proc", 4 * T);
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
     B(hit_off, "hit_off", 4 * T);
@@ -297,19 +300,21 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
     clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
-    compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
+    compact_starts(s.start_flag, s.pos_of, n, s.starts, s.kidx, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
+    order_starts(s.hits, s.start_flag, s.kidx, n, s.counters, s.proc, s.block_cnt, s.scan, st);
     mk.mark();
     // a6 tracklets
-    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.counters, s.tl, tl_blocks, chunk, st);
+    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.counters, s.tl, tl_blocks, chunk, st);
     mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);
-    select_keys(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, T, st);
-    select_own(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag, T, st);
+    select_keys(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, T, st);
+    select_own(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag, T,
+               st);
     scan_u32(s.own_cnt, s.hit_off, T, s.counters + C_N_STARTS, s.counters + C_N_TRACK_HITS, s.scan, st);
     scan_u32(s.trk_flag, s.trk_idx, T, s.counters + C_N_STARTS, s.counters + C_N_TRACKS, s.scan, st);
-    select_write(s.hits, s.starts, s.tl, g, s.counters, s.hit_key, s.own_cnt, s.trk_flag, s.hit_off, s.trk_idx, out,
-                 T, st);
+    select_write(s.hits, s.starts, s.proc, s.tl, g, s.counters, s.hit_key, s.own_cnt, s.trk_flag, s.hit_off,
+                 s.trk_idx, out, T, st);
     finish_counts(s.counters, out.counts, st);
     mk.mark();
     mk.done();

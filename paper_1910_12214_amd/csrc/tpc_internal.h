@@ -62,6 +62,7 @@ enum Counter {  // device scratch counters (uint32)
     C_N_TRACK_HITS,
     C_N_PAIRS_KEPT,
     C_N_VALID_CLU,
+    C_QUEUE_XCD0,  // 8 per-XCD tracklet queues follow
     C_N_COUNTERS = 32
 };
 
@@ -146,8 +147,12 @@ void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, cons
 void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uint32_t* counters, const int32_t* up,
                     const int32_t* dn, int32_t* upc, int32_t* dnc, uint8_t* start_flag, uint32_t* cnt,
                     hipStream_t s);
-void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
+void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts, uint32_t* kidx,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s);
+// processing order: start indices k in grid order (sector, row, bin) of their start hits
+void order_starts(const Hit* hits, const uint8_t* start_flag, const uint32_t* kidx, int64_t n_max,
+                  const uint32_t* counters, uint32_t* proc, uint32_t* block_cnt, void* scan_scratch, hipStream_t s);
+constexpr int kXcd = 8;  // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin
 
 // tracklets.hip
 struct TrackletOut {
@@ -161,17 +166,17 @@ struct TrackletOut {
     uint32_t* flags;     // bit0 valid, bit1 fail
 };
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, uint32_t* counters, const TrackletOut& o,
-                     int grid_blocks, int chunk, hipStream_t s);
+                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
+                     const TrackletOut& o, int grid_blocks, int chunk, hipStream_t s);
 
 // select.hip
-void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
-                 uint64_t* hit_key, int64_t t_max, hipStream_t s);
-void select_own(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, const uint32_t* counters,
-                const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt, uint32_t* trk_flag, int64_t t_max,
-                hipStream_t s);
-void select_write(const Hit* hits, const uint32_t* starts, const TrackletOut& o, const GridDesc& g,
-                  const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
+void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
+                 uint32_t* counters, uint64_t* hit_key, int64_t t_max, hipStream_t s);
+void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
+                const uint32_t* counters, const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt,
+                uint32_t* trk_flag, int64_t t_max, hipStream_t s);
+void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o,
+                  const GridDesc& g, const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
                   const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
                   const tpc_tracks_t& out, int64_t t_max, hipStream_t s);
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s);

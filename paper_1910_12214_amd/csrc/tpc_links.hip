@@ -1,8 +1,8 @@
 // Neighbour finding, cleaning and start-hit selection.
 //
 // Neighbour finding: one lane per grid hit m (row r); the candidates u (row r+1)
-// and d (row r-1) inside the window are enumerated from the row grids (one
-// extra bin on every side, then exact FP64 window tests); the pair with the
+// and d (row r-1) inside the window are enumerated from the row grids (the
+// bins that can hold a window hit, then exact FP64 window tests); the pair with the
 // smallest straight-line deviation D below the cut wins, equal D broken by the
 // smaller (id_u, id_d).  Because lanes of a wave hold consecutive grid hits
 // (same row, neighbouring bins) their candidate loads hit the same cache lines.
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_flag_count(const uint8_t* __restrict
 __global__ __launch_bounds__(kBlock) void k_flag_write(const uint8_t* __restrict__ flag, int64_t n,
                                                        const uint32_t* __restrict__ block_off,
                                                        const uint32_t* __restrict__ pos_of,
-                                                       uint32_t* __restrict__ out) {
+                                                       uint32_t* __restrict__ out, uint32_t* __restrict__ kidx) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool f = i < n && flag[i];
     const uint64_t mask = __ballot(f);
@@ -146,7 +146,48 @@ __global__ __launch_bounds__(kBlock) void k_flag_write(const uint8_t* __restrict
     for (int k = 0; k < w; ++k) off += wc[k];
     if (f) {
         const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;  // mbcnt
-        out[off + (uint32_t)__popcll(below)] = pos_of[i];
+        const uint32_t k = off + (uint32_t)__popcll(below);
+        const uint32_t p = pos_of[i];
+        out[k] = p;
+        kidx[p] = k;
+    }
+}
+
+// The same compaction over grid positions: the processing order of the tracklets.
+__global__ __launch_bounds__(kBlock) void k_pos_count(const Hit* __restrict__ hits, const uint8_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ counters,
+                                                      uint32_t* __restrict__ block_cnt) {
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    const bool f = p < n && flag[hits[p].id];
+    const uint64_t mask = __ballot(f);
+    __shared__ uint32_t wc[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kBlock / 64; ++k) t += wc[k];
+        block_cnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pos_write(const Hit* __restrict__ hits, const uint8_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ counters,
+                                                      const uint32_t* __restrict__ block_off,
+                                                      const uint32_t* __restrict__ kidx, uint32_t* __restrict__ proc) {
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    const bool f = p < n && flag[hits[p].id];
+    const uint64_t mask = __ballot(f);
+    __shared__ uint32_t wc[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wc[w] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t off = block_off[blockIdx.x];
+    for (int k = 0; k < w; ++k) off += wc[k];
+    if (f) {
+        const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+        proc[off + (uint32_t)__popcll(below)] = kidx[p];
     }
 }
 
@@ -168,12 +209,20 @@ void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uin
     k_clean_flag<<<blocks(n_max), kBlock, 0, s>>>(kp, hits, counters, up, dn, upc, dnc, start_flag, cnt);
 }
 
-void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
+void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts, uint32_t* kidx,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s) {
     const unsigned nb = blocks(n);
     k_flag_count<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt);
     scan_u32(block_cnt, block_cnt, nb, nullptr, n_starts_dev, scan_scratch, s);
-    k_flag_write<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt, pos_of, starts);
+    k_flag_write<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt, pos_of, starts, kidx);
+}
+
+void order_starts(const Hit* hits, const uint8_t* start_flag, const uint32_t* kidx, int64_t n_max,
+                  const uint32_t* counters, uint32_t* proc, uint32_t* block_cnt, void* scan_scratch, hipStream_t s) {
+    const unsigned nb = blocks(n_max);
+    k_pos_count<<<nb, kBlock, 0, s>>>(hits, start_flag, counters, block_cnt);
+    scan_u32(block_cnt, block_cnt, nb, nullptr, nullptr, scan_scratch, s);
+    k_pos_write<<<nb, kBlock, 0, s>>>(hits, start_flag, counters, block_cnt, kidx, proc);
 }
 
 }  // namespace tpc

@@ -19,11 +19,27 @@ __device__ inline uint64_t tl_key(uint32_t nh, uint32_t start_id) {
     return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - start_id);
 }
 
+// Walk of the processing order restricted to this workgroup's XCD slice (the same
+// slices the tracklet kernel drained, so the hits are still in that XCD's L2).
+struct SliceWalk {
+    uint32_t j, hi, step;
+    __device__ SliceWalk(uint32_t n) {
+        const uint32_t x = blockIdx.x % kXcd, per = gridDim.x / kXcd, b = blockIdx.x / kXcd;
+        const uint32_t lo = (uint32_t)((uint64_t)n * x / kXcd);
+        hi = (uint32_t)((uint64_t)n * (x + 1) / kXcd);
+        j = lo + b * blockDim.x + threadIdx.x;
+        step = per * blockDim.x;
+    }
+    __device__ bool ok() const { return j < hi; }
+    __device__ void next() { j += step; }
+};
+
 __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
-                                                 TrackletOut o, int R, const uint32_t* __restrict__ counters,
-                                                 uint64_t* __restrict__ hit_key) {
+                                                 const uint32_t* __restrict__ proc, TrackletOut o, int R,
+                                                 const uint32_t* __restrict__ counters, uint64_t* __restrict__ hit_key) {
     const uint32_t n = counters[C_N_STARTS];
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+    for (SliceWalk w(n); w.ok(); w.next()) {
+        const uint32_t k = proc[w.j];
         if (!(o.flags[k] & 1u)) continue;
         const uint32_t nh = (uint32_t)o.nhits[k];
         const uint64_t key = tl_key(nh, hits[starts[k]].id);
@@ -37,11 +53,13 @@ __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, c
 }
 
 __global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
-                                                TrackletOut o, int R, const uint32_t* __restrict__ counters,
+                                                const uint32_t* __restrict__ proc, TrackletOut o, int R,
+                                                const uint32_t* __restrict__ counters,
                                                 const uint64_t* __restrict__ hit_key, int n_min_trk,
                                                 uint32_t* __restrict__ own_cnt, uint32_t* __restrict__ trk_flag) {
     const uint32_t n = counters[C_N_STARTS];
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+    for (SliceWalk w(n); w.ok(); w.next()) {
+        const uint32_t k = proc[w.j];
         uint32_t owned = 0;
         if (o.flags[k] & 1u) {
             const uint32_t nh = (uint32_t)o.nhits[k];
@@ -56,14 +74,16 @@ __global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, co
 }
 
 __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
-                                                  TrackletOut o, GridDesc g, const uint32_t* __restrict__ counters,
+                                                  const uint32_t* __restrict__ proc, TrackletOut o, GridDesc g,
+                                                  const uint32_t* __restrict__ counters,
                                                   const uint64_t* __restrict__ hit_key,
                                                   const uint32_t* __restrict__ own_cnt,
                                                   const uint32_t* __restrict__ hit_off,
                                                   const uint32_t* __restrict__ trk_idx, tpc_tracks_t out) {
     const uint32_t n = counters[C_N_STARTS];
     const int R = g.R;
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+    for (SliceWalk w(n); w.ok(); w.next()) {
+        const uint32_t k = proc[w.j];
         const uint32_t cnt = own_cnt[k];
         if (!cnt) continue;
         const uint32_t t = trk_idx[k], off = hit_off[k];
@@ -72,10 +92,10 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
         const Hit hs = hits[starts[k]];
         const uint64_t key = tl_key(nh, hs.id);
         const int32_t* slot = o.hits + (size_t)k * R;
-        uint32_t w = off;
+        uint32_t wr = off;
         for (int j = R - (int)nh; j < R; ++j) {
             const int32_t pos = slot[j];
-            if (hit_key[pos] == key) out.hit_ids[w++] = (int32_t)hits[pos].id;
+            if (hit_key[pos] == key) out.hit_ids[wr++] = (int32_t)hits[pos].id;
         }
         out.hit_offset[t] = (int32_t)off;
         out.n_hits[t] = (int32_t)cnt;
@@ -107,31 +127,32 @@ __global__ void k_finish(const uint32_t* __restrict__ c, int32_t* __restrict__ o
 
 inline unsigned sel_blocks(int64_t t_max) {
     int64_t b = (t_max + kBlock - 1) / kBlock;
-    if (b < 1) b = 1;
     if (b > 4096) b = 4096;
-    return (unsigned)b;
+    b = (b + kXcd - 1) / kXcd * kXcd;  // whole rounds over the XCDs
+    return (unsigned)(b < kXcd ? kXcd : b);
 }
 
 }  // namespace
 
-void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
-                 uint64_t* hit_key, int64_t t_max, hipStream_t s) {
-    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, R, counters, hit_key);
+void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
+                 uint32_t* counters, uint64_t* hit_key, int64_t t_max, hipStream_t s) {
+    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, R, counters, hit_key);
 }
 
-void select_own(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, const uint32_t* counters,
-                const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt, uint32_t* trk_flag, int64_t t_max,
-                hipStream_t s) {
-    k_own<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, R, counters, hit_key, n_min_trk, own_cnt, trk_flag);
+void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
+                const uint32_t* counters, const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt,
+                uint32_t* trk_flag, int64_t t_max, hipStream_t s) {
+    k_own<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, R, counters, hit_key, n_min_trk, own_cnt,
+                                               trk_flag);
 }
 
-void select_write(const Hit* hits, const uint32_t* starts, const TrackletOut& o, const GridDesc& g,
-                  const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
+void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o,
+                  const GridDesc& g, const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
                   const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
                   const tpc_tracks_t& out, int64_t t_max, hipStream_t s) {
     (void)trk_flag;
-    k_write<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, o, g, counters, hit_key, own_cnt, hit_off, trk_idx,
-                                                 out);
+    k_write<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, g, counters, hit_key, own_cnt, hit_off,
+                                                 trk_idx, out);
 }
 
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s) {

@@ -378,40 +378,61 @@ constexpr int kTlBlock = 128;
 // queue at once (one atomic per wave for all idle lanes), so long and short
 // tracklets share a wave without idling it.  `chunk` scales how many queue
 // entries an idle lane reserves at a time (1 = one tracklet).
+//
+// The queue runs over the processing order `proc` (tracklets sorted by the grid
+// position of their start hit: sector, row, z bin), split into one contiguous
+// slice per XCD.  Workgroup b is dispatched to XCD b mod 8, drains that XCD's
+// slice first and then steals from the others, so each XCD's L2 holds the hits
+// of a few sectors and z ranges instead of the whole event.
 __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, const Hit* __restrict__ hits,
                                                         const uint32_t* __restrict__ bin_off,
                                                         const int32_t* __restrict__ upc,
                                                         const uint32_t* __restrict__ starts,
+                                                        const uint32_t* __restrict__ proc,
                                                         uint32_t* __restrict__ counters, TrackletOut o, int chunk) {
     const uint32_t n = counters[C_N_STARTS];
     const int lane = threadIdx.x & 63;
+    const int xcd = blockIdx.x % kXcd;
     uint32_t n_valid = 0, n_fail = 0;
     Lane L;
     L.phase = 0;
-    uint32_t res_next = 0, res_end = 0;  // this lane's reserved queue range
+    uint32_t res_next = 0, res_end = 0;  // this lane's reserved range of the processing order
+    int cur = 0;                         // slices this wave has found empty (wave-uniform)
     while (true) {
         // refill lanes without work
-        if (L.phase == 0 && res_next < res_end) {
-            start_pass_a(L, res_next++, g, kp, hits, upc, starts, o);
-        }
+        if (L.phase == 0 && res_next < res_end) start_pass_a(L, proc[res_next++], g, kp, hits, upc, starts, o);
         const uint64_t need = __ballot(L.phase == 0);
         if (need) {
             const uint32_t cnt = (uint32_t)__popcll(need) * (uint32_t)chunk;
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&counters[C_QUEUE_TL], cnt);
-            base = __shfl(base, 0, 64);
+            uint32_t lo = 0, hi = 0, base = 0;
+            bool got = false;
+            while (cur < kXcd) {
+                const int x = (xcd + cur) % kXcd;
+                lo = (uint32_t)((uint64_t)n * x / kXcd);
+                hi = (uint32_t)((uint64_t)n * (x + 1) / kXcd);
+                uint32_t b = 0;
+                if (lane == 0) b = atomicAdd(&counters[C_QUEUE_XCD0 + x], cnt);
+                base = __shfl(b, 0, 64);
+                if (lo + base < hi) {
+                    got = true;
+                    break;
+                }
+                ++cur;
+            }
             if (L.phase == 0) {
-                const uint64_t below = lane ? (need & (~0ull >> (64 - lane))) : 0ull;
-                const uint32_t mine = base + (uint32_t)__popcll(below) * (uint32_t)chunk;
-                res_next = mine;
-                res_end = mine + (uint32_t)chunk < n ? mine + (uint32_t)chunk : n;
-                if (res_next < res_end)
-                    start_pass_a(L, res_next++, g, kp, hits, upc, starts, o);
-                else
+                if (got) {
+                    const uint64_t below = lane ? (need & (~0ull >> (64 - lane))) : 0ull;
+                    const uint32_t mine = lo + base + (uint32_t)__popcll(below) * (uint32_t)chunk;
+                    res_next = mine;
+                    res_end = mine + (uint32_t)chunk < hi ? mine + (uint32_t)chunk : hi;
+                }
+                if (got && res_next < res_end)
+                    start_pass_a(L, proc[res_next++], g, kp, hits, upc, starts, o);
+                else if (!got)
                     L.phase = 3;
             }
         }
-        if (!__ballot(L.phase == 1 || L.phase == 2)) break;
+    if (!__ballot(L.phase == 1 || L.phase == 2)) break;
         if (L.phase == 1) {
             if (step_a(L, g, kp, hits, bin_off, upc, o)) {
                 if (L.fail) {
@@ -451,9 +472,10 @@ __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, 
 }  // namespace
 
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, uint32_t* counters, const TrackletOut& o,
-                     int grid_blocks, int chunk, hipStream_t s) {
-    k_tracklets<<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, counters, o, chunk);
+                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
+                     const TrackletOut& o, int grid_blocks, int chunk, hipStream_t s) {
+    grid_blocks = (grid_blocks + kXcd - 1) / kXcd * kXcd;
+    k_tracklets<<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
 }
 
 }  // namespace tpc
