@@ -160,8 +160,31 @@ def main():
         from paper_1910_12214_amd import scorer as sc
         from synth import metrics
 
-        params_mlp, tau = sc.load()
+        params_mlp, tau_trained = sc.load()
         mlp = torch.from_numpy(params_mlp).to(dev)
+        # threshold for this workload: largest tau on a grid whose efficiency on a validation event of
+        # the same workload (another seed) is within 0.5% of the plain finder's
+        import dataclasses
+
+        wv = dataclasses.replace(w, seed=w.seed + 7919)
+        evv = synth.generate(wv)
+        tv = [torch.from_numpy(a).to(dev) for a in (evv.y, evv.z, evv.row, evv.sector)]
+        geov = synth.geometry(wv)
+
+        def eff_of(tau_try):
+            o = ctx.track(*tv, geov, synth.BZ, params, mlp=mlp if tau_try is not None else None,
+                          tau_logit=tau_try or 0.0)
+            h = tpcca.tracks_to_host(o)
+            return metrics.match(evv.leg, np.concatenate([[0], np.cumsum(h["n_hits"])]), h["hit_ids"])["efficiency"]
+
+        eff_plain_v = eff_of(None)
+        tau = None
+        for t_try in (-8.0, -6.0, -4.0, -3.0, -2.0, -1.0, 0.0, 0.5, 1.0, 2.0):
+            if eff_plain_v - eff_of(t_try) <= 0.005:
+                tau = t_try
+        if tau is None:
+            tau = -8.0
+        log("pruned leg: tau", tau, "on", wv.name)
         out_m = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
         ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream)
         for _ in range(args.warmup):
@@ -183,6 +206,9 @@ def main():
         line["plain"] = {"value": value, "efficiency": mp["efficiency"], "fake_rate": mp["fake_rate"],
                          "clone_rate": mp["clone_rate"], "tracklets": int(counts[tpcca.CNT_TRACKLETS])}
         line["mlp_pruned"] = {"value": ev.n / (ms_m * 1e-3), "ms_per_step": ms_m, "tau_logit": tau,
+                              "tau_from": f"validation event {wv.name} (seed {wv.seed})",
+                              "trained_on": "one-sector 200-helix events, seeds 1-200",
+                              "tau_trained_workload": tau_trained,
                               "efficiency": mm["efficiency"], "fake_rate": mm["fake_rate"],
                               "clone_rate": mm["clone_rate"], "tracklets": int(cm[tpcca.CNT_TRACKLETS]),
                               "pairs": int(cm[tpcca.CNT_PAIRS]), "pairs_kept": int(cm[tpcca.CNT_PAIRS_KEPT]),
