@@ -132,6 +132,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = ev.n / (ms_step * 1e-3)
     per_stage = {k: v / max(1, n_calls) for k, v in stage_ms.items()}
+    tuning = ctx.tuning() if tf else None
     dom = max(per_stage, key=per_stage.get)
     alg_bytes = ALG_BYTES_PER_CLUSTER[dom] * ev.n
     achieved = alg_bytes / (per_stage[dom] * 1e-3) / 1e9
@@ -150,6 +151,7 @@ def main():
                    "tracklets": int(counts[tpcca.CNT_TRACKLETS]), "input_sha256": ev.sha256()[:16],
                    "bin_cm": [params["bin_y"], params["bin_z"]]},
         "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
+        "tiles": tuning,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom]},

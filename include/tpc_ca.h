@@ -148,6 +148,7 @@ typedef struct {
     float bin_y, bin_z;
     int32_t tracklet_chunk;  /* tracklets taken per queue pop (per wave) */
     int32_t blocks_per_cu;   /* persistent grid size / number of CUs */
+    int32_t waves_per_simd;  /* tracklet kernel occupancy variant: 2 (no spills), 3 or 4 */
     float best_ms;           /* autotune measurement of the chosen candidate */
     int32_t n_candidates;
 } tpc_tuning_t;

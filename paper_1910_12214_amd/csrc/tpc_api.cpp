@@ -286,7 +286,7 @@ void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s
 }
 
 void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
-                   const tpc_tracks_t& out, const float* mlp_q, int tl_blocks, int chunk, hipStream_t st) {
+                   const tpc_tracks_t& out, const float* mlp_q, int tl_blocks, int chunk, int waves, hipStream_t st) {
     const int64_t n = pr.n, T = pr.t_max;
     const GridDesc& g = pr.g;
     Marks mk{c, st, {}};
@@ -304,7 +304,8 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     order_starts(s.hits, s.start_flag, s.kidx, n, s.counters, s.proc, s.block_cnt, s.scan, st);
     mk.mark();
     // a6 tracklets
-    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.counters, s.tl, tl_blocks, chunk, st);
+    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.counters, s.tl, tl_blocks, chunk, waves,
+                    st);
     mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);
@@ -411,7 +412,7 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
         if (!q) return TPC_ERR_HIP;
         mlp_quantize(p->mlp, q, st);
     }
-    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * 8, 1, st);
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * 4, 1, 2, st);
     TPC_HIP(c, hipGetLastError());
     c->last_n = pr.n;
     c->last_R = pr.g.R;
@@ -446,12 +447,12 @@ int timed_run(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo,
     }
     const bool prof = c->prof_on;
     c->prof_on = false;
-    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, st);  // warm (sizes, caches)
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, t.waves, st);  // warm (sizes, caches)
     hipEvent_t e0, e1;
     TPC_HIP(c, hipEventCreate(&e0));
     TPC_HIP(c, hipEventCreate(&e1));
     TPC_HIP(c, hipEventRecord(e0, st));
-    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, st);
+    enqueue_chain(c, *cl, pr, s, *out, q, c->n_cu * t.blocks_per_cu, t.chunk, t.waves, st);
     TPC_HIP(c, hipEventRecord(e1, st));
     TPC_HIP(c, hipEventSynchronize(e1));
     TPC_HIP(c, hipEventElapsedTime(ms, e0, e1));
@@ -462,12 +463,14 @@ int timed_run(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo,
     return TPC_OK;
 }
 
-// Two-stage search: grid bin size first, then queue chunk x persistent blocks per CU.
+// Two-stage search: grid bin size first (default tracklet tiles), then the tracklet
+// kernel's occupancy variant x queue chunk; persistent blocks per CU follow the
+// occupancy (two waves per block: 2 x waves per SIMD).
 int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
              tpc_tracks_t* out, hipStream_t st) {
     static const float bins[][2] = {{8.f, 8.f}, {8.f, 16.f}, {12.f, 24.f}, {16.f, 32.f}};
     static const int chunks[] = {1, 2, 4};
-    static const int bpcs[] = {4, 8, 16};
+    static const int wavess[] = {2, 3, 4};
     Tuning best;
     best.best_ms = 1e30f;
     int n = 0, rc;
@@ -476,7 +479,8 @@ int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, 
         t.bin_y = b[0];
         t.bin_z = b[1];
         t.chunk = 1;
-        t.blocks_per_cu = 8;
+        t.waves = 2;
+        t.blocks_per_cu = 4;
         float ms = 0.f;
         if ((rc = timed_run(c, cl, geo, bz, p, out, st, t, &ms))) return rc;
         ++n;
@@ -486,12 +490,13 @@ int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, 
         }
     }
     const Tuning base = best;
-    for (int ch : chunks)
-        for (int bp : bpcs) {
-            if (ch == base.chunk && bp == base.blocks_per_cu) continue;
+    for (int w : wavess)
+        for (int ch : chunks) {
+            if (ch == base.chunk && w == base.waves) continue;
             Tuning t = base;
             t.chunk = ch;
-            t.blocks_per_cu = bp;
+            t.waves = w;
+            t.blocks_per_cu = 2 * w;
             float ms = 0.f;
             if ((rc = timed_run(c, cl, geo, bz, p, out, st, t, &ms))) return rc;
             ++n;
@@ -550,7 +555,7 @@ int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geomet
     c->last_n_starts_cap = pr.t_max;
     if (c->prof_on) {  // stage timing needs eager launches
         if (q) mlp_quantize(p->mlp, q, st);
-        enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, st);
+        enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, t.waves, st);
         TPC_HIP(c, hipGetLastError());
     } else {
         // every kernel argument is part of the key: a replay runs exactly the captured chain
@@ -571,7 +576,7 @@ int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geomet
             GraphEntry ge;
             TPC_HIP(c, hipStreamBeginCapture(c->own_stream, hipStreamCaptureModeThreadLocal));
             if (q) mlp_quantize(p->mlp, q, c->own_stream);
-            enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, c->own_stream);
+            enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, t.waves, c->own_stream);
             TPC_HIP(c, hipStreamEndCapture(c->own_stream, &ge.graph));
             TPC_HIP(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
             it = c->graphs.emplace(key, ge).first;
@@ -589,6 +594,7 @@ int tpc_timeframe_tuning(tpc_ctx_t* c, tpc_tuning_t* o) {
     o->bin_z = c->tuning.bin_z;
     o->tracklet_chunk = c->tuning.chunk;
     o->blocks_per_cu = c->tuning.blocks_per_cu;
+    o->waves_per_simd = c->tuning.waves;
     o->best_ms = c->tuning.best_ms;
     o->n_candidates = c->tuning.n_candidates;
     return TPC_OK;
@@ -602,12 +608,13 @@ int tpc_timeframe_set_tuning(tpc_ctx_t* c, const tpc_tuning_t* t) {
         return TPC_OK;
     }
     if (!(t->bin_y > 0.f) || !(t->bin_z > 0.f) || t->tracklet_chunk < 1 || t->tracklet_chunk > 64 ||
-        t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
+        t->blocks_per_cu < 1 || t->blocks_per_cu > 64 || t->waves_per_simd < 2 || t->waves_per_simd > 4)
         return fail(c, TPC_ERR_ARG, "bad tiles");
     c->tuning.bin_y = t->bin_y;
     c->tuning.bin_z = t->bin_z;
     c->tuning.chunk = t->tracklet_chunk;
     c->tuning.blocks_per_cu = t->blocks_per_cu;
+    c->tuning.waves = t->waves_per_simd;
     c->tuning.best_ms = 0.f;
     c->tuning.n_candidates = 0;
     c->tune_forced = true;

@@ -68,8 +68,9 @@ enum Counter {  // device scratch counters (uint32)
 
 struct Tuning {
     float bin_y = 8.f, bin_z = 8.f;
-    int chunk = 1;         // queue pops of 64 tracklets per wave
+    int chunk = 1;         // tracklets an idle lane reserves per queue pop
     int blocks_per_cu = 8;
+    int waves = 2;         // tracklet kernel occupancy variant (waves per SIMD)
     float best_ms = 0.f;
     int n_candidates = 0;
 };
@@ -167,7 +168,7 @@ struct TrackletOut {
 };
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
                      const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
-                     const TrackletOut& o, int grid_blocks, int chunk, hipStream_t s);
+                     const TrackletOut& o, int grid_blocks, int chunk, int waves, hipStream_t s);
 
 // select.hip
 void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,

@@ -178,22 +178,35 @@ __device__ inline void c0_init(double C[15], const KParams& kp) {
 }
 
 // Per-lane tracklet state between row steps.
+// Rarely touched per-lane values live in LDS, not registers: pass A's direction
+// and curvature at its outermost hit, and pass B's state at its innermost hit.
+struct Spare {
+    double pl[3];
+    float pin[5], cin[15];
+};
+
 struct Lane {
     int phase;  // 0 needs work, 1 pass A, 2 pass B, 3 retired
     uint32_t k;
     int s, r0, r, last, inner, nA, nB, ia, miss, ndf;
     int32_t next;
     bool on, fail;
-    double x, chi2, pl2, pl3, pl4;
+    double x, chi2;
     double p[5], C[15];
-    float pin[5], cin[15];
+    Spare* sp;
 };
 
 __device__ inline void save_inner(Lane& L) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) L.pin[i] = (float)L.p[i];
+    for (int i = 0; i < 5; ++i) L.sp->pin[i] = (float)L.p[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) L.cin[i] = (float)L.C[i];
+    for (int i = 0; i < 15; ++i) L.sp->cin[i] = (float)L.C[i];
+}
+
+__device__ inline void save_dir(Lane& L) {
+    L.sp->pl[0] = L.p[2];
+    L.sp->pl[1] = L.p[3];
+    L.sp->pl[2] = L.p[4];
 }
 
 __device__ inline void start_pass_a(Lane& L, uint32_t k, const GridDesc& g, const KParams& kp,
@@ -219,9 +232,7 @@ __device__ inline void start_pass_a(Lane& L, uint32_t k, const GridDesc& g, cons
     o.hits[(size_t)k * R] = (int32_t)p0;
     L.nA = 1;
     L.last = L.r0;
-    L.pl2 = L.p[2];
-    L.pl3 = L.p[3];
-    L.pl4 = L.p[4];
+    save_dir(L);
     L.next = p1;
     L.on = true;
     L.fail = false;
@@ -239,9 +250,9 @@ __device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& k
     const Hit hb = hits[pb];
     L.p[0] = hb.y;
     L.p[1] = hb.z;
-    L.p[2] = L.pl2;
-    L.p[3] = L.pl3;
-    L.p[4] = L.pl4;
+    L.p[2] = L.sp->pl[0];
+    L.p[3] = L.sp->pl[1];
+    L.p[4] = L.sp->pl[2];
     c0_init(L.C, kp);
     slot[R - 1] = pb;
     L.nB = 1;
@@ -268,9 +279,9 @@ __device__ inline uint32_t finish(Lane& L, const KParams& kp, const TrackletOut&
     o.row_ref[k] = L.phase == 2 ? L.inner : L.last;
     o.flags[k] = (valid ? 1u : 0u) | (fail ? 2u : 0u);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) o.state[(size_t)k * 5 + i] = fail ? 0.f : L.pin[i];
+    for (int i = 0; i < 5; ++i) o.state[(size_t)k * 5 + i] = fail ? 0.f : L.sp->pin[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) o.cov[(size_t)k * 15 + i] = fail ? 0.f : L.cin[i];
+    for (int i = 0; i < 15; ++i) o.cov[(size_t)k * 15 + i] = fail ? 0.f : L.sp->cin[i];
     L.phase = 0;
     return (valid ? 1u : 0u) | (fail ? 2u : 0u);
 }
@@ -316,9 +327,7 @@ __device__ inline bool step_a(Lane& L, const GridDesc& g, const KParams& kp, con
         o.hits[(size_t)L.k * R + L.nA] = acc;
         ++L.nA;
         L.last = r;
-        L.pl2 = L.p[2];
-        L.pl3 = L.p[3];
-        L.pl4 = L.p[4];
+        save_dir(L);
         L.miss = 0;
         return false;
     }
@@ -384,7 +393,9 @@ constexpr int kTlBlock = 128;
 // slice per XCD.  Workgroup b is dispatched to XCD b mod 8, drains that XCD's
 // slice first and then steals from the others, so each XCD's L2 holds the hits
 // of a few sectors and z ranges instead of the whole event.
-__global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+template <int WAVES>
+__global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES))) void k_tracklets(
+    GridDesc g, KParams kp, const Hit* __restrict__ hits,
                                                         const uint32_t* __restrict__ bin_off,
                                                         const int32_t* __restrict__ upc,
                                                         const uint32_t* __restrict__ starts,
@@ -394,8 +405,10 @@ __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, 
     const int lane = threadIdx.x & 63;
     const int xcd = blockIdx.x % kXcd;
     uint32_t n_valid = 0, n_fail = 0;
+    __shared__ Spare spare[kTlBlock];
     Lane L;
     L.phase = 0;
+    L.sp = &spare[threadIdx.x];
     uint32_t res_next = 0, res_end = 0;  // this lane's reserved range of the processing order
     int cur = 0;                         // slices this wave has found empty (wave-uniform)
     while (true) {
@@ -473,9 +486,15 @@ __global__ __launch_bounds__(kTlBlock) void k_tracklets(GridDesc g, KParams kp, 
 
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
                      const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
-                     const TrackletOut& o, int grid_blocks, int chunk, hipStream_t s) {
+                     const TrackletOut& o, int grid_blocks, int chunk, int waves, hipStream_t s) {
     grid_blocks = (grid_blocks + kXcd - 1) / kXcd * kXcd;
-    k_tracklets<<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+    // occupancy variants: 2 waves per SIMD keeps the whole state in registers, 3 and 4 spill some of it
+    if (waves >= 4)
+        k_tracklets<4><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+    else if (waves == 3)
+        k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+    else
+        k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
 }
 
 }  // namespace tpc

@@ -52,7 +52,8 @@ class Tracks(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("tracklet_chunk", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("best_ms", ctypes.c_float), ("n_candidates", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("best_ms", ctypes.c_float),
+                ("n_candidates", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):
@@ -273,6 +274,7 @@ class Context:
             self._check(self.lib.tpc_timeframe_set_tuning(self.h, None))
             return
         t = Tuning()
+        t.waves_per_simd = 2
         for k, v in tiles.items():
             setattr(t, k, v)
         self._check(self.lib.tpc_timeframe_set_tuning(self.h, ctypes.byref(t)))

@@ -69,8 +69,8 @@ def test_timeframe_equals_sector_path(ctx, small_tf):
 
 
 @pytest.mark.parametrize("tiles", [dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=4),
-                                   dict(bin_y=16.0, bin_z=32.0, tracklet_chunk=4, blocks_per_cu=16),
-                                   dict(bin_y=5.0, bin_z=11.0, tracklet_chunk=2, blocks_per_cu=1)])
+                                   dict(bin_y=16.0, bin_z=32.0, tracklet_chunk=4, blocks_per_cu=8, waves_per_simd=4),
+                                   dict(bin_y=5.0, bin_z=11.0, tracklet_chunk=2, blocks_per_cu=1, waves_per_simd=3)])
 def test_every_tile_choice_gives_identical_tracks(ctx, small_tf, tiles):
     from paper_1910_12214_amd import tpcca
 
