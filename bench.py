@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--workload", default="pbpb_event_5000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
+    ap.add_argument("--sector-path", action="store_true", help="time frames through tpc_track_sectors")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     return ap.parse_args()
 
@@ -113,20 +114,32 @@ def main():
     ctx = tpcca.Context(0)
     out = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
     stream = torch.cuda.current_stream()
-    ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=True)  # sizes scratch
+    # time frames go through the time-frame entry point (autotuned tiles, one graph launch per frame)
+    tf = w.t_frame_us > 0 and not args.sector_path
+
+    def step(**kw):
+        return ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, timeframe=tf, **kw)
+
+    step(sync_check=True)  # sizes scratch (and tunes the time-frame tiles)
     log("warmup")
     for _ in range(args.warmup):
-        ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=False)
+        step(sync_check=False)
     torch.cuda.synchronize()
-    ctx.profile(True)
+    if not tf:
+        ctx.profile(True)  # stage events recorded inside the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, sync_check=False)
+        step(sync_check=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.profile(False)
     log("timed", args.steps, "steps")
+    if tf:  # graph replays cannot carry timing events: time the steps in an eager pass
+        ctx.profile(True)
+        for _ in range(args.steps):
+            step(sync_check=False)
+        torch.cuda.synchronize()
+    ctx.profile(False)
     stage_ms, n_calls = ctx.profile_read()
     counts = out["counts"].cpu().numpy()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -149,7 +162,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "clusters": ev.n, "tracks": int(counts[tpcca.CNT_TRACKS]),
                    "tracklets": int(counts[tpcca.CNT_TRACKLETS]), "input_sha256": ev.sha256()[:16],
-                   "bin_cm": [params["bin_y"], params["bin_z"]]},
+                   "bin_cm": [params["bin_y"], params["bin_z"]],
+                   "entry": "tpc_track_timeframe" if tf else "tpc_track_sectors"},
         "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
         "tiles": tuning,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
