@@ -248,3 +248,31 @@ def test_invalid_rows_and_sectors_are_ignored():
     sector = np.array([0, 0, 5], dtype=np.uint8)
     res = oracle.track(y, z, row, sector, geom(n_sectors=2), P, synth.BZ)
     assert res["n_valid"] == 1 and res["n_tracks"] == 0
+
+
+def test_oracle_thread_count_does_not_change_results(pbpb_small):
+    w, ev = pbpb_small
+    a = oracle.track(ev.y, ev.z, ev.row, ev.sector, synth.geometry(w), P, synth.BZ, n_threads=1)
+    b = oracle.track(ev.y, ev.z, ev.row, ev.sector, synth.geometry(w), P, synth.BZ, n_threads=7)
+    for k in ("up", "dn", "nb_flag", "start_id", "tl_hits", "tl_state", "tl_cov", "tl_flag", "hit_key", "trk_hits"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_input_order_only_relabels_ids():
+    """A seeded permutation of the input changes cluster ids (and so id tie-breaks) but, away from
+    flagged near-ties, not which clusters form a track."""
+    w = synth.scaled(synth.PBPB_EVENT, 0.05)
+    a_ev = synth.generate(w)
+    b_ev = synth.generate(dataclasses.replace(w, order=1))
+    geom = synth.geometry(w)
+    a = oracle.track(a_ev.y, a_ev.z, a_ev.row, a_ev.sector, geom, P, synth.BZ, n_threads=4)
+    b = oracle.track(b_ev.y, b_ev.z, b_ev.row, b_ev.sector, geom, P, synth.BZ, n_threads=4)
+
+    def track_sets(ev, r):
+        key = ev.particle.astype(np.int64) * 1000 + ev.crossing  # identity of a cluster across orders
+        key[ev.particle < 0] = -1 - np.arange((ev.particle < 0).sum())
+        return {tuple(sorted(key[r["trk_hits"][r["trk_off"][k]:r["trk_off"][k + 1]]].tolist()))
+                for k in range(r["n_tracks"])}
+
+    sa, sb = track_sets(a_ev, a), track_sets(b_ev, b)
+    assert len(sa ^ sb) <= 0.01 * len(sa), len(sa ^ sb)
