@@ -168,3 +168,30 @@ def lift(o, ids, n):
     r["hit_key"] = key
     r["trk_hits"] = ids[o["trk_hits"].astype(np.int64)]
     return r
+
+
+def test_pp_timeframe_with_fused_scorer_equals_sector_path(ctx):
+    """pp time frame (many tiny collisions, 10% noise) with the trained scorer fused into neighbour
+    finding, through the graph path, equals the per-sector path with the same scorer."""
+    from paper_1910_12214_amd import scorer as sc
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.scaled(synth.PP_TIMEFRAME, 0.1)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    params, tau = sc.load()
+    mlp = dev(params)
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=2, blocks_per_cu=6, waves_per_simd=3))
+    a = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, mlp=mlp, tau_logit=tau,
+                                       timeframe=True))
+    a2 = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, mlp=mlp, tau_logit=tau,
+                                        timeframe=True))  # graph replay
+    ctx.set_tuning(None)
+    b = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0),
+                                       mlp=mlp, tau_logit=tau))
+    same(a, b)
+    same(a2, b)
+    c = a["counts"]
+    say(f"[tf] pp frame {ev.n} clusters: pairs {c[tpcca.CNT_PAIRS]} kept {c[tpcca.CNT_PAIRS_KEPT]} tracks {c[0]}")
+    assert c[tpcca.CNT_PAIRS_KEPT] < c[tpcca.CNT_PAIRS]
