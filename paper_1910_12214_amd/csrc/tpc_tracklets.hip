@@ -30,11 +30,45 @@ namespace tpc {
 
 namespace {
 
+// 1/x from the hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r(1 - x r)); each step squares the relative error, so the result is
+// within an ulp or two of the rounded quotient.  x = 0 gives NaN; every caller's
+// divisor is positive (c = cos phi > 0, B > 0, L != 0, det > 0 or rejected by the
+// caller's own det > 0 test).
+__device__ inline double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(x) for x >= 0 by Goldschmidt's iteration on the hardware 1/sqrt estimate
+// (s ~ sqrt(x), h ~ 1/(2 sqrt(x)) refined together), then two Newton corrections
+// of s from the residual x - s^2.
+__device__ inline double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double e = fma(-s, h, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    double d = fma(-s, s, x);
+    s = fma(d, h, s);
+    d = fma(-s, s, x);
+    s = fma(d, h, s);
+    return x == 0.0 ? 0.0 : s;
+}
+
+// g(u) = asin(u)/u and g'(u).  Row steps keep |u| = |k L / 2| well below 0.05
+// (0.02 for the lowest momenta), where the Maclaurin series of asin(u)/u to u^12
+// is exact to rounding (the first omitted term is below 1e-18 relative).
 __device__ inline void asin_over(double u, double& g, double& gp) {
-    if (fabs(u) < 1e-2) {
+    if (fabs(u) < 0.05) {
         const double u2 = u * u;
-        g = 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0 + u2 * (35.0 / 1152.0))));
-        gp = u * (1.0 / 3.0 + u2 * (3.0 / 10.0 + u2 * (15.0 / 56.0 + u2 * (35.0 / 144.0))));
+        g = 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0 + u2 * (35.0 / 1152.0 +
+            u2 * (63.0 / 2816.0 + u2 * (231.0 / 13312.0))))));
+        gp = u * (1.0 / 3.0 + u2 * (3.0 / 10.0 + u2 * (15.0 / 56.0 + u2 * (35.0 / 144.0 +
+             u2 * (315.0 / 1408.0 + u2 * (693.0 / 3328.0 + u2 * (1001.0 / 5120.0)))))));
     } else {
         const double a = asin(u);
         g = a / u;
@@ -52,21 +86,24 @@ __device__ inline bool propagate(double p[5], double C[15], double x0, double x1
     const double s0 = p[2], s1 = s0 + k * dx;
     if (!(fabs(s1) < kp.s_max) || !(fabs(s0) < kp.s_max)) return false;
     if (dx == 0.0) return true;
-    const double c0 = sqrt(1.0 - s0 * s0), c1 = sqrt(1.0 - s1 * s1);
+    const double c0 = sqrt_pos(1.0 - s0 * s0), c1 = sqrt_pos(1.0 - s1 * s1);
     const double A = s0 + s1, B = c0 + c1;
-    const double dy = dx * A / B;
-    const double L = copysign(sqrt(dx * dx + dy * dy), dx);
+    const double iB = rcp(B);
+    const double dy = dx * A * iB;
+    const double L = copysign(sqrt_pos(dx * dx + dy * dy), dx);
     const double u = 0.5 * k * L;
     double g, gp;
     asin_over(u, g, gp);
     const double arc = L * g;
     const double t = p[3];
     // Jacobian: F = I + {(0,2)=a, (0,4)=b, (1,2)=c, (1,3)=d, (1,4)=e, (2,4)=f}
-    const double iB2 = 1.0 / (B * B);
-    const double dB_s = -s0 / c0 - s1 / c1, dA_q = kp.kq * dx, dB_q = -(s1 / c1) * kp.kq * dx;
+    const double iB2 = iB * iB;
+    const double t1 = s1 * rcp(c1);
+    const double dB_s = -s0 * rcp(c0) - t1, dA_q = kp.kq * dx, dB_q = -t1 * kp.kq * dx;
     const double a = dx * (2.0 * B - A * dB_s) * iB2;
     const double b = dx * (dA_q * B - A * dB_q) * iB2;
-    const double dL_s = dy / L * a, dL_q = dy / L * b;
+    const double dyL = dy * rcp(L);
+    const double dL_s = dyL * a, dL_q = dyL * b;
     const double du_s = 0.5 * k * dL_s, du_q = 0.5 * kp.kq * L + 0.5 * k * dL_q;
     const double c = t * (dL_s * g + L * gp * du_s);
     const double d = arc;
@@ -102,14 +139,15 @@ __device__ inline double chi2_of(const double p[5], const double C[15], double m
     const double syy = C[0] + kp.vy, syz = C[1], szz = C[2] + kp.vz;
     const double det = syy * szz - syz * syz;
     const double ry = my - p[0], rz = mz - p[1];
-    return (ry * ry * szz - 2.0 * ry * rz * syz + rz * rz * syy) / det;
+    return (ry * ry * szz - 2.0 * ry * rz * syz + rz * rz * syy) * rcp(det);
 }
 
 // Kalman update; false = fit failure.
 __device__ inline bool kf_update(double p[5], double C[15], double my, double mz, const KParams& kp, double& chi2) {
     const double syy = C[0] + kp.vy, syz = C[1], szz = C[2] + kp.vz;
     const double det = syy * szz - syz * syz;
-    const double i00 = szz / det, i01 = -syz / det, i11 = syy / det;
+    const double idet = rcp(det);
+    const double i00 = szz * idet, i01 = -syz * idet, i11 = syy * idet;
     const double ry = my - p[0], rz = mz - p[1];
     chi2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
     const double c0[5] = {C[0], C[1], C[3], C[6], C[10]};
@@ -141,8 +179,9 @@ __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const
                                      const double C[15]) {
     const double syy = C[0] + kp.vy, syz = C[1], szz = C[2] + kp.vz;
     const double det = syy * szz - syz * syz;
-    const double i00 = szz / det, i01 = -syz / det, i11 = syy / det;
-    const double bx = sqrt(kp.fol_cut * syy), bz = sqrt(kp.fol_cut * szz);
+    const double idet = rcp(det);
+    const double i00 = szz * idet, i01 = -syz * idet, i11 = syy * idet;
+    const double bx = sqrt_pos(kp.fol_cut * syy), bz = sqrt_pos(kp.fol_cut * szz);
     if (!(det > 0.0) || !isfinite(bx) || !isfinite(bz)) return -1;
     const BinRange br = bin_range(g, s, r, p[0] - bx, p[0] + bx, p[1] - bz, p[1] + bz);
     if (br.empty) return -1;
@@ -286,60 +325,20 @@ __device__ inline uint32_t finish(Lane& L, const KParams& kp, const TrackletOut&
     return (valid ? 1u : 0u) | (fail ? 2u : 0u);
 }
 
-// One row of pass A; returns true when pass A has ended.
-__device__ inline bool step_a(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                              const uint32_t* __restrict__ bin_off, const int32_t* __restrict__ upc,
-                              const TrackletOut& o) {
+// One row of the lane's current pass (A upward, B inward); true when the pass has
+// ended.  Both passes share one propagation, one row search and one filter update,
+// so a wave whose lanes are in different passes issues each of them once per row.
+//   pass A: take the next chain hit if it lies on this row and passes the chi2 cut,
+//           else (and for the rest of the pass) search the row;
+//   pass B: rows at or above the start row re-use pass A's hit on that row (if any),
+//           rows below it are searched.
+__device__ inline bool step(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+                            const uint32_t* __restrict__ bin_off, const int32_t* __restrict__ upc,
+                            const TrackletOut& o) {
     const int R = g.R;
+    const bool A = L.phase == 1;
     const int r = L.r;
-    if (r >= R) return true;
-    const double xr = g.row_x[r];
-    if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
-    L.x = xr;
-    if (fabs(L.p[0]) > xr * kp.tan_half + kp.edge) return true;
-    int32_t acc = -1;
-    Hit ha;
-    if (L.on) {
-        if (L.next >= 0) {
-            const Hit hn = hits[L.next];
-            if ((int)(hn.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hn.y, hn.z, kp) <= kp.fol_cut) {
-                acc = L.next;
-                ha = hn;
-                L.next = upc[L.next];
-            } else {
-                L.on = false;
-            }
-        } else {
-            L.on = false;
-        }
-    }
-    if (acc < 0) {
-        acc = search_row(g, kp, hits, bin_off, L.s, r, L.p, L.C);
-        if (acc >= 0) ha = hits[acc];
-    }
-    L.r = r + 1;
-    if (acc >= 0) {
-        double c2;
-        if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
-            L.fail = true;
-            return true;
-        }
-        o.hits[(size_t)L.k * R + L.nA] = acc;
-        ++L.nA;
-        L.last = r;
-        save_dir(L);
-        L.miss = 0;
-        return false;
-    }
-    return ++L.miss > kp.n_miss;
-}
-
-// One row of pass B; returns true when pass B has ended.
-__device__ inline bool step_b(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                              const uint32_t* __restrict__ bin_off, const TrackletOut& o) {
-    const int R = g.R;
-    const int r = L.r;
-    if (r < 0) return true;
+    if (A ? r >= R : r < 0) return true;
     const double xr = g.row_x[r];
     if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
     L.x = xr;
@@ -347,8 +346,24 @@ __device__ inline bool step_b(Lane& L, const GridDesc& g, const KParams& kp, con
     int32_t* slot = o.hits + (size_t)L.k * R;
     int32_t acc = -1;
     Hit ha;
-    if (r >= L.r0) {
-        if (L.ia >= 0) {
+    bool search;
+    if (A) {
+        if (L.on) {
+            L.on = false;
+            if (L.next >= 0) {
+                const Hit hn = hits[L.next];
+                if ((int)(hn.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hn.y, hn.z, kp) <= kp.fol_cut) {
+                    acc = L.next;
+                    ha = hn;
+                    L.next = upc[L.next];
+                    L.on = true;
+                }
+            }
+        }
+        search = acc < 0;
+    } else {
+        search = r < L.r0;
+        if (!search && L.ia >= 0) {
             const int32_t pa = slot[L.ia];
             const Hit hp = hits[pa];
             if ((int)(hp.rs % (uint32_t)R) == r) {
@@ -357,27 +372,33 @@ __device__ inline bool step_b(Lane& L, const GridDesc& g, const KParams& kp, con
                 --L.ia;
             }
         }
-    } else {
+    }
+    if (search) {
         acc = search_row(g, kp, hits, bin_off, L.s, r, L.p, L.C);
         if (acc >= 0) ha = hits[acc];
     }
-    L.r = r - 1;
-    if (acc >= 0) {
-        double c2;
-        if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
-            L.fail = true;
-            return true;
-        }
+    L.r = A ? r + 1 : r - 1;
+    if (acc < 0) return ++L.miss > kp.n_miss;
+    double c2;
+    if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
+        L.fail = true;
+        return true;
+    }
+    L.miss = 0;
+    if (A) {
+        slot[L.nA] = acc;
+        ++L.nA;
+        L.last = r;
+        save_dir(L);
+    } else {
         L.chi2 += c2;
         L.ndf += 2;
         slot[R - 1 - L.nB] = acc;
         ++L.nB;
         L.inner = r;
         save_inner(L);
-        L.miss = 0;
-        return false;
     }
-    return ++L.miss > kp.n_miss;
+    return false;
 }
 
 constexpr int kTlBlock = 128;
@@ -446,18 +467,10 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
             }
         }
     if (!__ballot(L.phase == 1 || L.phase == 2)) break;
-        if (L.phase == 1) {
-            if (step_a(L, g, kp, hits, bin_off, upc, o)) {
-                if (L.fail) {
-                    const uint32_t f = finish(L, kp, o);
-                    n_valid += f & 1u;
-                    n_fail += (f >> 1) & 1u;
-                } else {
-                    start_pass_b(L, g, kp, hits, o);
-                }
-            }
-        } else if (L.phase == 2) {
-            if (step_b(L, g, kp, hits, bin_off, o)) {
+        if ((L.phase == 1 || L.phase == 2) && step(L, g, kp, hits, bin_off, upc, o)) {
+            if (L.phase == 1 && !L.fail) {
+                start_pass_b(L, g, kp, hits, o);
+            } else {
                 const uint32_t f = finish(L, kp, o);
                 n_valid += f & 1u;
                 n_fail += (f >> 1) & 1u;
