@@ -16,10 +16,21 @@ struct BinRange {
     bool empty;
 };
 
-__device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0, double y1, double z0, double z1) {
+// Row tables bin_range needs, loaded ahead of the arithmetic that sets the box.
+struct RowBins {
+    double ymin;
+    int ny;
+    uint32_t base;
+};
+
+__device__ inline RowBins row_bins(const GridDesc& g, int s, int r) {
+    return RowBins{(double)g.row_ymin[r], g.row_ny[r], g.bin_base[s * g.R + r]};
+}
+
+__device__ inline BinRange bin_range(const GridDesc& g, const RowBins& rb, double y0, double y1, double z0, double z1) {
     BinRange b;
-    b.ny = g.row_ny[r];
-    const double ymin = g.row_ymin[r], iby = g.inv_by, ibz = g.inv_bz, zmin = g.z_min;
+    b.ny = rb.ny;
+    const double ymin = rb.ymin, iby = g.inv_by, ibz = g.inv_bz, zmin = g.z_min;
     const double vy0 = (y0 - ymin) * iby, vy1 = (y1 - ymin) * iby;
     const double vz0 = (z0 - zmin) * ibz, vz1 = (z1 - zmin) * ibz;
     const double fy0 = floor(vy0 - (1e-6 * fabs(vy0) + 1e-6)), fy1 = floor(vy1 + (1e-6 * fabs(vy1) + 1e-6));
@@ -29,8 +40,12 @@ __device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0,
     b.iy1 = fy1 > (double)(b.ny - 1) ? b.ny - 1 : (int)fy1;
     b.iz0 = fz0 < 0.0 ? 0 : (int)fz0;
     b.iz1 = fz1 > (double)(g.nz - 1) ? g.nz - 1 : (int)fz1;
-    b.base = g.bin_base[s * g.R + r];
+    b.base = rb.base;
     return b;
+}
+
+__device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0, double y1, double z0, double z1) {
+    return bin_range(g, row_bins(g, s, r), y0, y1, z0, z1);
 }
 
 __device__ inline uint32_t wave_sum(uint32_t v) {

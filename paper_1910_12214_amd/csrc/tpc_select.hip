@@ -19,16 +19,20 @@ __device__ inline uint64_t tl_key(uint32_t nh, uint32_t start_id) {
     return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - start_id);
 }
 
-// Walk of the processing order restricted to this workgroup's XCD slice (the same
-// slices the tracklet kernel drained, so the hits are still in that XCD's L2).
-struct SliceWalk {
+// One wave per tracklet.  Waves walk the processing order restricted to their
+// workgroup's XCD slice (the same slices the tracklet kernel drained, so the hits
+// are still in that XCD's L2); the lanes of a wave share the tracklet's hit list,
+// so slot reads are contiguous and the output hit ids are written coalesced.
+struct WaveWalk {
     uint32_t j, hi, step;
-    __device__ SliceWalk(uint32_t n) {
+    __device__ WaveWalk(uint32_t n) {
         const uint32_t x = blockIdx.x % kXcd, per = gridDim.x / kXcd, b = blockIdx.x / kXcd;
+        const uint32_t wpb = blockDim.x >> 6;
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const uint32_t lo = (uint32_t)((uint64_t)n * x / kXcd);
         hi = (uint32_t)((uint64_t)n * (x + 1) / kXcd);
-        j = lo + b * blockDim.x + threadIdx.x;
-        step = per * blockDim.x;
+        j = lo + b * wpb + wave;
+        step = per * wpb;
     }
     __device__ bool ok() const { return j < hi; }
     __device__ void next() { j += step; }
@@ -38,13 +42,14 @@ __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, c
                                                  const uint32_t* __restrict__ proc, TrackletOut o, int R,
                                                  const uint32_t* __restrict__ counters, uint64_t* __restrict__ hit_key) {
     const uint32_t n = counters[C_N_STARTS];
-    for (SliceWalk w(n); w.ok(); w.next()) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (WaveWalk w(n); w.ok(); w.next()) {
         const uint32_t k = proc[w.j];
         if (!(o.flags[k] & 1u)) continue;
         const uint32_t nh = (uint32_t)o.nhits[k];
         const uint64_t key = tl_key(nh, hits[starts[k]].id);
-        const int32_t* slot = o.hits + (size_t)k * R;
-        for (int j = R - (int)nh; j < R; ++j) {
+        const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
+        for (uint32_t j = lane; j < nh; j += 64) {
             const int32_t pos = slot[j];
             // keys only grow: a plain read at or above ours makes the atomic unnecessary
             if (hit_key[pos] < key) atomicMax((unsigned long long*)&hit_key[pos], (unsigned long long)key);
@@ -58,18 +63,22 @@ __global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, co
                                                 const uint64_t* __restrict__ hit_key, int n_min_trk,
                                                 uint32_t* __restrict__ own_cnt, uint32_t* __restrict__ trk_flag) {
     const uint32_t n = counters[C_N_STARTS];
-    for (SliceWalk w(n); w.ok(); w.next()) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (WaveWalk w(n); w.ok(); w.next()) {
         const uint32_t k = proc[w.j];
         uint32_t owned = 0;
         if (o.flags[k] & 1u) {
             const uint32_t nh = (uint32_t)o.nhits[k];
             const uint64_t key = tl_key(nh, hits[starts[k]].id);
-            const int32_t* slot = o.hits + (size_t)k * R;
-            for (int j = R - (int)nh; j < R; ++j) owned += hit_key[slot[j]] == key;
+            const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
+            for (uint32_t j = lane; j < nh; j += 64) owned += hit_key[slot[j]] == key;
+            owned = wave_sum(owned);
             if ((int)owned < n_min_trk) owned = 0;
         }
-        own_cnt[k] = owned;
-        trk_flag[k] = owned ? 1u : 0u;
+        if (lane == 0) {
+            own_cnt[k] = owned;
+            trk_flag[k] = owned ? 1u : 0u;
+        }
     }
 }
 
@@ -82,7 +91,9 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
                                                   const uint32_t* __restrict__ trk_idx, tpc_tracks_t out) {
     const uint32_t n = counters[C_N_STARTS];
     const int R = g.R;
-    for (SliceWalk w(n); w.ok(); w.next()) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (WaveWalk w(n); w.ok(); w.next()) {
         const uint32_t k = proc[w.j];
         const uint32_t cnt = own_cnt[k];
         if (!cnt) continue;
@@ -91,23 +102,32 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
         const uint32_t nh = (uint32_t)o.nhits[k];
         const Hit hs = hits[starts[k]];
         const uint64_t key = tl_key(nh, hs.id);
-        const int32_t* slot = o.hits + (size_t)k * R;
+        const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
         uint32_t wr = off;
-        for (int j = R - (int)nh; j < R; ++j) {
-            const int32_t pos = slot[j];
-            if (hit_key[pos] == key) out.hit_ids[wr++] = (int32_t)hits[pos].id;
+        for (uint32_t base = 0; base < nh; base += 64) {
+            const uint32_t j = base + lane;
+            bool mine = false;
+            int32_t pos = 0;
+            if (j < nh) {
+                pos = slot[j];
+                mine = hit_key[pos] == key;
+            }
+            const uint64_t m = __ballot(mine);
+            if (mine) out.hit_ids[wr + (uint32_t)__popcll(m & below)] = (int32_t)hits[pos].id;
+            wr += (uint32_t)__popcll(m);
         }
-        out.hit_offset[t] = (int32_t)off;
-        out.n_hits[t] = (int32_t)cnt;
-        out.start_id[t] = (int32_t)hs.id;
-        out.sector[t] = (int32_t)(hs.rs / (uint32_t)R);
-        const int rr = o.row_ref[k];
-        out.row_ref[t] = rr;
-        out.x_ref[t] = g.row_x[rr];
-        for (int i = 0; i < 5; ++i) out.state[(size_t)t * 5 + i] = o.state[(size_t)k * 5 + i];
-        for (int i = 0; i < 15; ++i) out.cov[(size_t)t * 15 + i] = o.cov[(size_t)k * 15 + i];
-        out.chi2[t] = o.chi2[k];
-        out.ndf[t] = o.ndf[k];
+        if (lane < 5) out.state[(size_t)t * 5 + lane] = o.state[(size_t)k * 5 + lane];
+        else if (lane < 20) out.cov[(size_t)t * 15 + (lane - 5)] = o.cov[(size_t)k * 15 + (lane - 5)];
+        else if (lane == 20) out.hit_offset[t] = (int32_t)off;
+        else if (lane == 21) out.n_hits[t] = (int32_t)cnt;
+        else if (lane == 22) out.start_id[t] = (int32_t)hs.id;
+        else if (lane == 23) out.sector[t] = (int32_t)(hs.rs / (uint32_t)R);
+        else if (lane == 24) {
+            const int rr = o.row_ref[k];
+            out.row_ref[t] = rr;
+            out.x_ref[t] = g.row_x[rr];
+        } else if (lane == 25) out.chi2[t] = o.chi2[k];
+        else if (lane == 26) out.ndf[t] = o.ndf[k];
     }
 }
 
@@ -126,8 +146,8 @@ __global__ void k_finish(const uint32_t* __restrict__ c, int32_t* __restrict__ o
 }
 
 inline unsigned sel_blocks(int64_t t_max) {
-    int64_t b = (t_max + kBlock - 1) / kBlock;
-    if (b > 4096) b = 4096;
+    int64_t b = (t_max + kBlock / 64 - 1) / (kBlock / 64);  // one wave per tracklet
+    if (b > 8192) b = 8192;
     b = (b + kXcd - 1) / kXcd * kXcd;  // whole rounds over the XCDs
     return (unsigned)(b < kXcd ? kXcd : b);
 }

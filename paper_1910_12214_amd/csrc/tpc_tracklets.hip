@@ -173,35 +173,53 @@ __device__ inline bool kf_update(double p[5], double C[15], double my, double mz
     return ok;
 }
 
-// Nearest hit in row r of sector s: smallest chi2 <= cut inside the ellipse's box.
+// Nearest hit in one row: smallest chi2 <= cut inside the ellipse's box, ties by
+// cluster id; -1 if none.  The winner's coordinates come back in (hy, hz).  Loads
+// run one step ahead: the next z row's bin bounds while this row's hits are
+// scanned, and the next candidate while the current one is tested.
 __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                                     const uint32_t* __restrict__ bin_off, int s, int r, const double p[5],
-                                     const double C[15]) {
+                                     const uint32_t* __restrict__ bin_off, const RowBins& rb, const double p[5],
+                                     const double C[15], float& hy, float& hz) {
     const double syy = C[0] + kp.vy, syz = C[1], szz = C[2] + kp.vz;
     const double det = syy * szz - syz * syz;
     const double idet = rcp(det);
     const double i00 = szz * idet, i01 = -syz * idet, i11 = syy * idet;
     const double bx = sqrt_pos(kp.fol_cut * syy), bz = sqrt_pos(kp.fol_cut * szz);
     if (!(det > 0.0) || !isfinite(bx) || !isfinite(bz)) return -1;
-    const BinRange br = bin_range(g, s, r, p[0] - bx, p[0] + bx, p[1] - bz, p[1] + bz);
+    const BinRange br = bin_range(g, rb, p[0] - bx, p[0] + bx, p[1] - bz, p[1] + bz);
     if (br.empty) return -1;
     double best = 1e300;
     uint32_t best_id = 0xFFFFFFFFu;
     int32_t best_pos = -1;
+    uint32_t zrow = br.base + br.iz0 * br.ny;
+    uint32_t kb = bin_off[zrow + br.iy0], ke = bin_off[zrow + br.iy1 + 1];
     for (int iz = br.iz0; iz <= br.iz1; ++iz) {
-        const uint32_t k1 = bin_off[br.base + iz * br.ny + br.iy1 + 1];
-        for (uint32_t k = bin_off[br.base + iz * br.ny + br.iy0]; k < k1; ++k) {
-            const Hit h = hits[k];
-            const double ry = (double)h.y - p[0], rz = (double)h.z - p[1];
-            if (fabs(ry) > bx || fabs(rz) > bz) continue;
-            const double c2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
-            if (!(c2 <= kp.fol_cut)) continue;
-            if (c2 < best || (c2 == best && h.id < best_id)) {
-                best = c2;
-                best_id = h.id;
-                best_pos = (int32_t)k;
+        uint32_t nb = 0, ne = 0;
+        if (iz < br.iz1) {
+            zrow += br.ny;
+            nb = bin_off[zrow + br.iy0];
+            ne = bin_off[zrow + br.iy1 + 1];
+        }
+        if (kb < ke) {
+            Hit h = hits[kb];
+            for (uint32_t k = kb; k < ke; ++k) {
+                const Hit hn = hits[k + 1 < ke ? k + 1 : k];
+                const double ry = (double)h.y - p[0], rz = (double)h.z - p[1];
+                if (fabs(ry) <= bx && fabs(rz) <= bz) {
+                    const double c2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
+                    if (c2 <= kp.fol_cut && (c2 < best || (c2 == best && h.id < best_id))) {
+                        best = c2;
+                        best_id = h.id;
+                        best_pos = (int32_t)k;
+                        hy = h.y;
+                        hz = h.z;
+                    }
+                }
+                h = hn;
             }
         }
+        kb = nb;
+        ke = ne;
     }
     return best_pos;
 }
@@ -339,48 +357,56 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const KParams& kp, const
     const bool A = L.phase == 1;
     const int r = L.r;
     if (A ? r >= R : r < 0) return true;
+    int32_t* slot = o.hits + (size_t)L.k * R;
+    // Loads that do not depend on the propagated state go out before it is computed:
+    // the row tables, and the hit this row may take without a search (the next chain
+    // hit in pass A, pass A's hit on this row in pass B) with its upward link.
     const double xr = g.row_x[r];
+    const RowBins rb = row_bins(g, L.s, r);
+    int32_t cand = -1;
+    if (A) {
+        if (L.on) cand = L.next;
+    } else if (r >= L.r0 && L.ia >= 0) {
+        cand = slot[L.ia];
+    }
+    Hit hc;
+    int32_t cand_up = -1;
+    if (cand >= 0) {
+        hc = hits[cand];
+        if (A) cand_up = upc[cand];
+    }
     if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
     L.x = xr;
     if (fabs(L.p[0]) > xr * kp.tan_half + kp.edge) return true;
-    int32_t* slot = o.hits + (size_t)L.k * R;
     int32_t acc = -1;
-    Hit ha;
+    float hy = 0.f, hz = 0.f;
     bool search;
     if (A) {
         if (L.on) {
             L.on = false;
-            if (L.next >= 0) {
-                const Hit hn = hits[L.next];
-                if ((int)(hn.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hn.y, hn.z, kp) <= kp.fol_cut) {
-                    acc = L.next;
-                    ha = hn;
-                    L.next = upc[L.next];
-                    L.on = true;
-                }
+            if (cand >= 0 && (int)(hc.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hc.y, hc.z, kp) <= kp.fol_cut) {
+                acc = cand;
+                L.next = cand_up;
+                L.on = true;
             }
         }
         search = acc < 0;
     } else {
         search = r < L.r0;
-        if (!search && L.ia >= 0) {
-            const int32_t pa = slot[L.ia];
-            const Hit hp = hits[pa];
-            if ((int)(hp.rs % (uint32_t)R) == r) {
-                acc = pa;
-                ha = hp;
-                --L.ia;
-            }
+        if (cand >= 0 && (int)(hc.rs % (uint32_t)R) == r) {
+            acc = cand;
+            --L.ia;
         }
     }
-    if (search) {
-        acc = search_row(g, kp, hits, bin_off, L.s, r, L.p, L.C);
-        if (acc >= 0) ha = hits[acc];
+    if (acc >= 0) {
+        hy = hc.y;
+        hz = hc.z;
     }
+    if (search) acc = search_row(g, kp, hits, bin_off, rb, L.p, L.C, hy, hz);
     L.r = A ? r + 1 : r - 1;
     if (acc < 0) return ++L.miss > kp.n_miss;
     double c2;
-    if (!kf_update(L.p, L.C, ha.y, ha.z, kp, c2)) {
+    if (!kf_update(L.p, L.C, hy, hz, kp, c2)) {
         L.fail = true;
         return true;
     }
