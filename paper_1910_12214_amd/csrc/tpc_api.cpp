@@ -58,6 +58,7 @@ struct Prepared {
     int64_t n = 0;
     int64_t t_max = 0;
     uint32_t n_bins = 0;
+    int slab_bins = 1;  // z bins per slab of the tracklet processing order
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -189,12 +190,13 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
     pr->n = cl->n;
     pr->n_bins = (uint32_t)nb;
     pr->t_max = cl->n / p->l_min_chain + 1;
+    pr->slab_bins = std::max(1, (int)std::lround(kSlabCm / bin_z));
     return TPC_OK;
 }
 
 struct Scratch {
-    uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *bin_fill, *bin_off, *row_off, *block_cnt, *starts;
-    uint32_t *kidx, *proc;
+    uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
+    uint32_t *tl_slot, *proc, *slab_cnt;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
     int32_t *up, *dn, *upc, *dnc;
@@ -218,6 +220,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(bin_of, "bin_of", 4 * n);
     B(pos_of, "pos_of", 4 * n);
     B(sorted_id, "sorted_id", 4 * n);
+    B(slot_of, "slot_of", 4 * n);
     B(hits, "hits", sizeof(Hit) * n);
     B(up, "up", 4 * n);
     B(dn, "dn", 4 * n);
@@ -226,12 +229,12 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(start_flag, "start_flag", 4 * ((n + 3) / 4));
     B(hit_key, "hit_key", 8 * n);
     B(bin_cnt, "bin_cnt", 4 * (NB + 1));
-    B(bin_fill, "bin_fill", 4 * (NB + 1));
     B(bin_off, "bin_off", 4 * (NB + 1));
     B(row_off, "row_off", 4 * (S * R + 1));
     B(block_cnt, "block_cnt", 4 * nblk);
     B(starts, "starts", 4 * T);
-    B(kidx, "kidx", 4 * n);
+    B(tl_slot, "tl_slot", 4 * T);
+    B(slab_cnt, "slab_cnt", 4 * ((int64_t)S * slab_count(pr.g, pr.slab_bins) + 1));
     B(proc, "proc", 4 * T);
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
@@ -277,12 +280,11 @@ void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s
     const GridDesc& g = pr.g;
     fill_u32(s.counters, 0u, C_N_COUNTERS, st);
     fill_u32(s.bin_cnt, 0u, NB, st);
-    fill_u32(s.bin_fill, 0u, NB, st);
     fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
-    grid_count(cl, g, s.bin_of, s.bin_cnt, s.pos_of, st);
+    grid_count(cl, g, s.bin_of, s.bin_cnt, s.slot_of, s.pos_of, st);
     scan_u32(s.bin_cnt, s.bin_off, NB, nullptr, s.bin_off + NB, s.scan, st);
-    grid_scatter(cl, s.bin_of, s.bin_off, s.bin_fill, s.sorted_id, st);
-    grid_finalize(cl, g, s.bin_off, s.sorted_id, s.hits, s.pos_of, s.row_off, s.counters, st);
+    grid_scatter(cl, s.bin_of, s.slot_of, s.bin_off, s.sorted_id, st);
+    grid_finalize(cl, g, s.bin_of, s.bin_off, s.sorted_id, s.hits, s.pos_of, s.row_off, s.counters, st);
 }
 
 void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s,
@@ -300,8 +302,8 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
     clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
-    compact_starts(s.start_flag, s.pos_of, n, s.starts, s.kidx, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
-    order_starts(s.hits, s.start_flag, s.kidx, n, s.counters, s.proc, s.block_cnt, s.scan, st);
+    compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
+    order_starts(g, s.hits, s.starts, T, s.counters, pr.slab_bins, s.slab_cnt, s.tl_slot, s.proc, s.scan, st);
     mk.mark();
     // a6 tracklets
     build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.counters, s.tl, tl_blocks, chunk, waves,

@@ -134,12 +134,14 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 
 // grid.hip
-void grid_count(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* bin_of, uint32_t* bin_cnt, uint32_t* pos_of,
-                hipStream_t s);
-void grid_scatter(const tpc_clusters_t& cl, const uint32_t* bin_of, const uint32_t* bin_off, uint32_t* bin_fill,
+// bin_of, slot_of, pos_of, sorted_id: [n]; bin_cnt: [n_bins] zeroed; hits: [n]
+void grid_count(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* bin_of, uint32_t* bin_cnt, uint32_t* slot_of,
+                uint32_t* pos_of, hipStream_t s);
+void grid_scatter(const tpc_clusters_t& cl, const uint32_t* bin_of, const uint32_t* slot_of, const uint32_t* bin_off,
                   uint32_t* sorted_id, hipStream_t s);
-void grid_finalize(const tpc_clusters_t& cl, const GridDesc& g, const uint32_t* bin_off, uint32_t* sorted_id,
-                   Hit* hits, uint32_t* pos_of, uint32_t* row_off, uint32_t* counters, hipStream_t s);
+void grid_finalize(const tpc_clusters_t& cl, const GridDesc& g, const uint32_t* bin_of, const uint32_t* bin_off,
+                   const uint32_t* sorted_id, Hit* hits, uint32_t* pos_of, uint32_t* row_off, uint32_t* counters,
+                   hipStream_t s);
 
 // links.hip
 void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
@@ -148,11 +150,15 @@ void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, cons
 void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uint32_t* counters, const int32_t* up,
                     const int32_t* dn, int32_t* upc, int32_t* dnc, uint8_t* start_flag, uint32_t* cnt,
                     hipStream_t s);
-void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts, uint32_t* kidx,
+void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s);
-// processing order: start indices k in grid order (sector, row, bin) of their start hits
-void order_starts(const Hit* hits, const uint8_t* start_flag, const uint32_t* kidx, int64_t n_max,
-                  const uint32_t* counters, uint32_t* proc, uint32_t* block_cnt, void* scan_scratch, hipStream_t s);
+// processing order: start indices k grouped by (sector, z slab of slab_bins z bins) of
+// their start hits; slab_cnt: [S * slab_count + 1], slot: [t_max]
+constexpr float kSlabCm = 64.f;
+int slab_count(const GridDesc& g, int slab_bins);
+void order_starts(const GridDesc& g, const Hit* hits, const uint32_t* starts, int64_t t_max, const uint32_t* counters,
+                  int slab_bins, uint32_t* slab_cnt, uint32_t* slot, uint32_t* proc, void* scan_scratch,
+                  hipStream_t s);
 constexpr int kXcd = 8;  // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin
 
 // tracklets.hip

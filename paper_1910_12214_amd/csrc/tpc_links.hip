@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_flag_count(const uint8_t* __restrict
 __global__ __launch_bounds__(kBlock) void k_flag_write(const uint8_t* __restrict__ flag, int64_t n,
                                                        const uint32_t* __restrict__ block_off,
                                                        const uint32_t* __restrict__ pos_of,
-                                                       uint32_t* __restrict__ out, uint32_t* __restrict__ kidx) {
+                                                       uint32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool f = i < n && flag[i];
     const uint64_t mask = __ballot(f);
@@ -147,48 +147,39 @@ __global__ __launch_bounds__(kBlock) void k_flag_write(const uint8_t* __restrict
     if (f) {
         const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;  // mbcnt
         const uint32_t k = off + (uint32_t)__popcll(below);
-        const uint32_t p = pos_of[i];
-        out[k] = p;
-        kidx[p] = k;
+        out[k] = pos_of[i];
     }
 }
 
-// The same compaction over grid positions: the processing order of the tracklets.
-__global__ __launch_bounds__(kBlock) void k_pos_count(const Hit* __restrict__ hits, const uint8_t* __restrict__ flag,
-                                                      const uint32_t* __restrict__ counters,
-                                                      uint32_t* __restrict__ block_cnt) {
-    const uint32_t n = counters[C_N_VALID_CLU];
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    const bool f = p < n && flag[hits[p].id];
-    const uint64_t mask = __ballot(f);
-    __shared__ uint32_t wc[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int k = 0; k < kBlock / 64; ++k) t += wc[k];
-        block_cnt[blockIdx.x] = t;
-    }
+// Processing order of the tracklets: start indices grouped by (sector, z slab) of
+// the start hit, so that tracklets taken from the queue together read the hits of
+// one sector and a narrow z range (inside a time frame, one group of collisions).
+// The order inside a group is the arbitrary order of the slot atomics: tracklet
+// results do not depend on which lane builds which tracklet, only locality does.
+__device__ inline uint32_t slab_of(const GridDesc& g, const Hit& h, int slab_bins, int n_slab) {
+    const float vz = (h.z - g.z_min) * g.inv_bz;
+    const int iz = !(vz > 0.0f) ? 0 : (vz >= (float)g.nz ? g.nz - 1 : (int)vz);
+    return (h.rs / (uint32_t)g.R) * (uint32_t)n_slab + (uint32_t)(iz / slab_bins);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pos_write(const Hit* __restrict__ hits, const uint8_t* __restrict__ flag,
-                                                      const uint32_t* __restrict__ counters,
-                                                      const uint32_t* __restrict__ block_off,
-                                                      const uint32_t* __restrict__ kidx, uint32_t* __restrict__ proc) {
-    const uint32_t n = counters[C_N_VALID_CLU];
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    const bool f = p < n && flag[hits[p].id];
-    const uint64_t mask = __ballot(f);
-    __shared__ uint32_t wc[kBlock / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) wc[w] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    uint32_t off = block_off[blockIdx.x];
-    for (int k = 0; k < w; ++k) off += wc[k];
-    if (f) {
-        const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
-        proc[off + (uint32_t)__popcll(below)] = kidx[p];
-    }
+__global__ __launch_bounds__(kBlock) void k_slab_count(GridDesc g, const Hit* __restrict__ hits,
+                                                       const uint32_t* __restrict__ starts,
+                                                       const uint32_t* __restrict__ counters, int slab_bins,
+                                                       int n_slab, uint32_t* __restrict__ slab_cnt,
+                                                       uint32_t* __restrict__ slot) {
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= counters[C_N_STARTS]) return;
+    slot[k] = atomicAdd(&slab_cnt[slab_of(g, hits[starts[k]], slab_bins, n_slab)], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_slab_write(GridDesc g, const Hit* __restrict__ hits,
+                                                       const uint32_t* __restrict__ starts,
+                                                       const uint32_t* __restrict__ counters, int slab_bins,
+                                                       int n_slab, const uint32_t* __restrict__ slab_off,
+                                                       const uint32_t* __restrict__ slot, uint32_t* __restrict__ proc) {
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= counters[C_N_STARTS]) return;
+    proc[slab_off[slab_of(g, hits[starts[k]], slab_bins, n_slab)] + slot[k]] = k;
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1); }
@@ -209,20 +200,25 @@ void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uin
     k_clean_flag<<<blocks(n_max), kBlock, 0, s>>>(kp, hits, counters, up, dn, upc, dnc, start_flag, cnt);
 }
 
-void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts, uint32_t* kidx,
+void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s) {
     const unsigned nb = blocks(n);
     k_flag_count<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt);
     scan_u32(block_cnt, block_cnt, nb, nullptr, n_starts_dev, scan_scratch, s);
-    k_flag_write<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt, pos_of, starts, kidx);
+    k_flag_write<<<nb, kBlock, 0, s>>>(start_flag, n, block_cnt, pos_of, starts);
 }
 
-void order_starts(const Hit* hits, const uint8_t* start_flag, const uint32_t* kidx, int64_t n_max,
-                  const uint32_t* counters, uint32_t* proc, uint32_t* block_cnt, void* scan_scratch, hipStream_t s) {
-    const unsigned nb = blocks(n_max);
-    k_pos_count<<<nb, kBlock, 0, s>>>(hits, start_flag, counters, block_cnt);
-    scan_u32(block_cnt, block_cnt, nb, nullptr, nullptr, scan_scratch, s);
-    k_pos_write<<<nb, kBlock, 0, s>>>(hits, start_flag, counters, block_cnt, kidx, proc);
+int slab_count(const GridDesc& g, int slab_bins) { return (g.nz + slab_bins - 1) / slab_bins; }
+
+void order_starts(const GridDesc& g, const Hit* hits, const uint32_t* starts, int64_t t_max, const uint32_t* counters,
+                  int slab_bins, uint32_t* slab_cnt, uint32_t* slot, uint32_t* proc, void* scan_scratch,
+                  hipStream_t s) {
+    const int n_slab = slab_count(g, slab_bins);
+    const int64_t nb = (int64_t)g.S * n_slab;
+    fill_u32(slab_cnt, 0u, nb, s);
+    k_slab_count<<<blocks(t_max), kBlock, 0, s>>>(g, hits, starts, counters, slab_bins, n_slab, slab_cnt, slot);
+    scan_u32(slab_cnt, slab_cnt, nb, nullptr, nullptr, scan_scratch, s);
+    k_slab_write<<<blocks(t_max), kBlock, 0, s>>>(g, hits, starts, counters, slab_bins, n_slab, slab_cnt, slot, proc);
 }
 
 }  // namespace tpc

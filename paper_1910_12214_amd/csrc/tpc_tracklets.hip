@@ -435,11 +435,11 @@ constexpr int kTlBlock = 128;
 // tracklets share a wave without idling it.  `chunk` scales how many queue
 // entries an idle lane reserves at a time (1 = one tracklet).
 //
-// The queue runs over the processing order `proc` (tracklets sorted by the grid
-// position of their start hit: sector, row, z bin), split into one contiguous
-// slice per XCD.  Workgroup b is dispatched to XCD b mod 8, drains that XCD's
-// slice first and then steals from the others, so each XCD's L2 holds the hits
-// of a few sectors and z ranges instead of the whole event.
+// The queue runs over the processing order `proc` (tracklets grouped by sector
+// and z slab of their start hit), split into one contiguous slice per XCD.
+// Workgroup b is dispatched to XCD b mod 8, drains that XCD's slice first and
+// then steals from the others, so the tracklets an XCD builds at any moment read
+// the hits of one sector and a narrow z range, which its L2 holds.
 template <int WAVES>
 __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES))) void k_tracklets(
     GridDesc g, KParams kp, const Hit* __restrict__ hits,
