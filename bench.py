@@ -176,13 +176,18 @@ def main():
         from paper_1910_12214_amd import scorer as sc
         from synth import metrics
 
-        params_mlp, tau_trained = sc.load()
+        # the scorer trained on events of this workload's generator if there is one, else the
+        # one-sector scorer
+        ck = sc.PBPB_CKPT if w.name.startswith("pbpb") and os.path.exists(sc.PBPB_CKPT) else sc.DEFAULT_CKPT
+        params_mlp, tau_trained = sc.load(ck)
         mlp = torch.from_numpy(params_mlp).to(dev)
         # threshold for this workload: largest tau on a grid whose efficiency on a validation event of
         # the same workload (another seed) is within 0.5% of the plain finder's
         import dataclasses
 
         wv = dataclasses.replace(w, seed=w.seed + 7919)
+        if w.n_collisions > 1:  # a time frame: validate on a tenth of one (same rate and mix)
+            wv = synth.scaled(wv, 0.1)
         evv = synth.generate(wv)
         tv = [torch.from_numpy(a).to(dev) for a in (evv.y, evv.z, evv.row, evv.sector)]
         geov = synth.geometry(wv)
@@ -202,17 +207,30 @@ def main():
             tau = -8.0
         log("pruned leg: tau", tau, "on", wv.name)
         out_m = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
-        ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream)
+
+        def step_m(**kw):  # the same entry point as the plain leg
+            return ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
+                             timeframe=tf, **kw)
+
+        step_m()
         for _ in range(args.warmup):
-            ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
-                      sync_check=False)
+            step_m(sync_check=False)
+        torch.cuda.synchronize()
+        if not tf:
+            ctx.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
-                      sync_check=False)
+            step_m(sync_check=False)
         torch.cuda.synchronize()
         ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
+        if tf:
+            ctx.profile(True)
+            for _ in range(args.steps):
+                step_m(sync_check=False)
+            torch.cuda.synchronize()
+        ctx.profile(False)
+        st_m, n_m = ctx.profile_read()
         log("timed pruned")
         hp = tpcca.tracks_to_host(out)
         hm = tpcca.tracks_to_host(out_m)
@@ -223,7 +241,8 @@ def main():
                          "clone_rate": mp["clone_rate"], "tracklets": int(counts[tpcca.CNT_TRACKLETS])}
         line["mlp_pruned"] = {"value": ev.n / (ms_m * 1e-3), "ms_per_step": ms_m, "tau_logit": tau,
                               "tau_from": f"validation event {wv.name} (seed {wv.seed})",
-                              "trained_on": "one-sector 200-helix events, seeds 1-200",
+                              "trained_on": sc.trained_on(ck),
+                              "stage_ms": {k: round(v / max(1, n_m), 4) for k, v in st_m.items()},
                               "tau_trained_workload": tau_trained,
                               "efficiency": mm["efficiency"], "fake_rate": mm["fake_rate"],
                               "clone_rate": mm["clone_rate"], "tracklets": int(cm[tpcca.CNT_TRACKLETS]),

@@ -175,6 +175,8 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
     k.vz = p->sigma_z * p->sigma_z;
     k.vy15 = 1.5 * p->sigma_y * p->sigma_y;
     k.vz15 = 1.5 * p->sigma_z * p->sigma_z;
+    k.ivy15 = 1.0 / k.vy15;
+    k.ivz15 = 1.0 / k.vz15;
     k.s_max = p->s_max;
     k.edge = p->edge_margin;
     k.tan_half = (double)geo->tan_half;
@@ -197,6 +199,7 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
 struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
     uint32_t *tl_slot, *proc, *slab_cnt;
+    void* seeds;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
     int32_t *up, *dn, *upc, *dnc;
@@ -234,8 +237,9 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(block_cnt, "block_cnt", 4 * nblk);
     B(starts, "starts", 4 * T);
     B(tl_slot, "tl_slot", 4 * T);
-    B(slab_cnt, "slab_cnt", 4 * ((int64_t)S * slab_count(pr.g, pr.slab_bins) + 1));
+    B(slab_cnt, "slab_cnt", 4 * ((int64_t)S * slab_count(pr.g, pr.slab_bins) * R + 1));
     B(proc, "proc", 4 * T);
+    B(seeds, "tl_seeds", seed_bytes() * T);
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
     B(hit_off, "hit_off", 4 * T);
@@ -306,8 +310,8 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     order_starts(g, s.hits, s.starts, T, s.counters, pr.slab_bins, s.slab_cnt, s.tl_slot, s.proc, s.scan, st);
     mk.mark();
     // a6 tracklets
-    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.counters, s.tl, tl_blocks, chunk, waves,
-                    st);
+    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.seeds, s.counters, s.tl, T, tl_blocks,
+                    chunk, waves, st);
     mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);

@@ -37,6 +37,7 @@ struct GridDesc {
 struct KParams {
     double win_y, win_z, nb_cut, fol_cut;
     double vy, vz, vy15, vz15;
+    double ivy15, ivz15;  // 1 / vy15, 1 / vz15 (the pair criterion multiplies)
     double s_max, edge, tan_half, kq;
     double c0s, c0t, c0q;
     int32_t l_min, n_miss, n_min_tl, n_min_trk;
@@ -152,8 +153,8 @@ void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uin
                     hipStream_t s);
 void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s);
-// processing order: start indices k grouped by (sector, z slab of slab_bins z bins) of
-// their start hits; slab_cnt: [S * slab_count + 1], slot: [t_max]
+// processing order: start indices k grouped by (sector, z slab of slab_bins z bins, row)
+// of their start hits; slab_cnt: [S * slab_count * R + 1], slot: [t_max]
 constexpr float kSlabCm = 64.f;
 int slab_count(const GridDesc& g, int slab_bins);
 void order_starts(const GridDesc& g, const Hit* hits, const uint32_t* starts, int64_t t_max, const uint32_t* counters,
@@ -172,9 +173,12 @@ struct TrackletOut {
     int32_t* row_ref;
     uint32_t* flags;     // bit0 valid, bit1 fail
 };
+size_t seed_bytes();  // bytes of one precomputed tracklet start record
+// seeds: [t_max] start records in processing order (written here, then consumed)
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
-                     const TrackletOut& o, int grid_blocks, int chunk, int waves, hipStream_t s);
+                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, void* seeds,
+                     uint32_t* counters, const TrackletOut& o, int64_t t_max, int grid_blocks, int chunk, int waves,
+                     hipStream_t s);
 
 // select.hip
 void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,

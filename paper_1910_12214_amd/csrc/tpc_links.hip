@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(GridDesc g, KParams kp, c
                                 if (!(fabs(yd - ym) <= wyd) || !(fabs(zd - zm) <= wzd)) continue;
                                 ++pairs;
                                 const double py = yd + (yu - yd) * w, pz = zd + (zu - zd) * w;
-                                const double Dv = (ym - py) * (ym - py) / kp.vy15 + (zm - pz) * (zm - pz) / kp.vz15;
+                                const double Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
                                 if (!(Dv <= kp.nb_cut)) continue;
                                 if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
                                     best = Dv;
@@ -151,15 +151,17 @@ __global__ __launch_bounds__(kBlock) void k_flag_write(const uint8_t* __restrict
     }
 }
 
-// Processing order of the tracklets: start indices grouped by (sector, z slab) of
-// the start hit, so that tracklets taken from the queue together read the hits of
-// one sector and a narrow z range (inside a time frame, one group of collisions).
-// The order inside a group is the arbitrary order of the slot atomics: tracklet
-// results do not depend on which lane builds which tracklet, only locality does.
+// Processing order of the tracklets: start indices grouped by (sector, z slab, row)
+// of the start hit.  Tracklets taken from the queue together read the hits of one
+// sector and a narrow z range (inside a time frame, one group of collisions), and
+// the lanes of a wave start on the same row, so they tend to be in the same pass
+// at the same time.  The order inside a group is the arbitrary order of the slot
+// atomics: tracklet results do not depend on which lane builds which tracklet.
 __device__ inline uint32_t slab_of(const GridDesc& g, const Hit& h, int slab_bins, int n_slab) {
     const float vz = (h.z - g.z_min) * g.inv_bz;
     const int iz = !(vz > 0.0f) ? 0 : (vz >= (float)g.nz ? g.nz - 1 : (int)vz);
-    return (h.rs / (uint32_t)g.R) * (uint32_t)n_slab + (uint32_t)(iz / slab_bins);
+    const uint32_t s = h.rs / (uint32_t)g.R, r = h.rs % (uint32_t)g.R;
+    return (s * (uint32_t)n_slab + (uint32_t)(iz / slab_bins)) * (uint32_t)g.R + r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_slab_count(GridDesc g, const Hit* __restrict__ hits,
@@ -214,7 +216,7 @@ void order_starts(const GridDesc& g, const Hit* hits, const uint32_t* starts, in
                   int slab_bins, uint32_t* slab_cnt, uint32_t* slot, uint32_t* proc, void* scan_scratch,
                   hipStream_t s) {
     const int n_slab = slab_count(g, slab_bins);
-    const int64_t nb = (int64_t)g.S * n_slab;
+    const int64_t nb = (int64_t)g.S * n_slab * g.R;
     fill_u32(slab_cnt, 0u, nb, s);
     k_slab_count<<<blocks(t_max), kBlock, 0, s>>>(g, hits, starts, counters, slab_bins, n_slab, slab_cnt, slot);
     scan_u32(slab_cnt, slab_cnt, nb, nullptr, nullptr, scan_scratch, s);

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64 * kNbWaves) void k_neighbours_mlp(GridDesc g, KP
                     ++kept;
                     const double yu = u.y, zu = u.z, yd = d.y, zd = d.z;
                     const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
-                    const double Dv = (ym - py) * (ym - py) / kp.vy15 + (zm - pz) * (zm - pz) / kp.vz15;
+                    const double Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
                     if (!(Dv <= kp.nb_cut)) return;
                     if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
                         best = Dv;

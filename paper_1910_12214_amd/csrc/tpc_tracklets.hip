@@ -238,8 +238,20 @@ __device__ inline void c0_init(double C[15], const KParams& kp) {
 // Rarely touched per-lane values live in LDS, not registers: pass A's direction
 // and curvature at its outermost hit, and pass B's state at its innermost hit.
 struct Spare {
-    double pl[3];
+    double pl[3];      // pass A at its outermost hit: sin phi, dz/ds, q/pT
+    float ly, lz;      // that hit's coordinates
+    int32_t lpos;      // and grid position
     float pin[5], cin[15];
+};
+
+// Start of one tracklet, precomputed in processing order (three 16-byte loads).
+struct alignas(16) Seed {
+    uint32_t k;        // start index
+    int32_t p0, p1;    // grid positions of the start hit and its cleaned upward link
+    uint32_t rs;       // sector * n_rows + row of the start hit
+    float y0, z0;
+    uint32_t pad0, pad1;
+    double s0, t0;     // initial sin phi and dz/ds from the first link
 };
 
 struct Lane {
@@ -260,53 +272,46 @@ __device__ inline void save_inner(Lane& L) {
     for (int i = 0; i < 15; ++i) L.sp->cin[i] = (float)L.C[i];
 }
 
-__device__ inline void save_dir(Lane& L) {
+__device__ inline void save_dir(Lane& L, float hy, float hz, int32_t pos) {
     L.sp->pl[0] = L.p[2];
     L.sp->pl[1] = L.p[3];
     L.sp->pl[2] = L.p[4];
+    L.sp->ly = hy;
+    L.sp->lz = hz;
+    L.sp->lpos = pos;
 }
 
-__device__ inline void start_pass_a(Lane& L, uint32_t k, const GridDesc& g, const KParams& kp,
-                                    const Hit* __restrict__ hits, const int32_t* __restrict__ upc,
-                                    const uint32_t* __restrict__ starts, const TrackletOut& o) {
+__device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, const KParams& kp,
+                                    const TrackletOut& o) {
     const int R = g.R;
-    L.k = k;
-    const uint32_t p0 = starts[k];
-    const Hit h0 = hits[p0];
-    L.s = (int)(h0.rs / (uint32_t)R);
-    L.r0 = (int)(h0.rs % (uint32_t)R);
-    const int32_t p1 = upc[p0];
-    const Hit h1 = hits[p1];
-    const double x0 = g.row_x[L.r0], x1 = g.row_x[h1.rs % (uint32_t)R];
-    const double ty = ((double)h1.y - (double)h0.y) / (x1 - x0);
-    const double tz = ((double)h1.z - (double)h0.z) / (x1 - x0);
-    L.p[0] = h0.y;
-    L.p[1] = h0.z;
-    L.p[2] = ty / sqrt(1.0 + ty * ty);
-    L.p[3] = tz * sqrt(1.0 - L.p[2] * L.p[2]);
+    L.k = sd.k;
+    L.s = (int)(sd.rs / (uint32_t)R);
+    L.r0 = (int)(sd.rs % (uint32_t)R);
+    L.p[0] = sd.y0;
+    L.p[1] = sd.z0;
+    L.p[2] = sd.s0;
+    L.p[3] = sd.t0;
     L.p[4] = 0.0;
     c0_init(L.C, kp);
-    o.hits[(size_t)k * R] = (int32_t)p0;
+    o.hits[(size_t)sd.k * R] = sd.p0;
     L.nA = 1;
     L.last = L.r0;
-    save_dir(L);
-    L.next = p1;
+    save_dir(L, sd.y0, sd.z0, sd.p0);
+    L.next = sd.p1;
     L.on = true;
     L.fail = false;
     L.miss = 0;
-    L.x = x0;
+    L.x = g.row_x[L.r0];
     L.r = L.r0 + 1;
     L.phase = 1;
 }
 
-__device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                                    const TrackletOut& o) {
+__device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& kp, const TrackletOut& o) {
     const int R = g.R;
     int32_t* slot = o.hits + (size_t)L.k * R;
-    const int32_t pb = slot[L.nA - 1];
-    const Hit hb = hits[pb];
-    L.p[0] = hb.y;
-    L.p[1] = hb.z;
+    const int32_t pb = L.sp->lpos;
+    L.p[0] = L.sp->ly;
+    L.p[1] = L.sp->lz;
     L.p[2] = L.sp->pl[0];
     L.p[3] = L.sp->pl[1];
     L.p[4] = L.sp->pl[2];
@@ -415,7 +420,7 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const KParams& kp, const
         slot[L.nA] = acc;
         ++L.nA;
         L.last = r;
-        save_dir(L);
+        save_dir(L, hy, hz, acc);
     } else {
         L.chi2 += c2;
         L.ndf += 2;
@@ -429,79 +434,103 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const KParams& kp, const
 
 constexpr int kTlBlock = 128;
 
+__global__ __launch_bounds__(kBlock) void k_seeds(GridDesc g, const Hit* __restrict__ hits,
+                                                  const int32_t* __restrict__ upc, const uint32_t* __restrict__ starts,
+                                                  const uint32_t* __restrict__ proc,
+                                                  const uint32_t* __restrict__ counters, Seed* __restrict__ seeds) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= counters[C_N_STARTS]) return;
+    const int R = g.R;
+    Seed sd;
+    sd.k = proc[j];
+    sd.p0 = (int32_t)starts[sd.k];
+    const Hit h0 = hits[sd.p0];
+    sd.p1 = upc[sd.p0];
+    const Hit h1 = hits[sd.p1];
+    sd.rs = h0.rs;
+    sd.y0 = h0.y;
+    sd.z0 = h0.z;
+    sd.pad0 = sd.pad1 = 0;
+    const double x0 = g.row_x[h0.rs % (uint32_t)R], x1 = g.row_x[h1.rs % (uint32_t)R];
+    const double ty = ((double)h1.y - (double)h0.y) / (x1 - x0);
+    const double tz = ((double)h1.z - (double)h0.z) / (x1 - x0);
+    sd.s0 = ty / sqrt(1.0 + ty * ty);
+    sd.t0 = tz * sqrt(1.0 - sd.s0 * sd.s0);
+    seeds[j] = sd;
+}
+
 // Persistent kernel.  Every lane advances its own tracklet by one row per
-// iteration; a lane whose tracklet is finished takes the next one from the
-// queue at once (one atomic per wave for all idle lanes), so long and short
-// tracklets share a wave without idling it.  `chunk` scales how many queue
-// entries an idle lane reserves at a time (1 = one tracklet).
+// iteration; a lane whose tracklet is finished takes the next one at once, so
+// long and short tracklets share a wave without idling it.
 //
-// The queue runs over the processing order `proc` (tracklets grouped by sector
-// and z slab of their start hit), split into one contiguous slice per XCD.
-// Workgroup b is dispatched to XCD b mod 8, drains that XCD's slice first and
-// then steals from the others, so the tracklets an XCD builds at any moment read
-// the hits of one sector and a narrow z range, which its L2 holds.
+// Work comes from the processing order (tracklets grouped by sector and z slab
+// of their start hit), split into one contiguous slice per XCD.  Workgroup b is
+// dispatched to XCD b mod 8 and drains that XCD's slice first, then steals from
+// the others, so the tracklets an XCD builds at any moment read the hits of one
+// sector and a narrow z range, which its L2 holds.  A wave reserves 64 * chunk
+// entries per atomic and hands them to its idle lanes by rank.  A lane that
+// receives an entry issues the loads of its seed record before the row step of
+// the busy lanes and starts pass A after it, so the load latency hides behind
+// that step instead of stalling the wave.
 template <int WAVES>
 __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES))) void k_tracklets(
-    GridDesc g, KParams kp, const Hit* __restrict__ hits,
-                                                        const uint32_t* __restrict__ bin_off,
-                                                        const int32_t* __restrict__ upc,
-                                                        const uint32_t* __restrict__ starts,
-                                                        const uint32_t* __restrict__ proc,
-                                                        uint32_t* __restrict__ counters, TrackletOut o, int chunk) {
+    GridDesc g, KParams kp, const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+    const int32_t* __restrict__ upc, const Seed* __restrict__ seeds, uint32_t* __restrict__ counters, TrackletOut o,
+    int chunk) {
     const uint32_t n = counters[C_N_STARTS];
     const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int xcd = blockIdx.x % kXcd;
+    const uint32_t grab = 64u * (uint32_t)chunk;
     uint32_t n_valid = 0, n_fail = 0;
     __shared__ Spare spare[kTlBlock];
     Lane L;
-    L.phase = 0;
+    L.phase = 0;  // 0 idle, 1 pass A, 2 pass B, 3 retired, 4 seed loading
     L.sp = &spare[threadIdx.x];
-    uint32_t res_next = 0, res_end = 0;  // this lane's reserved range of the processing order
-    int cur = 0;                         // slices this wave has found empty (wave-uniform)
+    uint32_t plo = 0, phi = 0;  // wave-uniform: reserved, not yet handed out
+    uint32_t my_j = 0;
+    int cur = 0;                // slices this wave has found empty (wave-uniform)
     while (true) {
-        // refill lanes without work
-        if (L.phase == 0 && res_next < res_end) start_pass_a(L, proc[res_next++], g, kp, hits, upc, starts, o);
-        const uint64_t need = __ballot(L.phase == 0);
-        if (need) {
-            const uint32_t cnt = (uint32_t)__popcll(need) * (uint32_t)chunk;
-            uint32_t lo = 0, hi = 0, base = 0;
-            bool got = false;
-            while (cur < kXcd) {
+        uint64_t need = __ballot(L.phase == 0);
+        while (need && cur < kXcd) {
+            if (plo == phi) {
                 const int x = (xcd + cur) % kXcd;
-                lo = (uint32_t)((uint64_t)n * x / kXcd);
-                hi = (uint32_t)((uint64_t)n * (x + 1) / kXcd);
+                const uint32_t lo = (uint32_t)((uint64_t)n * x / kXcd);
+                const uint32_t hi = (uint32_t)((uint64_t)n * (x + 1) / kXcd);
                 uint32_t b = 0;
-                if (lane == 0) b = atomicAdd(&counters[C_QUEUE_XCD0 + x], cnt);
-                base = __shfl(b, 0, 64);
-                if (lo + base < hi) {
-                    got = true;
-                    break;
+                if (lane == 0) b = atomicAdd(&counters[C_QUEUE_XCD0 + x], grab);
+                b = __shfl(b, 0, 64);
+                if (lo + b >= hi || b >= hi - lo) {
+                    ++cur;
+                    continue;
                 }
-                ++cur;
+                plo = lo + b;
+                phi = hi - plo < grab ? hi : plo + grab;
             }
-            if (L.phase == 0) {
-                if (got) {
-                    const uint64_t below = lane ? (need & (~0ull >> (64 - lane))) : 0ull;
-                    const uint32_t mine = lo + base + (uint32_t)__popcll(below) * (uint32_t)chunk;
-                    res_next = mine;
-                    res_end = mine + (uint32_t)chunk < hi ? mine + (uint32_t)chunk : hi;
-                }
-                if (got && res_next < res_end)
-                    start_pass_a(L, proc[res_next++], g, kp, hits, upc, starts, o);
-                else if (!got)
-                    L.phase = 3;
+            const uint32_t avail = phi - plo;
+            const uint32_t rank = (uint32_t)__popcll(need & below);
+            if (((need >> lane) & 1ull) && rank < avail) {
+                my_j = plo + rank;
+                L.phase = 4;
             }
+            const uint32_t take = (uint32_t)__popcll(need) < avail ? (uint32_t)__popcll(need) : avail;
+            plo += take;
+            need = __ballot(L.phase == 0);
         }
-    if (!__ballot(L.phase == 1 || L.phase == 2)) break;
+        if (L.phase == 0) L.phase = 3;  // every slice is drained
+        if (!__ballot(L.phase == 1 || L.phase == 2 || L.phase == 4)) break;
+        Seed sd;
+        if (L.phase == 4) sd = seeds[my_j];
         if ((L.phase == 1 || L.phase == 2) && step(L, g, kp, hits, bin_off, upc, o)) {
             if (L.phase == 1 && !L.fail) {
-                start_pass_b(L, g, kp, hits, o);
+                start_pass_b(L, g, kp, o);
             } else {
                 const uint32_t f = finish(L, kp, o);
                 n_valid += f & 1u;
                 n_fail += (f >> 1) & 1u;
             }
         }
+        if (L.phase == 4) start_pass_a(L, sd, g, kp, o);
     }
     __shared__ uint32_t sv[kTlBlock / 64], sf[kTlBlock / 64];
     const uint32_t wv = wave_sum(n_valid), wf = wave_sum(n_fail);
@@ -523,17 +552,23 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
 
 }  // namespace
 
+size_t seed_bytes() { return sizeof(Seed); }
+
 void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, uint32_t* counters,
-                     const TrackletOut& o, int grid_blocks, int chunk, int waves, hipStream_t s) {
+                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, void* seeds,
+                     uint32_t* counters, const TrackletOut& o, int64_t t_max, int grid_blocks, int chunk, int waves,
+                     hipStream_t s) {
+    Seed* sd = (Seed*)seeds;
+    const unsigned nb = (unsigned)((t_max + kBlock - 1) / kBlock > 0 ? (t_max + kBlock - 1) / kBlock : 1);
+    k_seeds<<<nb, kBlock, 0, s>>>(g, hits, upc, starts, proc, counters, sd);
     grid_blocks = (grid_blocks + kXcd - 1) / kXcd * kXcd;
     // occupancy variants: 2 waves per SIMD keeps the whole state in registers, 3 and 4 spill some of it
     if (waves >= 4)
-        k_tracklets<4><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+        k_tracklets<4><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
     else if (waves == 3)
-        k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+        k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
     else
-        k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, starts, proc, counters, o, chunk);
+        k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
 }
 
 }  // namespace tpc

@@ -2,17 +2,22 @@
 
 The scorer (MLP 12-64-64-1, BF16 weights, FP32 accumulation) prunes candidate neighbour pairs
 before the cellular automaton chooses links.  It is trained on the GPU by the library's own
-forward/backward kernels (``tpc_mlp_train``) on truth-labelled window triplets of one-sector
+forward/backward kernels (``tpc_mlp_train``) on truth-labelled window triplets of synthetic
 events; the plain finder is both the fallback and the judge of the efficiency the pruning costs.
 
-    python -m paper_1910_12214_amd.scorer train --out scorer.npz
+    python -m paper_1910_12214_amd.scorer train --set sector     # -> scorer_sector200.npz
+    python -m paper_1910_12214_amd.scorer train --set pbpb       # -> scorer_pbpb.npz
 
-Recipe: training events = one-sector 200-helix events with seeds 1..200 (every window candidate
-triplet, label 1 iff the three clusters are consecutive crossings of one leg; subsampled to
-10^7 if there are more), He-uniform initialisation from a seeded generator, Adam (lr 1e-3,
-betas 0.9/0.999) for 5 epochs of batch 4096; the threshold tau (on the logit) is the largest
-candidate whose efficiency on validation seeds 201..210 is within 0.5% of the plain finder's;
-held-out test seeds 1001..1020.
+Training sets (every window candidate triplet of the events, label 1 iff the three clusters are
+consecutive crossings of one leg, uniformly subsampled to 10^7 if there are more):
+  sector: one-sector 200-helix events, training seeds 1..200, threshold seeds 201..210, held-out
+          test seeds 1001..1020;
+  pbpb:   central Pb-Pb-like full-TPC events (the benchmark event's generator), training seeds
+          0x10001..0x10008, threshold seeds 0x20001..0x20002, test seeds 0x30001..0x30002 — all
+          disjoint from the benchmark event's seed and its validation seed.
+He-uniform initialisation from a seeded generator, Adam (lr 1e-3, betas 0.9/0.999) for 5 epochs
+of batch 4096; the threshold tau (on the logit) is the largest candidate whose efficiency on the
+threshold seeds is within 0.5% of the plain finder's.
 """
 from __future__ import annotations
 
@@ -31,9 +36,34 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 DEFAULT_CKPT = os.path.join(_HERE, "scorer_sector200.npz")
+PBPB_CKPT = os.path.join(_HERE, "scorer_pbpb.npz")
 TRAIN_SEEDS = range(1, 201)
 VAL_SEEDS = range(201, 211)
 TEST_SEEDS = range(1001, 1021)
+
+
+def _sector_events(seeds):
+    import synth
+
+    return [synth.sector_event(s) for s in seeds]
+
+
+def _pbpb_events(seeds):
+    import dataclasses
+
+    import synth
+
+    return [dataclasses.replace(synth.PBPB_EVENT, name=f"pbpb_event_5000_s{s:#x}", seed=s) for s in seeds]
+
+
+# name -> (training, threshold, test workloads, checkpoint, description)
+SETS = {
+    "sector": (lambda: _sector_events(TRAIN_SEEDS), lambda: _sector_events(VAL_SEEDS),
+               lambda: _sector_events(TEST_SEEDS), DEFAULT_CKPT, "one-sector 200-helix events, seeds 1-200"),
+    "pbpb": (lambda: _pbpb_events(range(0x10001, 0x10009)), lambda: _pbpb_events(range(0x20001, 0x20003)),
+             lambda: _pbpb_events(range(0x30001, 0x30003)), PBPB_CKPT,
+             "central Pb-Pb-like full-TPC events, seeds 0x10001-0x10008"),
+}
 MAX_TRIPLETS = 10_000_000
 N_PARAMS = 5057
 
@@ -60,16 +90,15 @@ def event_tensors(ev):
     return _dev(ev.y), _dev(ev.z), _dev(ev.row), _dev(ev.sector)
 
 
-def training_set(ctx, seeds=TRAIN_SEEDS, max_triplets=MAX_TRIPLETS, subsample_seed=77):
-    """Features and labels of every window triplet of the given one-sector events (GPU tensors)."""
+def training_set(ctx, workloads=None, max_triplets=MAX_TRIPLETS, subsample_seed=77):
+    """Features and labels of every window triplet of the given events (GPU tensors)."""
     import torch
 
     import synth
     from synth import metrics
 
     feats, labels = [], []
-    for s in seeds:
-        w = synth.sector_event(s)
+    for w in workloads if workloads is not None else _sector_events(TRAIN_SEEDS):
         ev = synth.generate(w)
         trip, f = ctx.triplets(*event_tensors(ev), synth.geometry(w), synth.TRACKER_PARAMS)
         t = trip.cpu().numpy().astype(np.int64)
@@ -109,8 +138,9 @@ def train(ctx, F, Y, epochs=5, batch=4096, lr=1e-3, seed=5, log=None):
     return params.cpu().numpy(), hist
 
 
-def evaluate(ctx, seeds, params=None, tau=0.0, repeat=3):
-    """Aggregate efficiency / fake / clone rates and tracking time over one-sector events."""
+def evaluate(ctx, workloads, params=None, tau=0.0, repeat=3):
+    """Aggregate efficiency / fake / clone rates and tracking time over events (workloads, or
+    one-sector event seeds)."""
     import torch
 
     import synth
@@ -120,8 +150,9 @@ def evaluate(ctx, seeds, params=None, tau=0.0, repeat=3):
     tot = dict(n_findable=0, n_matched_findable=0, n_tracks=0, n_good=0, clones=0, clusters=0, ms=0.0,
                tracklets=0, pairs=0, kept=0, links=0)
     mlp = _dev(params) if params is not None else None
-    for s in seeds:
-        w = synth.sector_event(s)
+    for w in workloads:
+        if isinstance(w, int):
+            w = synth.sector_event(w)
         ev = synth.generate(w)
         ten = event_tensors(ev)
         geom = synth.geometry(w)
@@ -151,12 +182,13 @@ def evaluate(ctx, seeds, params=None, tau=0.0, repeat=3):
     return tot
 
 
-def choose_tau(ctx, params, seeds=VAL_SEEDS, max_loss=0.005, log=None):
+def choose_tau(ctx, params, workloads=None, max_loss=0.005, log=None):
     """Largest logit threshold whose validation efficiency is within max_loss of the plain finder's."""
-    plain = evaluate(ctx, seeds, repeat=1)
+    workloads = workloads if workloads is not None else _sector_events(VAL_SEEDS)
+    plain = evaluate(ctx, workloads, repeat=1)
     best = None
     for tau in np.arange(-8.0, 4.01, 0.5):
-        r = evaluate(ctx, seeds, params, float(tau), repeat=1)
+        r = evaluate(ctx, workloads, params, float(tau), repeat=1)
         ok = plain["efficiency"] - r["efficiency"] <= max_loss
         if log:
             log(f"tau {tau:+.1f}: eff {r['efficiency']:.4f} (plain {plain['efficiency']:.4f}) "
@@ -170,7 +202,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--out", default=DEFAULT_CKPT)
+    t.add_argument("--set", choices=sorted(SETS), default="sector", help="training/threshold/test events")
+    t.add_argument("--out", default=None, help="checkpoint (default: the set's file in the package)")
     t.add_argument("--epochs", type=int, default=5)
     t.add_argument("--report", default=None, help="write the training/validation/test summary as JSON")
     e = sub.add_parser("eval")
@@ -184,27 +217,31 @@ def main(argv=None):
 
     ctx = tpcca.Context(0)
     if args.cmd == "train":
+        tr, va, te, ckpt, desc = SETS[args.set]
+        out_path = args.out or ckpt
         t0 = time.perf_counter()
-        F, Y = training_set(ctx)
-        log(f"training set: {F.shape[0]} triplets from {len(TRAIN_SEEDS)} events, positives "
+        train_w = tr()
+        F, Y = training_set(ctx, train_w)
+        log(f"training set: {F.shape[0]} triplets from {len(train_w)} events, positives "
             f"{float(Y.float().mean()):.3f} ({time.perf_counter() - t0:.1f} s)")
         t0 = time.perf_counter()
         params, hist = train(ctx, F, Y, epochs=args.epochs, log=log)
         log(f"trained in {time.perf_counter() - t0:.2f} s")
-        tau, plain_val = choose_tau(ctx, params, log=log)
+        tau, plain_val = choose_tau(ctx, params, va(), log=log)
         log(f"tau = {tau}")
-        test_plain = evaluate(ctx, TEST_SEEDS)
-        test_mlp = evaluate(ctx, TEST_SEEDS, params, tau)
-        rep = {"n_train_triplets": int(F.shape[0]), "loss_per_epoch": hist, "tau_logit": tau,
+        test_plain = evaluate(ctx, te())
+        test_mlp = evaluate(ctx, te(), params, tau)
+        rep = {"set": args.set, "trained_on": desc, "n_train_triplets": int(F.shape[0]), "loss_per_epoch": hist,
+               "tau_logit": tau,
                "val_plain_efficiency": plain_val["efficiency"],
                "test_plain": {k: v for k, v in test_plain.items()}, "test_pruned": {k: v for k, v in test_mlp.items()}}
         log("test plain ", json.dumps({k: round(v, 5) if isinstance(v, float) else v for k, v in test_plain.items()}))
         log("test pruned", json.dumps({k: round(v, 5) if isinstance(v, float) else v for k, v in test_mlp.items()}))
-        np.savez(args.out, params=params, tau_logit=np.float64(tau), loss_per_epoch=np.array(hist),
-                 n_train_triplets=np.int64(F.shape[0]))
+        np.savez(out_path, params=params, tau_logit=np.float64(tau), loss_per_epoch=np.array(hist),
+                 n_train_triplets=np.int64(F.shape[0]), trained_on=np.array(desc))
         if args.report:
             json.dump(rep, open(args.report, "w"), indent=1)
-        log("wrote", args.out)
+        log("wrote", out_path)
     else:
         ck = np.load(args.ckpt)
         test_plain = evaluate(ctx, TEST_SEEDS)
@@ -218,6 +255,12 @@ def load(path: str = DEFAULT_CKPT):
     """(params float32[5057], tau_logit) of a saved scorer."""
     ck = np.load(path)
     return ck["params"].astype(np.float32), float(ck["tau_logit"])
+
+
+def trained_on(path: str = DEFAULT_CKPT) -> str:
+    """Description of the events a saved scorer was trained on."""
+    ck = np.load(path)
+    return str(ck["trained_on"]) if "trained_on" in ck.files else SETS["sector"][4]
 
 
 if __name__ == "__main__":
