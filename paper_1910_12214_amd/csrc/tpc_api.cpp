@@ -198,7 +198,7 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
 
 struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
-    uint32_t *tl_slot, *proc, *slab_cnt;
+    uint32_t *tl_slot, *proc, *slab_cnt, *nb_ovf;
     void* seeds;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
@@ -240,6 +240,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(slab_cnt, "slab_cnt", 4 * ((int64_t)S * slab_count(pr.g, pr.slab_bins) * R + 1));
     B(proc, "proc", 4 * T);
     B(seeds, "tl_seeds", seed_bytes() * T);
+    B(nb_ovf, "nb_ovf", 4 * nb_overflow_entries(n));
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
     B(hit_off, "hit_off", 4 * T);
@@ -301,7 +302,7 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     mk.mark();
     // a2 neighbours (a3: with the learned scorer fused), a4/a5 cleaning and starts
     if (mlp_q)
-        neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.counters, st);
+        neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.nb_ovf, st);
     else
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();

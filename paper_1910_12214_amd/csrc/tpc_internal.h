@@ -64,6 +64,7 @@ enum Counter {  // device scratch counters (uint32)
     C_N_PAIRS_KEPT,
     C_N_VALID_CLU,
     C_QUEUE_XCD0,  // 8 per-XCD tracklet queues follow
+    C_NB_OVF = C_QUEUE_XCD0 + 8,  // waves on the fused neighbour kernel's overflow list
     C_N_COUNTERS = 32
 };
 
@@ -196,8 +197,10 @@ void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s)
 size_t mlp_q_floats();
 void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
 void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s);
+// ovf: [nb_overflow_entries(n_max)] wave indices (counted in counters[C_NB_OVF])
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
-                    const uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* cnt, hipStream_t s);
+                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, hipStream_t s);
+size_t nb_overflow_entries(int64_t n_max);
 void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                    const uint32_t* counters, uint32_t* cnt, hipStream_t s);
 void triplet_write(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,

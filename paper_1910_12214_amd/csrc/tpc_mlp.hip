@@ -366,22 +366,195 @@ __global__ __launch_bounds__(kBlock) void k_trip_write(GridDesc g, KParams kp, c
 }
 
 // ------------------------------------------------- fused neighbour finding with pruning
+// Pair-parallel.  Lane = hit: enumerate the up and down window candidates once
+// (linear in their number) into a wave-level LDS list; the wave's candidate
+// pairs are numbered by a prefix sum of nu * nd.  Lane = pair, 64 per round:
+// features from the list, four 16-pair MFMA tiles, and the plain criterion D in
+// FP64; a pair survives if its logit >= tau and D <= cut.  Lane = hit again: the
+// best surviving pair over this round's slots of the hit (smallest D, ties by
+// (id_up, id_down)).  Work per round is the same for every lane whatever the
+// candidate counts of individual hits.  A wave whose candidates do not fit the
+// list goes to an overflow list for the per-lane kernel.
+constexpr int kPW = 4;        // waves per block
+constexpr int kCapC = 512;    // candidate records per wave (10-bit offsets and counts)
+
+struct alignas(16) Cand {
+    float y, z;
+    uint32_t id;
+    int32_t pos;
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kPW) void k_nb_pairs(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                       const uint32_t* __restrict__ bin_off,
+                                                       uint32_t* __restrict__ counters, const uint8_t* __restrict__ q,
+                                                       int32_t* __restrict__ up, int32_t* __restrict__ dn,
+                                                       uint32_t* __restrict__ ovf) {
+    __shared__ Cand cand_all[kPW][kCapC];
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kPW][64 * 40];
+    __shared__ float lg_all[kPW][64];
+    __shared__ double dv_all[kPW][64];
+    __shared__ uint32_t ps0_all[kPW][64], meta_all[kPW][64];
+    __shared__ float ym_all[kPW][64], zm_all[kPW][64];
+    __shared__ int32_t r_all[kPW][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Cand* cand = cand_all[w];
+    uint16_t* xs = xs_all[w];
+    float* lg = lg_all[w];
+    double* dv = dv_all[w];
+    uint32_t* ps0s = ps0_all[w];
+    uint32_t* meta = meta_all[w];
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t wave = blockIdx.x * kPW + w;
+    const uint32_t p = wave * 64 + lane;
+    const bool act = p < n;
+    Hit m;
+    m.y = m.z = 0.f;
+    Win win;
+    win.ok = false;
+    win.r = 1;
+    int nu = 0, nd = 0;
+    if (act) {
+        m = hits[p];
+        win = window_of(g, kp, m);
+        if (win.ok) {
+            nu = count_window(g, hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu);
+            nd = count_window(g, hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd);
+        }
+    }
+    const uint32_t np = (uint32_t)(nu * nd), nc = np ? (uint32_t)(nu + nd) : 0u;
+    uint32_t ic = nc, ip = np;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t a = __shfl_up(ic, d, 64), b = __shfl_up(ip, d, 64);
+        if (lane >= d) {
+            ic += a;
+            ip += b;
+        }
+    }
+    const uint32_t ctot = __shfl(ic, 63, 64), ptot = __shfl(ip, 63, 64);
+    if (ctot > (uint32_t)kCapC) {  // wave-uniform
+        if (lane == 0) ovf[atomicAdd(&counters[C_NB_OVF], 1u)] = wave;
+        return;
+    }
+    const uint32_t coff = ic - nc, pofs = ip - np;
+    if (np) {
+        uint32_t j = coff;
+        for_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu,
+                   [&](uint32_t k, const Hit& h) { cand[j++] = Cand{h.y, h.z, h.id, (int32_t)k}; });
+        for_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd,
+                   [&](uint32_t k, const Hit& h) { cand[j++] = Cand{h.y, h.z, h.id, (int32_t)k}; });
+    }
+    ps0s[lane] = pofs;
+    meta[lane] = coff | ((uint32_t)nu << 10) | ((uint32_t)nd << 20);
+    ym_all[w][lane] = m.y;
+    zm_all[w][lane] = m.z;
+    r_all[w][lane] = win.r;
+    wave_sync();
+    double best = 1e300;
+    uint32_t bu_id = 0xFFFFFFFFu, bd_id = 0xFFFFFFFFu;
+    int32_t bu = -1, bd = -1;
+    uint32_t kept = 0;
+    if (ptot) {
+        Frag F;
+        load_frag(q, F);
+        const float wy = (float)kp.win_y, wz = (float)kp.win_z;
+        for (uint32_t base = 0; base < ptot; base += 64) {
+            const uint32_t t = base + (uint32_t)lane;
+            const bool has = t < ptot;
+            float f[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) f[k] = 0.f;
+            double Dv = -1.0;
+            if (has) {
+                int lo = 0, hi = 63;  // owner: the last hit whose first pair slot is <= t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (ps0s[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t mt = meta[lo];
+                const uint32_t co = mt & 1023u, nuh = (mt >> 10) & 1023u, ndh = mt >> 20;
+                const uint32_t idx = t - ps0s[lo];
+                const uint32_t iu = idx / ndh, id = idx - iu * ndh;
+                const Cand cu = cand[co + iu], cd = cand[co + nuh + id];
+                const int r = r_all[w][lo];
+                const float xd = g.row_x[r - 1], xm = g.row_x[r], xu = g.row_x[r + 1];
+                const float ymh = ym_all[w][lo], zmh = zm_all[w][lo];
+                features(xd, cd.y, cd.z, xm, ymh, zmh, xu, cu.y, cu.z, wy, wz, (int)nuh, (int)ndh, f);
+                const double wgt = ((double)xm - (double)xd) / ((double)xu - (double)xd);
+                const double yu = cu.y, zu = cu.z, yd = cd.y, zd = cd.z;
+                const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
+                const double ym = ymh, zm = zmh;
+                Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
+            }
+            stage_row(xs + lane * 40, f);
+            wave_sync();
+            const uint32_t in_round = ptot - base < 64u ? ptot - base : 64u;
+            for (uint32_t T = 0; 16 * T < in_round; ++T) {
+                Act A;
+                forward_tile(F, xs + T * 16 * 40, A);
+                if (lane < 16) lg[16 * T + lane] = A.z3;
+            }
+            wave_sync();
+            if (has) {
+                const bool keep = (double)lg[lane] >= kp.tau;
+                kept += keep;
+                dv[lane] = (keep && Dv <= kp.nb_cut) ? Dv : -1.0;
+            }
+            wave_sync();
+            // this hit's slots in the round
+            if (np && pofs < base + 64 && pofs + np > base) {
+                const uint32_t s0 = pofs > base ? pofs : base, s1 = pofs + np < base + 64 ? pofs + np : base + 64;
+                for (uint32_t sl = s0; sl < s1; ++sl) {
+                    const double d = dv[sl - base];
+                    if (!(d >= 0.0)) continue;
+                    const uint32_t idx = sl - pofs;
+                    const uint32_t iu = idx / (uint32_t)nd, id = idx - iu * (uint32_t)nd;
+                    const Cand cu = cand[coff + iu], cd = cand[coff + (uint32_t)nu + id];
+                    if (d < best || (d == best && (cu.id < bu_id || (cu.id == bu_id && cd.id < bd_id)))) {
+                        best = d;
+                        bu = cu.pos;
+                        bd = cd.pos;
+                        bu_id = cu.id;
+                        bd_id = cd.id;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+    if (act) {
+        up[p] = bu;
+        dn[p] = bd;
+    }
+    const uint32_t linked = bu >= 0;
+    uint32_t a = wave_sum(np), b = wave_sum(kept), c = wave_sum(linked);
+    if (lane == 0) {
+        if (a) atomicAdd(&counters[C_N_PAIRS], a);
+        if (b) atomicAdd(&counters[C_N_PAIRS_KEPT], b);
+        if (c) atomicAdd(&counters[C_N_LINKS_RAW], c);
+    }
+}
+
+// ------------------------------------------------- fused neighbour finding with pruning
 constexpr int kNbWaves = 4;
 constexpr int kCap = 128;  // staged pairs per wave and round
 
-__global__ __launch_bounds__(64 * kNbWaves) void k_neighbours_mlp(GridDesc g, KParams kp, const Hit* __restrict__ hits,
-                                                                  const uint32_t* __restrict__ bin_off,
-                                                                  const uint32_t* __restrict__ counters,
-                                                                  const uint8_t* __restrict__ q,
-                                                                  int32_t* __restrict__ up, int32_t* __restrict__ dn,
-                                                                  uint32_t* __restrict__ cnt) {
-    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kNbWaves][kCap * 40];
-    __shared__ float lg_all[kNbWaves][kCap];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* xs = xs_all[w];
-    float* lg = lg_all[w];
-    const uint32_t n = counters[C_N_VALID_CLU];
-    const uint32_t p = (blockIdx.x * kNbWaves + w) * 64 + lane;
+// One wave's 64 hits by per-lane enumeration (staged pairs in rounds of kCap);
+// used for the waves whose window candidates do not fit the pair-parallel
+// kernel's LDS list.
+__device__ void nb_mlp_wave(uint32_t wave, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+                            const uint32_t* __restrict__ bin_off, uint32_t n, const uint8_t* __restrict__ q,
+                            int32_t* __restrict__ up, int32_t* __restrict__ dn, uint32_t* __restrict__ cnt,
+                            uint16_t* xs, float* lg) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t p = wave * 64 + lane;
     const bool act = p < n;
     Hit m;
     Win win;
@@ -483,6 +656,20 @@ __global__ __launch_bounds__(64 * kNbWaves) void k_neighbours_mlp(GridDesc g, KP
         if (b) atomicAdd(&cnt[C_N_PAIRS_KEPT], b);
         if (c) atomicAdd(&cnt[C_N_LINKS_RAW], c);
     }
+}
+
+__global__ __launch_bounds__(64 * kNbWaves) void k_nb_mlp_fallback(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                                   const uint32_t* __restrict__ bin_off,
+                                                                   uint32_t* __restrict__ counters,
+                                                                   const uint8_t* __restrict__ q,
+                                                                   const uint32_t* __restrict__ ovf,
+                                                                   int32_t* __restrict__ up, int32_t* __restrict__ dn) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kNbWaves][kCap * 40];
+    __shared__ float lg_all[kNbWaves][kCap];
+    const int w = threadIdx.x >> 6;
+    const uint32_t n = counters[C_N_VALID_CLU], n_ovf = counters[C_NB_OVF];
+    for (uint32_t i = blockIdx.x * kNbWaves + w; i < n_ovf; i += gridDim.x * kNbWaves)
+        nb_mlp_wave(ovf[i], g, kp, hits, bin_off, n, q, up, dn, counters, xs_all[w], lg_all[w]);
 }
 
 // ------------------------------------------------------------ training
@@ -701,11 +888,15 @@ void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hip
 }
 
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
-                    const uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* cnt, hipStream_t s) {
+                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, hipStream_t s) {
     const int64_t waves = (n_max + 63) / 64;
-    const unsigned nb = (unsigned)((waves + kNbWaves - 1) / kNbWaves > 0 ? (waves + kNbWaves - 1) / kNbWaves : 1);
-    k_neighbours_mlp<<<nb, 64 * kNbWaves, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, up, dn, cnt);
+    const unsigned nb = (unsigned)((waves + kPW - 1) / kPW > 0 ? (waves + kPW - 1) / kPW : 1);
+    k_nb_pairs<<<nb, 64 * kPW, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, up, dn, ovf);
+    // waves whose candidates overflowed the list (normally none): grid-stride over the overflow list
+    k_nb_mlp_fallback<<<64, 64 * kNbWaves, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, ovf, up, dn);
 }
+
+size_t nb_overflow_entries(int64_t n_max) { return (size_t)((n_max + 63) / 64 + 1); }
 
 void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                    const uint32_t* counters, uint32_t* cnt, hipStream_t s) {
