@@ -79,13 +79,15 @@ __device__ inline void asin_over(double u, double& g, double& gp) {
 // symmetric element (i, j) of the packed lower triangle
 #define CS(i, j) C[((i) >= (j)) ? ((i) * ((i) + 1) / 2 + (j)) : ((j) * ((j) + 1) / 2 + (i))]
 
-// Propagate state and covariance from x0 to x1.  false = |sin phi| reached s_max.
+// Propagate state and covariance from x0 to x1.  false = |sin phi| reached s_max;
+// then p and C hold meaningless values (the caller ends the pass and discards
+// them), which keeps this free of branches.
 __device__ inline bool propagate(double p[5], double C[15], double x0, double x1, const KParams& kp) {
     const double dx = x1 - x0;
     const double k = kp.kq * p[4];
     const double s0 = p[2], s1 = s0 + k * dx;
-    if (!(fabs(s1) < kp.s_max) || !(fabs(s0) < kp.s_max)) return false;
-    if (dx == 0.0) return true;
+    const bool ok = fabs(s1) < kp.s_max && fabs(s0) < kp.s_max;
+    if (dx == 0.0) return ok;
     const double c0 = sqrt_pos(1.0 - s0 * s0), c1 = sqrt_pos(1.0 - s1 * s1);
     const double A = s0 + s1, B = c0 + c1;
     const double iB = rcp(B);
@@ -132,7 +134,7 @@ __device__ inline bool propagate(double p[5], double C[15], double x0, double x1
 #pragma unroll
         for (int j = 0; j <= i; ++j) C[i * (i + 1) / 2 + j] = rr[j];
     }
-    return true;
+    return ok;
 }
 
 __device__ inline double chi2_of(const double p[5], const double C[15], double my, double mz, const KParams& kp) {
@@ -166,17 +168,39 @@ __device__ inline bool kf_update(double p[5], double C[15], double my, double mz
         for (int j = 0; j <= i; ++j) C[i * (i + 1) / 2 + j] -= K0[i] * c0[j] + K1[i] * c1[j];
     bool ok = det > 0.0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) ok = ok && isfinite(p[i]);
+    for (int i = 0; i < 5; ++i) ok &= (bool)isfinite(p[i]);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) ok = ok && isfinite(C[i]);
-    ok = ok && C[0] > 0.0 && C[2] > 0.0 && C[5] > 0.0 && C[9] > 0.0 && C[14] > 0.0;
+    for (int i = 0; i < 15; ++i) ok &= (bool)isfinite(C[i]);
+    ok &= (C[0] > 0.0) & (C[2] > 0.0) & (C[5] > 0.0) & (C[9] > 0.0) & (C[14] > 0.0);
     return ok;
 }
 
 // Nearest hit in one row: smallest chi2 <= cut inside the ellipse's box, ties by
 // cluster id; -1 if none.  The winner's coordinates come back in (hy, hz).  Loads
-// run one step ahead: the next z row's bin bounds while this row's hits are
-// scanned, and the next candidate while the current one is tested.
+// run ahead of their use: the next z row's bin bounds while this row's hits are
+// tested, and the first four candidates of a bin range in one go (a range rarely
+// holds more), so a row search waits for two loads in sequence, not one per hit.
+struct Best {
+    double c2;
+    uint32_t id;
+    int32_t pos;
+    float y, z;
+};
+
+__device__ inline void consider(Best& b, const Hit& h, uint32_t k, bool valid, const double p[5], double bx,
+                                double bz, double i00, double i01, double i11, double cut) {
+    const double ry = (double)h.y - p[0], rz = (double)h.z - p[1];
+    const double c2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
+    // bitwise, not short-circuit: no branches inside the candidate loop
+    const bool take = valid & (fabs(ry) <= bx) & (fabs(rz) <= bz) & (c2 <= cut) &
+                      ((c2 < b.c2) | ((c2 == b.c2) & (h.id < b.id)));
+    b.c2 = take ? c2 : b.c2;
+    b.id = take ? h.id : b.id;
+    b.pos = take ? (int32_t)k : b.pos;
+    b.y = take ? h.y : b.y;
+    b.z = take ? h.z : b.z;
+}
+
 __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
                                      const uint32_t* __restrict__ bin_off, const RowBins& rb, const double p[5],
                                      const double C[15], float& hy, float& hz) {
@@ -188,9 +212,8 @@ __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const
     if (!(det > 0.0) || !isfinite(bx) || !isfinite(bz)) return -1;
     const BinRange br = bin_range(g, rb, p[0] - bx, p[0] + bx, p[1] - bz, p[1] + bz);
     if (br.empty) return -1;
-    double best = 1e300;
-    uint32_t best_id = 0xFFFFFFFFu;
-    int32_t best_pos = -1;
+    Best b{1e300, 0xFFFFFFFFu, -1, hy, hz};
+    const double cut = kp.fol_cut;
     uint32_t zrow = br.base + br.iz0 * br.ny;
     uint32_t kb = bin_off[zrow + br.iy0], ke = bin_off[zrow + br.iy1 + 1];
     for (int iz = br.iz0; iz <= br.iz1; ++iz) {
@@ -201,27 +224,23 @@ __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const
             ne = bin_off[zrow + br.iy1 + 1];
         }
         if (kb < ke) {
-            Hit h = hits[kb];
-            for (uint32_t k = kb; k < ke; ++k) {
-                const Hit hn = hits[k + 1 < ke ? k + 1 : k];
-                const double ry = (double)h.y - p[0], rz = (double)h.z - p[1];
-                if (fabs(ry) <= bx && fabs(rz) <= bz) {
-                    const double c2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
-                    if (c2 <= kp.fol_cut && (c2 < best || (c2 == best && h.id < best_id))) {
-                        best = c2;
-                        best_id = h.id;
-                        best_pos = (int32_t)k;
-                        hy = h.y;
-                        hz = h.z;
-                    }
-                }
-                h = hn;
-            }
+            const uint32_t last = ke - 1;
+            const Hit h0 = hits[kb];
+            const Hit h1 = hits[kb + 1 < last ? kb + 1 : last];
+            const Hit h2 = hits[kb + 2 < last ? kb + 2 : last];
+            const Hit h3 = hits[kb + 3 < last ? kb + 3 : last];
+            consider(b, h0, kb, true, p, bx, bz, i00, i01, i11, cut);
+            consider(b, h1, kb + 1, kb + 1 < ke, p, bx, bz, i00, i01, i11, cut);
+            consider(b, h2, kb + 2, kb + 2 < ke, p, bx, bz, i00, i01, i11, cut);
+            consider(b, h3, kb + 3, kb + 3 < ke, p, bx, bz, i00, i01, i11, cut);
+            for (uint32_t k = kb + 4; k < ke; ++k) consider(b, hits[k], k, true, p, bx, bz, i00, i01, i11, cut);
         }
         kb = nb;
         ke = ne;
     }
-    return best_pos;
+    hy = b.y;
+    hz = b.z;
+    return b.pos;
 }
 
 __device__ inline void c0_init(double C[15], const KParams& kp) {
@@ -232,6 +251,20 @@ __device__ inline void c0_init(double C[15], const KParams& kp) {
     C[5] = kp.c0s;
     C[9] = kp.c0t;
     C[14] = kp.c0q;
+}
+
+// Per-row tables in LDS (the same for every sector: bins of sector s, row r start
+// at s * bins_per_sector + base[r]).
+struct RowTab {
+    const float* x;
+    const float* ymin;
+    const int32_t* ny;
+    const uint32_t* base;
+    uint32_t per_sector;
+};
+
+__device__ inline RowBins row_bins_lds(const RowTab& rt, int s, int r) {
+    return RowBins{(double)rt.ymin[r], rt.ny[r], (uint32_t)s * rt.per_sector + rt.base[r]};
 }
 
 // Per-lane tracklet state between row steps.
@@ -259,6 +292,7 @@ struct Lane {
     uint32_t k;
     int s, r0, r, last, inner, nA, nB, ia, miss, ndf;
     int32_t next;
+    int32_t pf;  // pass B: position of pass A's hit number ia (loaded one step ahead)
     bool on, fail;
     double x, chi2;
     double p[5], C[15];
@@ -281,7 +315,7 @@ __device__ inline void save_dir(Lane& L, float hy, float hz, int32_t pos) {
     L.sp->lpos = pos;
 }
 
-__device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, const KParams& kp,
+__device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, const RowTab& rt, const KParams& kp,
                                     const TrackletOut& o) {
     const int R = g.R;
     L.k = sd.k;
@@ -301,12 +335,13 @@ __device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, 
     L.on = true;
     L.fail = false;
     L.miss = 0;
-    L.x = g.row_x[L.r0];
+    L.x = rt.x[L.r0];
     L.r = L.r0 + 1;
     L.phase = 1;
 }
 
-__device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& kp, const TrackletOut& o) {
+__device__ inline void start_pass_b(Lane& L, const GridDesc& g, const RowTab& rt, const KParams& kp,
+                                    const TrackletOut& o) {
     const int R = g.R;
     int32_t* slot = o.hits + (size_t)L.k * R;
     const int32_t pb = L.sp->lpos;
@@ -322,9 +357,10 @@ __device__ inline void start_pass_b(Lane& L, const GridDesc& g, const KParams& k
     L.chi2 = 0.0;
     L.ndf = 0;
     save_inner(L);
-    L.x = g.row_x[L.last];
+    L.x = rt.x[L.last];
     L.miss = 0;
     L.ia = L.nA - 2;
+    L.pf = L.ia >= 0 ? slot[L.ia] : -1;
     L.r = L.last - 1;
     L.phase = 2;
 }
@@ -341,9 +377,15 @@ __device__ inline uint32_t finish(Lane& L, const KParams& kp, const TrackletOut&
     o.row_ref[k] = L.phase == 2 ? L.inner : L.last;
     o.flags[k] = (valid ? 1u : 0u) | (fail ? 2u : 0u);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) o.state[(size_t)k * 5 + i] = fail ? 0.f : L.sp->pin[i];
+    for (int i = 0; i < 5; ++i) {
+        const float v = L.sp->pin[i];
+        o.state[(size_t)k * 5 + i] = fail ? 0.f : v;
+    }
 #pragma unroll
-    for (int i = 0; i < 15; ++i) o.cov[(size_t)k * 15 + i] = fail ? 0.f : L.sp->cin[i];
+    for (int i = 0; i < 15; ++i) {
+        const float v = L.sp->cin[i];
+        o.cov[(size_t)k * 15 + i] = fail ? 0.f : v;
+    }
     L.phase = 0;
     return (valid ? 1u : 0u) | (fail ? 2u : 0u);
 }
@@ -355,81 +397,66 @@ __device__ inline uint32_t finish(Lane& L, const KParams& kp, const TrackletOut&
 //           else (and for the rest of the pass) search the row;
 //   pass B: rows at or above the start row re-use pass A's hit on that row (if any),
 //           rows below it are searched.
-__device__ inline bool step(Lane& L, const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
-                            const uint32_t* __restrict__ bin_off, const int32_t* __restrict__ upc,
-                            const TrackletOut& o) {
+__device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const KParams& kp,
+                            const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+                            const int32_t* __restrict__ upc, const TrackletOut& o) {
+    // Straight-line: every lane runs the same instructions and results are blended
+    // with selects; only the row search and the filter update are branches.  Values
+    // a lane computes after its pass has ended are discarded by the caller.
     const int R = g.R;
     const bool A = L.phase == 1;
     const int r = L.r;
-    if (A ? r >= R : r < 0) return true;
+    bool end = A ? r >= R : r < 0;
+    const int rc = r < 0 ? 0 : (r >= R ? R - 1 : r);
     int32_t* slot = o.hits + (size_t)L.k * R;
     // Loads that do not depend on the propagated state go out before it is computed:
-    // the row tables, and the hit this row may take without a search (the next chain
-    // hit in pass A, pass A's hit on this row in pass B) with its upward link.
-    const double xr = g.row_x[r];
-    const RowBins rb = row_bins(g, L.s, r);
-    int32_t cand = -1;
-    if (A) {
-        if (L.on) cand = L.next;
-    } else if (r >= L.r0 && L.ia >= 0) {
-        cand = slot[L.ia];
-    }
-    Hit hc;
-    int32_t cand_up = -1;
-    if (cand >= 0) {
-        hc = hits[cand];
-        if (A) cand_up = upc[cand];
-    }
-    if (!propagate(L.p, L.C, L.x, xr, kp)) return true;
+    // the hit this row may take without a search (the next chain hit in pass A, pass
+    // A's hit on this row in pass B) with its upward link, and in pass B the slot
+    // entry of the pass-A hit after it.
+    const double xr = rt.x[rc];
+    const RowBins rb = row_bins_lds(rt, L.s, rc);
+    const int32_t cand = A ? (L.on ? L.next : -1) : ((r >= L.r0 && L.ia >= 0) ? L.pf : -1);
+    const int32_t cc = cand < 0 ? 0 : cand;
+    const Hit hc = hits[cc];
+    const int32_t cand_up = upc[cc];
+    const int ia1 = L.ia < 1 ? 0 : (L.ia > R ? R - 1 : L.ia - 1);
+    const int32_t pf_next = slot[ia1];
+    end = end || !propagate(L.p, L.C, L.x, xr, kp);
     L.x = xr;
-    if (fabs(L.p[0]) > xr * kp.tan_half + kp.edge) return true;
-    int32_t acc = -1;
-    float hy = 0.f, hz = 0.f;
-    bool search;
-    if (A) {
-        if (L.on) {
-            L.on = false;
-            if (cand >= 0 && (int)(hc.rs % (uint32_t)R) == r && chi2_of(L.p, L.C, hc.y, hc.z, kp) <= kp.fol_cut) {
-                acc = cand;
-                L.next = cand_up;
-                L.on = true;
-            }
-        }
-        search = acc < 0;
-    } else {
-        search = r < L.r0;
-        if (cand >= 0 && (int)(hc.rs % (uint32_t)R) == r) {
-            acc = cand;
-            --L.ia;
-        }
-    }
-    if (acc >= 0) {
-        hy = hc.y;
-        hz = hc.z;
-    }
-    if (search) acc = search_row(g, kp, hits, bin_off, rb, L.p, L.C, hy, hz);
+    end = end || fabs(L.p[0]) > xr * kp.tan_half + kp.edge;
+    const bool on_row = (cand >= 0) & ((int)(hc.rs % (uint32_t)R) == r);
+    const bool link = A & L.on & on_row & (chi2_of(L.p, L.C, hc.y, hc.z, kp) <= kp.fol_cut);
+    const bool reused = !A & on_row;
+    L.on = A ? link : L.on;
+    L.next = link ? cand_up : L.next;
+    L.ia = reused ? L.ia - 1 : L.ia;
+    L.pf = reused ? pf_next : L.pf;
+    int32_t acc = (link || reused) ? cand : -1;
+    float hy = hc.y, hz = hc.z;
+    if (!end && (A ? !link : r < L.r0)) acc = search_row(g, kp, hits, bin_off, rb, L.p, L.C, hy, hz);
+    const bool has = !end && acc >= 0;
+    bool ok = true;
+    double c2 = 0.0;
+    if (has) ok = kf_update(L.p, L.C, hy, hz, kp, c2);
+    const bool good = has && ok;
     L.r = A ? r + 1 : r - 1;
-    if (acc < 0) return ++L.miss > kp.n_miss;
-    double c2;
-    if (!kf_update(L.p, L.C, hy, hz, kp, c2)) {
-        L.fail = true;
-        return true;
-    }
-    L.miss = 0;
-    if (A) {
-        slot[L.nA] = acc;
-        ++L.nA;
-        L.last = r;
+    L.miss = good ? 0 : L.miss + 1;
+    L.fail = L.fail || (has && !ok);
+    end = end || (has && !ok) || (!has && L.miss > kp.n_miss);
+    if (good) {
+        // pass A appends from the front of the slot, pass B from the back; the saved
+        // direction only matters in pass A and the saved inner state only in pass B
+        slot[A ? L.nA : R - 1 - L.nB] = acc;
+        L.nA += A ? 1 : 0;
+        L.nB += A ? 0 : 1;
+        L.last = A ? r : L.last;
+        L.inner = A ? L.inner : r;
+        L.chi2 += A ? 0.0 : c2;
+        L.ndf += A ? 0 : 2;
         save_dir(L, hy, hz, acc);
-    } else {
-        L.chi2 += c2;
-        L.ndf += 2;
-        slot[R - 1 - L.nB] = acc;
-        ++L.nB;
-        L.inner = r;
         save_inner(L);
     }
-    return false;
+    return end;
 }
 
 constexpr int kTlBlock = 128;
@@ -484,8 +511,24 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
     const uint32_t grab = 64u * (uint32_t)chunk;
     uint32_t n_valid = 0, n_fail = 0;
     __shared__ Spare spare[kTlBlock];
+    __shared__ float t_x[kMaxRows + 1], t_ymin[kMaxRows + 1];
+    __shared__ int32_t t_ny[kMaxRows + 1];
+    __shared__ uint32_t t_base[kMaxRows + 1];
+    for (int r = threadIdx.x; r <= g.R; r += kTlBlock) {
+        t_x[r] = r < g.R ? g.row_x[r] : 0.f;
+        t_ymin[r] = r < g.R ? g.row_ymin[r] : 0.f;
+        t_ny[r] = r < g.R ? g.row_ny[r] : 0;
+        t_base[r] = g.bin_base[r];
+    }
+    __syncthreads();
+    const RowTab rt{t_x, t_ymin, t_ny, t_base, t_base[g.R]};
     Lane L;
     L.phase = 0;  // 0 idle, 1 pass A, 2 pass B, 3 retired, 4 seed loading
+    L.k = 0;
+    L.s = L.r0 = L.r = L.last = L.inner = L.nA = L.nB = L.ia = L.miss = L.ndf = 0;
+    L.next = L.pf = -1;
+    L.on = L.fail = false;
+    L.x = L.chi2 = 0.0;
     L.sp = &spare[threadIdx.x];
     uint32_t plo = 0, phi = 0;  // wave-uniform: reserved, not yet handed out
     uint32_t my_j = 0;
@@ -521,16 +564,16 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
         if (!__ballot(L.phase == 1 || L.phase == 2 || L.phase == 4)) break;
         Seed sd;
         if (L.phase == 4) sd = seeds[my_j];
-        if ((L.phase == 1 || L.phase == 2) && step(L, g, kp, hits, bin_off, upc, o)) {
+        if ((L.phase == 1 || L.phase == 2) && step(L, g, rt, kp, hits, bin_off, upc, o)) {
             if (L.phase == 1 && !L.fail) {
-                start_pass_b(L, g, kp, o);
+                start_pass_b(L, g, rt, kp, o);
             } else {
                 const uint32_t f = finish(L, kp, o);
                 n_valid += f & 1u;
                 n_fail += (f >> 1) & 1u;
             }
         }
-        if (L.phase == 4) start_pass_a(L, sd, g, kp, o);
+        if (L.phase == 4) start_pass_a(L, sd, g, rt, kp, o);
     }
     __shared__ uint32_t sv[kTlBlock / 64], sf[kTlBlock / 64];
     const uint32_t wv = wave_sum(n_valid), wf = wave_sum(n_fail);
