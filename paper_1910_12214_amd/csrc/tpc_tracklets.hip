@@ -293,7 +293,7 @@ struct Lane {
     int s, r0, r, last, inner, nA, nB, ia, miss, ndf;
     int32_t next;
     int32_t pf;  // pass B: position of pass A's hit number ia (loaded one step ahead)
-    int32_t w[4];  // the slot's current aligned 4-entry chunk, stored once complete
+    int32_t w[8];  // the slot's current aligned 8-entry chunk, stored once complete
     bool on, fail;
     double x, chi2;
     double p[5], C[15];
@@ -316,27 +316,31 @@ __device__ inline void save_dir(Lane& L, float hy, float hz, int32_t pos) {
     L.sp->lpos = pos;
 }
 
-// Slot entries are collected per aligned chunk of four and stored as one 16-byte
-// write when the chunk is complete (or the pass ends), so a slot line is touched
-// once per four hits instead of once per hit (fewer partial lines leaving L2).
-// Needs 16-byte aligned slots (n_rows a multiple of 4); otherwise entries are
-// stored one by one.  Entries outside [0, nA) in pass A and [R - nB, R) in pass B
-// are never read, so a partly filled chunk may be stored with stale values.
+// Slot entries are collected per aligned chunk of kSlotChunk and stored as two
+// 16-byte writes when the chunk is complete (or the pass ends), so a slot line is
+// touched once per eight hits instead of once per hit (fewer partial lines leaving
+// L2).  Needs 32-byte aligned slots (n_rows a multiple of kSlotChunk); otherwise
+// entries are stored one by one.  Entries outside [0, nA) in pass A and
+// [R - nB, R) in pass B are never read, so a partly filled chunk may be stored with
+// stale values.
+constexpr int kSlotChunk = 8;
+
+__device__ inline void slot_flush(const Lane& L, int32_t* slot, int idx, bool wide) {
+    if (!wide) return;
+    int4* c = (int4*)(slot + (idx & ~(kSlotChunk - 1)));
+    c[0] = make_int4(L.w[0], L.w[1], L.w[2], L.w[3]);
+    c[1] = make_int4(L.w[4], L.w[5], L.w[6], L.w[7]);
+}
+
 __device__ inline void slot_put(Lane& L, int32_t* slot, int idx, int32_t v, bool wide, bool last_in_chunk) {
     if (!wide) {
         slot[idx] = v;
         return;
     }
-    const int q = idx & 3;
-    L.w[0] = q == 0 ? v : L.w[0];
-    L.w[1] = q == 1 ? v : L.w[1];
-    L.w[2] = q == 2 ? v : L.w[2];
-    L.w[3] = q == 3 ? v : L.w[3];
-    if (last_in_chunk) *(int4*)(slot + (idx & ~3)) = make_int4(L.w[0], L.w[1], L.w[2], L.w[3]);
-}
-
-__device__ inline void slot_flush(const Lane& L, int32_t* slot, int idx, bool wide) {
-    if (wide) *(int4*)(slot + (idx & ~3)) = make_int4(L.w[0], L.w[1], L.w[2], L.w[3]);
+    const int q = idx & (kSlotChunk - 1);
+#pragma unroll
+    for (int i = 0; i < kSlotChunk; ++i) L.w[i] = q == i ? v : L.w[i];
+    if (last_in_chunk) slot_flush(L, slot, idx, true);
 }
 
 __device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, const RowTab& rt, const KParams& kp,
@@ -351,7 +355,7 @@ __device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, 
     L.p[3] = sd.t0;
     L.p[4] = 0.0;
     c0_init(L.C, kp);
-    slot_put(L, o.hits + (size_t)sd.k * R, 0, sd.p0, (R & 3) == 0, false);
+    slot_put(L, o.hits + (size_t)sd.k * R, 0, sd.p0, (R & (kSlotChunk - 1)) == 0, false);
     L.nA = 1;
     L.last = L.r0;
     save_dir(L, sd.y0, sd.z0, sd.p0);
@@ -375,9 +379,9 @@ __device__ inline void start_pass_b(Lane& L, const GridDesc& g, const RowTab& rt
     L.p[3] = L.sp->pl[1];
     L.p[4] = L.sp->pl[2];
     c0_init(L.C, kp);
-    const bool wide = (R & 3) == 0;
-    if ((L.nA & 3) != 0) slot_flush(L, slot, L.nA - 1, wide);  // pass A's last, partial chunk
-    slot_put(L, slot, R - 1, pb, wide, ((R - 1) & 3) == 0);
+    const bool wide = (R & (kSlotChunk - 1)) == 0;
+    if ((L.nA & (kSlotChunk - 1)) != 0) slot_flush(L, slot, L.nA - 1, wide);  // pass A's last, partial chunk
+    slot_put(L, slot, R - 1, pb, wide, ((R - 1) & (kSlotChunk - 1)) == 0);
     L.nB = 1;
     L.inner = L.last;
     L.chi2 = 0.0;
@@ -394,7 +398,8 @@ __device__ inline void start_pass_b(Lane& L, const GridDesc& g, const RowTab& rt
 // Writes the tracklet's outputs; returns bit0 = valid, bit1 = fit failure.
 __device__ inline uint32_t finish(Lane& L, int R, const KParams& kp, const TrackletOut& o) {
     const bool fail = L.fail;
-    if (L.phase == 2 && !fail && ((R - L.nB) & 3) != 0) slot_flush(L, o.hits + (size_t)L.k * R, R - L.nB, (R & 3) == 0);
+    if (L.phase == 2 && !fail && ((R - L.nB) & (kSlotChunk - 1)) != 0)
+        slot_flush(L, o.hits + (size_t)L.k * R, R - L.nB, (R & (kSlotChunk - 1)) == 0);
     const int nB = fail ? 0 : L.nB;
     const bool valid = !fail && nB >= kp.n_min_tl;
     const uint32_t k = L.k;
@@ -474,7 +479,8 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const 
         // pass A appends from the front of the slot, pass B from the back; the saved
         // direction only matters in pass A and the saved inner state only in pass B
         const int idx = A ? L.nA : R - 1 - L.nB;
-        slot_put(L, slot, idx, acc, (R & 3) == 0, A ? (idx & 3) == 3 : (idx & 3) == 0);
+        slot_put(L, slot, idx, acc, (R & (kSlotChunk - 1)) == 0,
+                 A ? (idx & (kSlotChunk - 1)) == kSlotChunk - 1 : (idx & (kSlotChunk - 1)) == 0);
         L.nA += A ? 1 : 0;
         L.nB += A ? 0 : 1;
         L.last = A ? r : L.last;
@@ -555,6 +561,7 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
     L.k = 0;
     L.s = L.r0 = L.r = L.last = L.inner = L.nA = L.nB = L.ia = L.miss = L.ndf = 0;
     L.next = L.pf = -1;
+    for (int i = 0; i < kSlotChunk; ++i) L.w[i] = -1;
     L.on = L.fail = false;
     L.x = L.chi2 = 0.0;
     L.sp = &spare[threadIdx.x];
