@@ -200,6 +200,7 @@ struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
     uint32_t *tl_slot, *proc, *slab_cnt, *nb_ovf;
     void* seeds;
+    uint32_t *sort_cnt, *sel_order;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
     int32_t *up, *dn, *upc, *dnc;
@@ -216,6 +217,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     if (NB > scan_n) scan_n = NB;
     if (T > scan_n) scan_n = T;
     if (nblk > scan_n) scan_n = nblk;
+    if ((int64_t)select_sort_entries() > scan_n) scan_n = (int64_t)select_sort_entries();
 #define B(field, name, bytes)                                   \
     s->field = (decltype(s->field))buf(c, name, (size_t)(bytes)); \
     if (!s->field) return TPC_ERR_HIP;
@@ -240,6 +242,8 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(slab_cnt, "slab_cnt", 4 * ((int64_t)S * slab_count(pr.g, pr.slab_bins) * R + 1));
     B(proc, "proc", 4 * T);
     B(seeds, "tl_seeds", seed_bytes() * T);
+    B(sort_cnt, "sort_cnt", 4 * select_sort_entries());
+    B(sel_order, "sel_order", 4 * T);
     B(nb_ovf, "nb_ovf", 4 * nb_overflow_entries(n));
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
@@ -316,7 +320,7 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);
-    select_keys(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, T, st);
+    select_keys(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, s.sort_cnt, s.sel_order, s.scan, T, st);
     select_own(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag, T,
                st);
     scan_u32(s.own_cnt, s.hit_off, T, s.counters + C_N_STARTS, s.counters + C_N_TRACK_HITS, s.scan, st);

@@ -182,8 +182,11 @@ void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, cons
                      hipStream_t s);
 
 // select.hip
-void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
-                 uint32_t* counters, uint64_t* hit_key, int64_t t_max, hipStream_t s);
+// sort_cnt: [select_sort_entries()], order: [t_max] (valid tracklets by decreasing length)
+size_t select_sort_entries();
+void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
+                 uint64_t* hit_key, uint32_t* sort_cnt, uint32_t* order, void* scan_scratch, int64_t t_max,
+                 hipStream_t s);
 void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
                 const uint32_t* counters, const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt,
                 uint32_t* trk_flag, int64_t t_max, hipStream_t s);

@@ -38,19 +38,49 @@ struct WaveWalk {
     __device__ void next() { j += step; }
 };
 
-__global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
-                                                 const uint32_t* __restrict__ proc, TrackletOut o, int R,
-                                                 const uint32_t* __restrict__ counters, uint64_t* __restrict__ hit_key) {
+// Key pass order: valid tracklets by decreasing hit count (counting sort, one
+// bucket per count, arbitrary order inside a bucket).  Processed in this order,
+// the longest tracklet of a track tends to set its hits' keys first and its
+// shorter duplicates read a larger key and skip the atomic.  The keys themselves
+// do not depend on the order.
+constexpr int kSortBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_len_count(TrackletOut o, const uint32_t* __restrict__ counters,
+                                                      uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
     const uint32_t n = counters[C_N_STARTS];
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += kSortBlocks * kBlock)
+        if (o.flags[k] & 1u) atomicAdd(&hist[255 - min(o.nhits[k], 255)], 1u);
+    __syncthreads();
+    cnt[threadIdx.x * kSortBlocks + blockIdx.x] = hist[threadIdx.x];  // bucket-major: the scan gives the order
+}
+
+__global__ __launch_bounds__(kBlock) void k_len_scatter(TrackletOut o, const uint32_t* __restrict__ counters,
+                                                        const uint32_t* __restrict__ off, uint32_t* __restrict__ order) {
+    __shared__ uint32_t base[256];
+    base[threadIdx.x] = off[threadIdx.x * kSortBlocks + blockIdx.x];
+    __syncthreads();
+    const uint32_t n = counters[C_N_STARTS];
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < n; k += kSortBlocks * kBlock)
+        if (o.flags[k] & 1u) order[atomicAdd(&base[255 - min(o.nhits[k], 255)], 1u)] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
+                                                 const uint32_t* __restrict__ order, TrackletOut o, int R,
+                                                 const uint32_t* __restrict__ counters, uint64_t* __restrict__ hit_key) {
+    const uint32_t n = counters[C_N_VALID_TL];
     const uint32_t lane = threadIdx.x & 63;
-    for (WaveWalk w(n); w.ok(); w.next()) {
-        const uint32_t k = proc[w.j];
-        if (!(o.flags[k] & 1u)) continue;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wave = blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t j = wave; j < n; j += gridDim.x * wpb) {  // in order of decreasing length
+        const uint32_t k = order[j];
         const uint32_t nh = (uint32_t)o.nhits[k];
         const uint64_t key = tl_key(nh, hits[starts[k]].id);
         const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
-        for (uint32_t j = lane; j < nh; j += 64) {
-            const int32_t pos = slot[j];
+        for (uint32_t i = lane; i < nh; i += 64) {
+            const int32_t pos = slot[i];
             // keys only grow: a plain read at or above ours makes the atomic unnecessary
             if (hit_key[pos] < key) atomicMax((unsigned long long*)&hit_key[pos], (unsigned long long)key);
         }
@@ -154,9 +184,15 @@ inline unsigned sel_blocks(int64_t t_max) {
 
 }  // namespace
 
-void select_keys(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
-                 uint32_t* counters, uint64_t* hit_key, int64_t t_max, hipStream_t s) {
-    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, R, counters, hit_key);
+size_t select_sort_entries() { return (size_t)256 * kSortBlocks + 1; }
+
+void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, int R, uint32_t* counters,
+                 uint64_t* hit_key, uint32_t* sort_cnt, uint32_t* order, void* scan_scratch, int64_t t_max,
+                 hipStream_t s) {
+    k_len_count<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt);
+    scan_u32(sort_cnt, sort_cnt, (int64_t)256 * kSortBlocks, nullptr, nullptr, scan_scratch, s);
+    k_len_scatter<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt, order);
+    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, order, o, R, counters, hit_key);
 }
 
 void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
