@@ -435,6 +435,8 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
 }
 
 // ------------------------------------------------------------ time frames
+}  // extern "C"
+
 namespace {
 
 std::string bytes_of(const void* p, size_t n) { return std::string((const char*)p, n); }
@@ -522,6 +524,7 @@ int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, 
 }
 
 }  // namespace
+extern "C" {
 
 int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz,
                         const tpc_params_t* p, tpc_tracks_t* out, void* stream, int sync_check) {
