@@ -171,6 +171,30 @@ def main():
                      "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom]},
         "path_roofline_frac": total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
+    # Two events in flight: consecutive steps alternate between two contexts on two
+    # streams, so one event's tracklet tail (few long tracklets, most CUs idle) overlaps
+    # the next event's first stages.  Reported beside `value`, which is one event at a time.
+    if not tf:
+        ctx2 = tpcca.Context(0)
+        out2 = ctx2.alloc_tracks(max(1024, ev.n // 8), ev.n)
+        streams = (torch.cuda.Stream(), torch.cuda.Stream())
+        ctxs, outs = (ctx, ctx2), (out, out2)
+        for i in range(2 + 2 * args.warmup):
+            ctxs[i % 2].track(y, z, r, s, geom, synth.BZ, params, out=outs[i % 2], stream=streams[i % 2],
+                              sync_check=(i < 2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ctxs[i % 2].track(y, z, r, s, geom, synth.BZ, params, out=outs[i % 2], stream=streams[i % 2],
+                              sync_check=False)
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
+        h1, h2 = tpcca.tracks_to_host(out), tpcca.tracks_to_host(out2)
+        same = bool(np.array_equal(h1["hit_ids"], h2["hit_ids"]) and np.array_equal(h1["n_hits"], h2["n_hits"]))
+        line["two_in_flight"] = {"value": ev.n / (ms_p * 1e-3), "ms_per_step": ms_p, "streams": 2,
+                                 "outputs_equal": same}
+        ctx2.close()
+        log("timed two in flight")
     # learned pruning (scorer trained on one-sector events; tau from its validation seeds)
     if not args.no_mlp:
         from paper_1910_12214_amd import scorer as sc
