@@ -67,6 +67,10 @@ __global__ __launch_bounds__(kBlock) void k_len_scatter(TrackletOut o, const uin
         if (o.flags[k] & 1u) order[atomicAdd(&base[255 - min(o.nhits[k], 255)], 1u)] = k;
 }
 
+// One tracklet per wave (the launch covers every valid tracklet once when it can):
+// all slot entries are loaded, then all keys read, then the atomics issued, and
+// the wave ends.  A wave never issues a load after an atomic, so no load waits for
+// an atomic to complete (vector memory operations retire in order).
 __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, const uint32_t* __restrict__ starts,
                                                  const uint32_t* __restrict__ order, TrackletOut o, int R,
                                                  const uint32_t* __restrict__ counters, uint64_t* __restrict__ hit_key) {
@@ -79,11 +83,19 @@ __global__ __launch_bounds__(kBlock) void k_keys(const Hit* __restrict__ hits, c
         const uint32_t nh = (uint32_t)o.nhits[k];
         const uint64_t key = tl_key(nh, hits[starts[k]].id);
         const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
-        for (uint32_t i = lane; i < nh; i += 64) {
-            const int32_t pos = slot[i];
-            // keys only grow: a plain read at or above ours makes the atomic unnecessary
-            if (hit_key[pos] < key) atomicMax((unsigned long long*)&hit_key[pos], (unsigned long long)key);
+        int32_t pos[4];
+        uint64_t cur[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {  // R <= 255 < 4 * 64
+            const uint32_t i = lane + 64u * q;
+            pos[q] = i < nh ? slot[i] : -1;
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = pos[q] >= 0 ? hit_key[pos[q]] : ~0ull;
+        // keys only grow: a plain read at or above ours makes the atomic unnecessary
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cur[q] < key) atomicMax((unsigned long long*)&hit_key[pos[q]], (unsigned long long)key);
     }
 }
 
@@ -192,7 +204,9 @@ void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, 
     k_len_count<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt);
     scan_u32(sort_cnt, sort_cnt, (int64_t)256 * kSortBlocks, nullptr, nullptr, scan_scratch, s);
     k_len_scatter<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt, order);
-    k_keys<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, order, o, R, counters, hit_key);
+    int64_t kb = (t_max + kBlock / 64 - 1) / (kBlock / 64);  // one wave per possible tracklet, capped
+    if (kb > 65536) kb = 65536;
+    k_keys<<<(unsigned)(kb > 0 ? kb : 1), kBlock, 0, s>>>(hits, starts, order, o, R, counters, hit_key);
 }
 
 void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
