@@ -19,6 +19,8 @@ namespace tpc {
 
 namespace {
 
+constexpr int kListD = 6;  // down-window candidates held in registers per hit
+
 __global__ __launch_bounds__(kBlock) void k_neighbours(GridDesc g, KParams kp, const Hit* __restrict__ hits,
                                                        const uint32_t* __restrict__ bin_off,
                                                        const uint32_t* __restrict__ counters,
@@ -42,28 +44,74 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(GridDesc g, KParams kp, c
                 const double w = (xm - xd) / (xu - xd);
                 double best = 1e300;
                 uint32_t bu_id = 0xFFFFFFFFu, bd_id = 0xFFFFFFFFu;
+                // the down-window candidates, once, into a register list (selects with
+                // constant indices); more than kListD of them: the nested walk below
+                float ly[kListD], lz[kListD];
+                uint32_t lid[kListD];
+                int32_t lpos[kListD];
+                int nd = 0;
+#pragma unroll
+                for (int q = 0; q < kListD; ++q) {
+                    ly[q] = lz[q] = 0.f;
+                    lid[q] = 0;
+                    lpos[q] = -1;
+                }
+                for (int jz = D.iz0; jz <= D.iz1; ++jz) {
+                    const uint32_t j1 = bin_off[D.base + jz * D.ny + D.iy1 + 1];
+                    for (uint32_t j = bin_off[D.base + jz * D.ny + D.iy0]; j < j1; ++j) {
+                        const Hit d = hits[j];
+                        if (!(fabs((double)d.y - ym) <= wyd) || !(fabs((double)d.z - zm) <= wzd)) continue;
+#pragma unroll
+                        for (int q = 0; q < kListD; ++q) {
+                            const bool here = q == nd;
+                            ly[q] = here ? d.y : ly[q];
+                            lz[q] = here ? d.z : lz[q];
+                            lid[q] = here ? d.id : lid[q];
+                            lpos[q] = here ? (int32_t)j : lpos[q];
+                        }
+                        ++nd;
+                    }
+                }
                 for (int iz = U.iz0; iz <= U.iz1; ++iz) {
                     const uint32_t k1 = bin_off[U.base + iz * U.ny + U.iy1 + 1];
                     for (uint32_t k = bin_off[U.base + iz * U.ny + U.iy0]; k < k1; ++k) {
                         const Hit u = hits[k];
                         const double yu = u.y, zu = u.z;
                         if (!(fabs(yu - ym) <= wyu) || !(fabs(zu - zm) <= wzu)) continue;
-                        for (int jz = D.iz0; jz <= D.iz1; ++jz) {
-                            const uint32_t j1 = bin_off[D.base + jz * D.ny + D.iy1 + 1];
-                            for (uint32_t j = bin_off[D.base + jz * D.ny + D.iy0]; j < j1; ++j) {
-                                const Hit d = hits[j];
-                                const double yd = d.y, zd = d.z;
-                                if (!(fabs(yd - ym) <= wyd) || !(fabs(zd - zm) <= wzd)) continue;
-                                ++pairs;
+                        pairs += (uint32_t)nd;
+                        if (nd <= kListD) {
+#pragma unroll
+                            for (int q = 0; q < kListD; ++q) {
+                                const double yd = ly[q], zd = lz[q];
                                 const double py = yd + (yu - yd) * w, pz = zd + (zu - zd) * w;
                                 const double Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
-                                if (!(Dv <= kp.nb_cut)) continue;
-                                if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
-                                    best = Dv;
-                                    bu = (int32_t)k;
-                                    bd = (int32_t)j;
-                                    bu_id = u.id;
-                                    bd_id = d.id;
+                                const bool take = (q < nd) & (Dv <= kp.nb_cut) &
+                                                  ((Dv < best) | ((Dv == best) & ((u.id < bu_id) |
+                                                                                   ((u.id == bu_id) & (lid[q] < bd_id)))));
+                                best = take ? Dv : best;
+                                bu = take ? (int32_t)k : bu;
+                                bd = take ? lpos[q] : bd;
+                                bu_id = take ? u.id : bu_id;
+                                bd_id = take ? lid[q] : bd_id;
+                            }
+                        } else {
+                            for (int jz = D.iz0; jz <= D.iz1; ++jz) {
+                                const uint32_t j1 = bin_off[D.base + jz * D.ny + D.iy1 + 1];
+                                for (uint32_t j = bin_off[D.base + jz * D.ny + D.iy0]; j < j1; ++j) {
+                                    const Hit d = hits[j];
+                                    const double yd = d.y, zd = d.z;
+                                    if (!(fabs(yd - ym) <= wyd) || !(fabs(zd - zm) <= wzd)) continue;
+                                    const double py = yd + (yu - yd) * w, pz = zd + (zu - zd) * w;
+                                    const double Dv =
+                                        (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
+                                    if (!(Dv <= kp.nb_cut)) continue;
+                                    if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
+                                        best = Dv;
+                                        bu = (int32_t)k;
+                                        bd = (int32_t)j;
+                                        bu_id = u.id;
+                                        bd_id = d.id;
+                                    }
                                 }
                             }
                         }
