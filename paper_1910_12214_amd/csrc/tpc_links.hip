@@ -158,7 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_clean_flag(KParams kp, const Hit* __
             }
             flag = len >= kp.l_min;
         }
-        start_flag[hits[p].id] = flag;
+        // the flags start zeroed (cleared with the grid): only starts are written, a
+        // scattered byte write for 7% of the hits instead of all of them
+        if (flag) start_flag[hits[p].id] = 1;
     }
     block_add2(clean, 0, &cnt[C_N_LINKS_CLEAN], nullptr);
 }
