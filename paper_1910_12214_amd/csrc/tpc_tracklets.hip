@@ -452,7 +452,7 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const 
     const Hit hc = hits[cc];
     const int32_t cand_up = upc[cc];
     const int ia1 = L.ia < 1 ? 0 : (L.ia > R ? R - 1 : L.ia - 1);
-    const int32_t pf_next = slot[ia1];
+    const int32_t pf_next = A ? -1 : slot[ia1];  // pass A lanes load nothing (no slot lines into L2)
     end = end || !propagate(L.p, L.C, L.x, xr, kp);
     L.x = xr;
     end = end || fabs(L.p[0]) > xr * kp.tan_half + kp.edge;
