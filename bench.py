@@ -202,7 +202,11 @@ def main():
 
         # the scorer trained on events of this workload's generator if there is one, else the
         # one-sector scorer
-        ck = sc.PBPB_CKPT if w.name.startswith("pbpb") and os.path.exists(sc.PBPB_CKPT) else sc.DEFAULT_CKPT
+        ck = sc.DEFAULT_CKPT
+        if w.name.startswith("pbpb") and os.path.exists(sc.PBPB_CKPT):
+            ck = sc.PBPB_CKPT
+        elif w.name.startswith("pp") and os.path.exists(sc.PP_CKPT):
+            ck = sc.PP_CKPT
         params_mlp, tau_trained = sc.load(ck)
         mlp = torch.from_numpy(params_mlp).to(dev)
         # threshold for this workload: largest tau on a grid whose efficiency on a validation event of

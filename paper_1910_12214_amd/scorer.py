@@ -7,6 +7,7 @@ events; the plain finder is both the fallback and the judge of the efficiency th
 
     python -m paper_1910_12214_amd.scorer train --set sector     # -> scorer_sector200.npz
     python -m paper_1910_12214_amd.scorer train --set pbpb       # -> scorer_pbpb.npz
+    python -m paper_1910_12214_amd.scorer train --set pp         # -> scorer_pp.npz
 
 Training sets (every window candidate triplet of the events, label 1 iff the three clusters are
 consecutive crossings of one leg, uniformly subsampled to 10^7 if there are more):
@@ -14,7 +15,10 @@ consecutive crossings of one leg, uniformly subsampled to 10^7 if there are more
           test seeds 1001..1020;
   pbpb:   central Pb-Pb-like full-TPC events (the benchmark event's generator), training seeds
           0x10001..0x10008, threshold seeds 0x20001..0x20002, test seeds 0x30001..0x30002 — all
-          disjoint from the benchmark event's seed and its validation seed.
+          disjoint from the benchmark event's seed and its validation seed;
+  pp:     pp-like time frames of 570 collisions at 1 MHz (a twentieth of the benchmark frame, same
+          rate, multiplicity and noise), training seeds 0x40001..0x40008, threshold seeds
+          0x50001..0x50002, test seeds 0x60001..0x60002.
 He-uniform initialisation from a seeded generator, Adam (lr 1e-3, betas 0.9/0.999) for 5 epochs
 of batch 4096; the threshold tau (on the logit) is the largest candidate whose efficiency on the
 threshold seeds is within 0.5% of the plain finder's.
@@ -56,6 +60,18 @@ def _pbpb_events(seeds):
     return [dataclasses.replace(synth.PBPB_EVENT, name=f"pbpb_event_5000_s{s:#x}", seed=s) for s in seeds]
 
 
+PP_CKPT = os.path.join(_HERE, "scorer_pp.npz")
+
+
+def _pp_events(seeds):
+    import dataclasses
+
+    import synth
+
+    base = synth.scaled(synth.PP_TIMEFRAME, 0.05)  # 570 pp collisions over 0.57 ms
+    return [dataclasses.replace(base, name=f"pp_timeframe_570_s{s:#x}", seed=s) for s in seeds]
+
+
 # name -> (training, threshold, test workloads, checkpoint, description)
 SETS = {
     "sector": (lambda: _sector_events(TRAIN_SEEDS), lambda: _sector_events(VAL_SEEDS),
@@ -63,6 +79,9 @@ SETS = {
     "pbpb": (lambda: _pbpb_events(range(0x10001, 0x10009)), lambda: _pbpb_events(range(0x20001, 0x20003)),
              lambda: _pbpb_events(range(0x30001, 0x30003)), PBPB_CKPT,
              "central Pb-Pb-like full-TPC events, seeds 0x10001-0x10008"),
+    "pp": (lambda: _pp_events(range(0x40001, 0x40009)), lambda: _pp_events(range(0x50001, 0x50003)),
+           lambda: _pp_events(range(0x60001, 0x60003)), PP_CKPT,
+           "pp-like time frames of 570 collisions at 1 MHz, seeds 0x40001-0x40008"),
 }
 MAX_TRIPLETS = 10_000_000
 N_PARAMS = 5057

@@ -35,3 +35,11 @@ def test_pbpb_checkpoint_is_present_and_well_formed():
     p, tau = scorer.load(scorer.PBPB_CKPT)
     assert p.shape == (5057,) and p.dtype == np.float32 and np.isfinite(p).all() and np.isfinite(tau)
     assert "Pb-Pb" in scorer.trained_on(scorer.PBPB_CKPT)
+
+
+def test_pp_checkpoint_is_present_and_well_formed():
+    from paper_1910_12214_amd import scorer
+
+    p, tau = scorer.load(scorer.PP_CKPT)
+    assert p.shape == (5057,) and p.dtype == np.float32 and np.isfinite(p).all() and np.isfinite(tau)
+    assert "pp-like" in scorer.trained_on(scorer.PP_CKPT)
