@@ -200,6 +200,8 @@ struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
     uint32_t *tl_slot, *proc, *slab_cnt, *nb_ovf;
     void* seeds;
+    void* nb_cand = nullptr;  // fused neighbour finding with a scorer only
+    uint32_t *nb_nund = nullptr, *nb_wrec = nullptr;
     uint32_t *sort_cnt, *sel_order;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
@@ -210,7 +212,7 @@ struct Scratch {
     TrackletOut tl;
 };
 
-int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
+int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
     const int64_t n = pr.n > 0 ? pr.n : 1, T = pr.t_max, NB = pr.n_bins, R = pr.g.R, S = pr.g.S;
     const int64_t nblk = (n + kBlock - 1) / kBlock + 1;
     int64_t scan_n = n;
@@ -221,7 +223,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
 #define B(field, name, bytes)                                   \
     s->field = (decltype(s->field))buf(c, name, (size_t)(bytes)); \
     if (!s->field) return TPC_ERR_HIP;
-    B(counters, "counters", sizeof(uint32_t) * C_N_COUNTERS);
+    B(counters, "counters", sizeof(uint32_t) * kCounterWords);
     B(bin_of, "bin_of", 4 * n);
     B(pos_of, "pos_of", 4 * n);
     B(sorted_id, "sorted_id", 4 * n);
@@ -245,6 +247,11 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s) {
     B(sort_cnt, "sort_cnt", 4 * select_sort_entries());
     B(sel_order, "sel_order", 4 * T);
     B(nb_ovf, "nb_ovf", 4 * nb_overflow_entries(n));
+    if (mlp) {
+        B(nb_cand, "nb_cand", 16 * nb_cand_entries(n));
+        B(nb_nund, "nb_nund", 4 * n);
+        B(nb_wrec, "nb_wrec", 4 * nb_overflow_entries(n));
+    }
     B(own_cnt, "own_cnt", 4 * T);
     B(trk_flag, "trk_flag", 4 * T);
     B(hit_off, "hit_off", 4 * T);
@@ -287,7 +294,7 @@ struct Marks {
 void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s, hipStream_t st) {
     const int64_t n = pr.n, NB = pr.n_bins;
     const GridDesc& g = pr.g;
-    fill_u32(s.counters, 0u, C_N_COUNTERS, st);
+    fill_u32(s.counters, 0u, kCounterWords, st);
     fill_u32(s.bin_cnt, 0u, NB, st);
     fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
     grid_count(cl, g, s.bin_of, s.bin_cnt, s.slot_of, s.pos_of, st);
@@ -306,7 +313,8 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     mk.mark();
     // a2 neighbours (a3: with the learned scorer fused), a4/a5 cleaning and starts
     if (mlp_q)
-        neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.nb_ovf, st);
+        neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.nb_ovf, s.nb_cand, s.nb_nund,
+                       s.nb_wrec, st);
     else
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
@@ -415,7 +423,7 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     Prepared pr;
     if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
     Scratch s;
-    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    if ((rc = alloc_scratch(c, pr, &s, p->mlp != nullptr))) return rc;
     hipStream_t st = (hipStream_t)stream;
     float* q = nullptr;
     if (p->mlp) {
@@ -451,7 +459,7 @@ int timed_run(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo,
     int rc;
     if ((rc = prepare(c, cl, geo, bz, &p2, t.bin_y, t.bin_z, &pr))) return rc;
     Scratch s;
-    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    if ((rc = alloc_scratch(c, pr, &s, p->mlp != nullptr))) return rc;
     float* q = nullptr;
     if (p->mlp) {
         q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
@@ -555,7 +563,7 @@ int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geomet
     Prepared pr;
     if ((rc = prepare(c, cl, geo, bz, &p2, t.bin_y, t.bin_z, &pr))) return rc;
     Scratch s;
-    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    if ((rc = alloc_scratch(c, pr, &s, p->mlp != nullptr))) return rc;
     float* q = nullptr;
     if (p->mlp) {
         q = (float*)buf(c, "mlp_q", sizeof(float) * mlp_q_floats());
@@ -686,7 +694,7 @@ int tpc_triplets(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* g
     Prepared pr;
     if ((rc = prepare(c, cl, geo, 0.0, p, p->bin_y, p->bin_z, &pr))) return rc;
     Scratch s;
-    if ((rc = alloc_scratch(c, pr, &s))) return rc;
+    if ((rc = alloc_scratch(c, pr, &s, false))) return rc;
     hipStream_t st = (hipStream_t)stream;
     enqueue_grid(*cl, pr, s, st);
     const int64_t n = pr.n;

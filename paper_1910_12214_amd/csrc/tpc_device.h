@@ -54,9 +54,14 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Block-wide sums of two per-thread values, one atomic per block each.
-// Every thread of the block must call it.
-__device__ inline void block_add2(uint32_t a, uint32_t b, uint32_t* pa, uint32_t* pb) {
+// Adds v to counter c (< kSlotCandSeg) through tally line `line` (any value).
+__device__ inline void tally_add(uint32_t* counters, uint32_t line, int c, uint32_t v) {
+    if (v) atomicAdd(&counters[C_N_COUNTERS + (line & (uint32_t)(kTallyLines - 1)) * kTallyStride + c], v);
+}
+
+// Block-wide sums of two per-thread values into counters ca and cb (cb < 0: none),
+// one tally atomic per block each.  Every thread of the block must call it.
+__device__ inline void block_tally2(uint32_t a, uint32_t b, int ca, int cb, uint32_t* counters) {
     __shared__ uint32_t sa[kBlock / 64], sb[kBlock / 64];
     a = wave_sum(a);
     b = wave_sum(b);
@@ -72,8 +77,8 @@ __device__ inline void block_add2(uint32_t a, uint32_t b, uint32_t* pa, uint32_t
             ta += sa[k];
             tb += sb[k];
         }
-        if (pa && ta) atomicAdd(pa, ta);
-        if (pb && tb) atomicAdd(pb, tb);
+        tally_add(counters, blockIdx.x, ca, ta);
+        if (cb >= 0) tally_add(counters, blockIdx.x, cb, tb);
     }
 }
 

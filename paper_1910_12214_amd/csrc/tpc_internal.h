@@ -68,6 +68,17 @@ enum Counter {  // device scratch counters (uint32)
     C_N_COUNTERS = 32
 };
 
+// Spread tallies, stored after the counters.  Sums from many blocks go to one of
+// kTallyLines 64-byte lines (slot = counter index) rather than to one address: a
+// device-scope atomic on a single shared address is serialised chip-wide.  The
+// final count kernel adds the lines to the counters.  Slot kSlotCandSeg of line
+// l is the fill level of segment l of the fused neighbour kernel's candidate list.
+constexpr int kTallyLines = 256, kTallyStride = 16, kSlotCandSeg = 15;
+constexpr int kCounterWords = C_N_COUNTERS + kTallyLines * kTallyStride;
+static_assert(C_N_PAIRS < kSlotCandSeg && C_N_LINKS_RAW < kSlotCandSeg && C_N_LINKS_CLEAN < kSlotCandSeg &&
+                  C_N_PAIRS_KEPT < kSlotCandSeg,
+              "tallied counters must fit a tally line");
+
 struct Tuning {
     float bin_y = 8.f, bin_z = 8.f;
     int chunk = 1;         // tracklets an idle lane reserves per queue pop
@@ -200,10 +211,14 @@ void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s)
 size_t mlp_q_floats();
 void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
 void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s);
-// ovf: [nb_overflow_entries(n_max)] wave indices (counted in counters[C_NB_OVF])
+// ovf: [nb_overflow_entries(n_max)] wave indices (counted in counters[C_NB_OVF]);
+// cand: [nb_cand_entries(n_max)] 16-byte candidate records; nund: [n_max];
+// wrec: [nb_overflow_entries(n_max)]
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
-                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, hipStream_t s);
+                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, void* cand,
+                    uint32_t* nund, uint32_t* wrec, hipStream_t s);
 size_t nb_overflow_entries(int64_t n_max);
+size_t nb_cand_entries(int64_t n_max);
 void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                    const uint32_t* counters, uint32_t* cnt, hipStream_t s);
 void triplet_write(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(GridDesc g, KParams kp, c
         dn[p] = bd;
         linked = bu >= 0;
     }
-    block_add2(pairs, linked, &cnt[C_N_PAIRS], &cnt[C_N_LINKS_RAW]);
+    block_tally2(pairs, linked, C_N_PAIRS, C_N_LINKS_RAW, cnt);
 }
 
 __device__ inline int32_t clean_up(const int32_t* __restrict__ up, const int32_t* __restrict__ dn, int32_t p) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_clean_flag(KParams kp, const Hit* __
         // scattered byte write for 7% of the hits instead of all of them
         if (flag) start_flag[hits[p].id] = 1;
     }
-    block_add2(clean, 0, &cnt[C_N_LINKS_CLEAN], nullptr);
+    block_tally2(clean, 0, C_N_LINKS_CLEAN, -1, cnt);
 }
 
 // per-block number of set flags over cluster ids

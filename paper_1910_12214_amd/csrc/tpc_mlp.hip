@@ -366,17 +366,29 @@ __global__ __launch_bounds__(kBlock) void k_trip_write(GridDesc g, KParams kp, c
 }
 
 // ------------------------------------------------- fused neighbour finding with pruning
-// Pair-parallel.  Lane = hit: enumerate the up and down window candidates once
-// (linear in their number) into a wave-level LDS list; the wave's candidate
-// pairs are numbered by a prefix sum of nu * nd.  Lane = pair, 64 per round:
-// features from the list, four 16-pair MFMA tiles, and the plain criterion D in
-// FP64; a pair survives if its logit >= tau and D <= cut.  Lane = hit again: the
-// best surviving pair over this round's slots of the hit (smallest D, ties by
-// (id_up, id_down)).  Work per round is the same for every lane whatever the
-// candidate counts of individual hits.  A wave whose candidates do not fit the
-// list goes to an overflow list for the per-lane kernel.
-constexpr int kPW = 4;        // waves per block
+// Two kernels over the same 64-hit waves.
+//
+// Candidates (lane = hit, full occupancy: the window walks are chains of
+// dependent loads): count the up and down window candidates of each hit, keeping
+// the first kListC of each window in registers; a wave prefix sum numbers the
+// wave's candidates (only hits that have pairs) and its pairs (nu * nd per hit);
+// lane 0 reserves the wave's candidate records with one atomic in segment
+// (wave mod kTallyLines) of a global list (one fill counter per segment, each on
+// its own line: a single shared counter would serialise every wave of the chip),
+// and the hits write their records there.  A wave without pairs writes its empty
+// links at once; a wave whose candidates exceed kCapC, or do not fit its segment,
+// goes to an overflow list served by the per-lane kernel below.
+//
+// Scoring (lane = pair, MFMA): the wave copies its candidate records into LDS
+// (coalesced), recomputes the same prefix sums from the per-hit counts, then in
+// rounds of 64 pairs: features from the LDS list, four 16-pair MFMA tiles, and
+// the plain criterion D in FP64; a pair survives if its logit >= tau and
+// D <= cut.  Lane = hit again: the best surviving pair over this round's slots of
+// the hit (smallest D, ties by (id_up, id_down)).
+constexpr int kPW = 4;        // waves per block (scoring)
 constexpr int kCapC = 512;    // candidate records per wave (10-bit offsets and counts)
+constexpr int kListC = 4;     // window candidates held in registers per window
+constexpr uint32_t kNoWave = 0xFFFFFFFFu;
 
 struct alignas(16) Cand {
     float y, z;
@@ -390,43 +402,11 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(64 * kPW) void k_nb_pairs(GridDesc g, KParams kp, const Hit* __restrict__ hits,
-                                                       const uint32_t* __restrict__ bin_off,
-                                                       uint32_t* __restrict__ counters, const uint8_t* __restrict__ q,
-                                                       int32_t* __restrict__ up, int32_t* __restrict__ dn,
-                                                       uint32_t* __restrict__ ovf) {
-    __shared__ Cand cand_all[kPW][kCapC];
-    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kPW][64 * 40];
-    __shared__ float lg_all[kPW][64];
-    __shared__ double dv_all[kPW][64];
-    __shared__ uint32_t ps0_all[kPW][64], meta_all[kPW][64];
-    __shared__ float ym_all[kPW][64], zm_all[kPW][64];
-    __shared__ int32_t r_all[kPW][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Cand* cand = cand_all[w];
-    uint16_t* xs = xs_all[w];
-    float* lg = lg_all[w];
-    double* dv = dv_all[w];
-    uint32_t* ps0s = ps0_all[w];
-    uint32_t* meta = meta_all[w];
-    const uint32_t n = counters[C_N_VALID_CLU];
-    const uint32_t wave = blockIdx.x * kPW + w;
-    const uint32_t p = wave * 64 + lane;
-    const bool act = p < n;
-    Hit m;
-    m.y = m.z = 0.f;
-    Win win;
-    win.ok = false;
-    win.r = 1;
-    int nu = 0, nd = 0;
-    if (act) {
-        m = hits[p];
-        win = window_of(g, kp, m);
-        if (win.ok) {
-            nu = count_window(g, hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu);
-            nd = count_window(g, hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd);
-        }
-    }
+// Wave prefix sums of the candidate counts (hits with pairs only) and pair counts.
+struct WaveOffs {
+    uint32_t coff, pofs, ctot, ptot;
+};
+__device__ inline WaveOffs wave_offsets(int nu, int nd, int lane) {
     const uint32_t np = (uint32_t)(nu * nd), nc = np ? (uint32_t)(nu + nd) : 0u;
     uint32_t ic = nc, ip = np;
 #pragma unroll
@@ -437,97 +417,235 @@ __global__ __launch_bounds__(64 * kPW) void k_nb_pairs(GridDesc g, KParams kp, c
             ip += b;
         }
     }
-    const uint32_t ctot = __shfl(ic, 63, 64), ptot = __shfl(ip, 63, 64);
-    if (ctot > (uint32_t)kCapC) {  // wave-uniform
-        if (lane == 0) ovf[atomicAdd(&counters[C_NB_OVF], 1u)] = wave;
+    WaveOffs o;
+    o.ctot = __shfl(ic, 63, 64);
+    o.ptot = __shfl(ip, 63, 64);
+    o.coff = ic - nc;
+    o.pofs = ip - np;
+    return o;
+}
+
+// Window candidates of range B (the same exact FP64 test as for_window): their
+// number, the positions of the first kListC in l (selects with constant indices).
+__device__ inline int list_window(const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+                                  const BinRange& B, double ym, double zm, double wy, double wz,
+                                  uint32_t (&l)[kListC]) {
+    int c = 0;
+    if (B.empty) return 0;
+    for (int iz = B.iz0; iz <= B.iz1; ++iz) {
+        const uint32_t k1 = bin_off[B.base + iz * B.ny + B.iy1 + 1];
+        for (uint32_t k = bin_off[B.base + iz * B.ny + B.iy0]; k < k1; ++k) {
+            const Hit h = hits[k];
+            if (fabs((double)h.y - ym) <= wy && fabs((double)h.z - zm) <= wz) {
+#pragma unroll
+                for (int q = 0; q < kListC; ++q) l[q] = q == c ? k : l[q];
+                ++c;
+            }
+        }
+    }
+    return c;
+}
+
+__device__ inline void write_window(const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+                                    const BinRange& B, double ym, double zm, double wy, double wz, int cnt,
+                                    const uint32_t (&l)[kListC], Cand* __restrict__ out) {
+    if (cnt <= kListC) {
+#pragma unroll
+        for (int q = 0; q < kListC; ++q)
+            if (q < cnt) {
+                const Hit h = hits[l[q]];
+                out[q] = Cand{h.y, h.z, h.id, (int32_t)l[q]};
+            }
+    } else {
+        int j = 0;
+        for_window(hits, bin_off, B, ym, zm, wy, wz,
+                   [&](uint32_t k, const Hit& h) { out[j++] = Cand{h.y, h.z, h.id, (int32_t)k}; });
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_nb_cand(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                    const uint32_t* __restrict__ bin_off,
+                                                    uint32_t* __restrict__ counters, Cand* __restrict__ cand,
+                                                    uint32_t seg_cap, uint32_t* __restrict__ nund,
+                                                    uint32_t* __restrict__ wrec, int32_t* __restrict__ up,
+                                                    int32_t* __restrict__ dn, uint32_t* __restrict__ ovf) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    if (wave * 64u >= n) return;  // wave-uniform
+    const uint32_t p = wave * 64 + lane;
+    const bool act = p < n;
+    Hit m;
+    m.y = m.z = 0.f;
+    Win win;
+    win.ok = false;
+    int nu = 0, nd = 0;
+    uint32_t lu[kListC], ld[kListC];
+#pragma unroll
+    for (int q = 0; q < kListC; ++q) lu[q] = ld[q] = 0;
+    if (act) {
+        m = hits[p];
+        win = window_of(g, kp, m);
+        if (win.ok) {
+            nu = list_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu, lu);
+            if (nu) nd = list_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd, ld);
+        }
+    }
+    const WaveOffs o = wave_offsets(nu, nd, lane);
+    uint32_t cb = kNoWave;
+    if (o.ptot && o.ctot <= (uint32_t)kCapC) {  // wave-uniform
+        const uint32_t seg = wave & (uint32_t)(kTallyLines - 1);
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(&counters[C_N_COUNTERS + seg * kTallyStride + kSlotCandSeg], o.ctot);
+        b = __shfl(b, 0, 64);
+        if ((uint64_t)b + o.ctot <= (uint64_t)seg_cap) cb = seg * seg_cap + b;
+    }
+    if (lane == 0) {
+        wrec[wave] = cb;
+        if (o.ptot && cb == kNoWave) ovf[atomicAdd(&counters[C_NB_OVF], 1u)] = wave;
+    }
+    if (cb == kNoWave) {
+        if (!o.ptot && act) {
+            up[p] = -1;
+            dn[p] = -1;
+        }
         return;
     }
-    const uint32_t coff = ic - nc, pofs = ip - np;
-    if (np) {
-        uint32_t j = coff;
-        for_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu,
-                   [&](uint32_t k, const Hit& h) { cand[j++] = Cand{h.y, h.z, h.id, (int32_t)k}; });
-        for_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd,
-                   [&](uint32_t k, const Hit& h) { cand[j++] = Cand{h.y, h.z, h.id, (int32_t)k}; });
+    if (act) nund[p] = (uint32_t)nu | ((uint32_t)nd << 16);
+    if (nu * nd) {
+        Cand* c = cand + cb + o.coff;
+        write_window(hits, bin_off, win.U, m.y, m.z, win.wyu, win.wzu, nu, lu, c);
+        write_window(hits, bin_off, win.D, m.y, m.z, win.wyd, win.wzd, nd, ld, c + nu);
     }
+}
+
+__global__ __launch_bounds__(64 * kPW) void k_nb_score(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+                                                       uint32_t* __restrict__ counters, const uint8_t* __restrict__ q,
+                                                       const Cand* __restrict__ cand_g,
+                                                       const uint32_t* __restrict__ nund,
+                                                       const uint32_t* __restrict__ wrec, int32_t* __restrict__ up,
+                                                       int32_t* __restrict__ dn) {
+    __shared__ Cand cand_all[kPW][kCapC];
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[kPW][64 * 40];
+    __shared__ float lg_all[kPW][64];
+    __shared__ double dv_all[kPW][64];
+    __shared__ uint32_t ps0_all[kPW][64], meta_all[kPW][64];
+    __shared__ float ym_all[kPW][64], zm_all[kPW][64];
+    __shared__ float xd_all[kPW][64], xm_all[kPW][64], xu_all[kPW][64];
+    __shared__ uint8_t own_all[kPW][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Cand* cand = cand_all[w];
+    uint16_t* xs = xs_all[w];
+    float* lg = lg_all[w];
+    double* dv = dv_all[w];
+    uint32_t* ps0s = ps0_all[w];
+    uint32_t* meta = meta_all[w];
+    const uint32_t n = counters[C_N_VALID_CLU];
+    const uint32_t wave = blockIdx.x * kPW + w;
+    if (wave * 64u >= n) return;  // wave-uniform
+    const uint32_t cb = wrec[wave];
+    if (cb == kNoWave) return;  // no pairs (links written) or on the overflow list
+    const uint32_t p = wave * 64 + lane;
+    const bool act = p < n;
+    int nu = 0, nd = 0;
+    float ymv = 0.f, zmv = 0.f, xdv = 0.f, xmv = 0.f, xuv = 0.f;
+    if (act) {
+        const uint32_t v = nund[p];
+        nu = (int)(v & 0xFFFFu);
+        nd = (int)(v >> 16);
+        if (nu * nd) {  // such a hit passed window_of: 0 < r < R - 1
+            const Hit m = hits[p];
+            const int r = (int)(m.rs % (uint32_t)g.R);
+            ymv = m.y;
+            zmv = m.z;
+            xdv = g.row_x[r - 1];
+            xmv = g.row_x[r];
+            xuv = g.row_x[r + 1];
+        }
+    }
+    const WaveOffs o = wave_offsets(nu, nd, lane);
+    const uint32_t np = (uint32_t)(nu * nd), coff = o.coff, pofs = o.pofs, ptot = o.ptot;
+    for (uint32_t i = (uint32_t)lane; i < o.ctot; i += 64) cand[i] = cand_g[cb + i];
     ps0s[lane] = pofs;
     meta[lane] = coff | ((uint32_t)nu << 10) | ((uint32_t)nd << 20);
-    ym_all[w][lane] = m.y;
-    zm_all[w][lane] = m.z;
-    r_all[w][lane] = win.r;
+    ym_all[w][lane] = ymv;
+    zm_all[w][lane] = zmv;
+    xd_all[w][lane] = xdv;
+    xm_all[w][lane] = xmv;
+    xu_all[w][lane] = xuv;
     wave_sync();
     double best = 1e300;
     uint32_t bu_id = 0xFFFFFFFFu, bd_id = 0xFFFFFFFFu;
     int32_t bu = -1, bd = -1;
     uint32_t kept = 0;
-    if (ptot) {
-        Frag F;
-        load_frag(q, F);
-        const float wy = (float)kp.win_y, wz = (float)kp.win_z;
-        for (uint32_t base = 0; base < ptot; base += 64) {
-            const uint32_t t = base + (uint32_t)lane;
-            const bool has = t < ptot;
-            float f[12];
+    Frag F;
+    load_frag(q, F);
+    const float wy = (float)kp.win_y, wz = (float)kp.win_z;
+    uint8_t* own = own_all[w];
+    for (uint32_t base = 0; base < ptot; base += 64) {
+        const uint32_t t = base + (uint32_t)lane;
+        const bool has = t < ptot;
+        // this hit's slots in the round: [s0, s1)
+        const bool mine = np && pofs < base + 64 && pofs + np > base;
+        const uint32_t s0 = mine ? (pofs > base ? pofs - base : 0u) : 0u;
+        const uint32_t s1 = mine ? (pofs + np < base + 64 ? pofs + np - base : 64u) : 0u;
+        for (uint32_t sl = s0; sl < s1; ++sl) own[sl] = (uint8_t)lane;  // owner of each slot
+        wave_sync();
+        float f[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) f[k] = 0.f;
-            double Dv = -1.0;
-            if (has) {
-                int lo = 0, hi = 63;  // owner: the last hit whose first pair slot is <= t
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (ps0s[mid] <= t) lo = mid;
-                    else hi = mid - 1;
-                }
-                const uint32_t mt = meta[lo];
-                const uint32_t co = mt & 1023u, nuh = (mt >> 10) & 1023u, ndh = mt >> 20;
-                const uint32_t idx = t - ps0s[lo];
-                const uint32_t iu = idx / ndh, id = idx - iu * ndh;
-                const Cand cu = cand[co + iu], cd = cand[co + nuh + id];
-                const int r = r_all[w][lo];
-                const float xd = g.row_x[r - 1], xm = g.row_x[r], xu = g.row_x[r + 1];
-                const float ymh = ym_all[w][lo], zmh = zm_all[w][lo];
-                features(xd, cd.y, cd.z, xm, ymh, zmh, xu, cu.y, cu.z, wy, wz, (int)nuh, (int)ndh, f);
-                const double wgt = ((double)xm - (double)xd) / ((double)xu - (double)xd);
-                const double yu = cu.y, zu = cu.z, yd = cd.y, zd = cd.z;
-                const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
-                const double ym = ymh, zm = zmh;
-                Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
-            }
-            stage_row(xs + lane * 40, f);
-            wave_sync();
-            const uint32_t in_round = ptot - base < 64u ? ptot - base : 64u;
-            for (uint32_t T = 0; 16 * T < in_round; ++T) {
-                Act A;
-                forward_tile(F, xs + T * 16 * 40, A);
-                if (lane < 16) lg[16 * T + lane] = A.z3;
-            }
-            wave_sync();
-            if (has) {
-                const bool keep = (double)lg[lane] >= kp.tau;
-                kept += keep;
-                dv[lane] = (keep && Dv <= kp.nb_cut) ? Dv : -1.0;
-            }
-            wave_sync();
-            // this hit's slots in the round
-            if (np && pofs < base + 64 && pofs + np > base) {
-                const uint32_t s0 = pofs > base ? pofs : base, s1 = pofs + np < base + 64 ? pofs + np : base + 64;
-                for (uint32_t sl = s0; sl < s1; ++sl) {
-                    const double d = dv[sl - base];
-                    if (!(d >= 0.0)) continue;
-                    const uint32_t idx = sl - pofs;
-                    const uint32_t iu = idx / (uint32_t)nd, id = idx - iu * (uint32_t)nd;
-                    const Cand cu = cand[coff + iu], cd = cand[coff + (uint32_t)nu + id];
-                    if (d < best || (d == best && (cu.id < bu_id || (cu.id == bu_id && cd.id < bd_id)))) {
-                        best = d;
-                        bu = cu.pos;
-                        bd = cd.pos;
-                        bu_id = cu.id;
-                        bd_id = cd.id;
-                    }
-                }
-            }
-            wave_sync();
+        for (int k = 0; k < 12; ++k) f[k] = 0.f;
+        double Dv = -1.0;
+        if (has) {
+            const int lo = own[lane];
+            const uint32_t mt = meta[lo];
+            const uint32_t co = mt & 1023u, nuh = (mt >> 10) & 1023u, ndh = mt >> 20;
+            const uint32_t idx = t - ps0s[lo];
+            const uint32_t iu = idx / ndh, id = idx - iu * ndh;
+            const Cand cu = cand[co + iu], cd = cand[co + nuh + id];
+            const float xd = xd_all[w][lo], xm = xm_all[w][lo], xu = xu_all[w][lo];
+            const float ymh = ym_all[w][lo], zmh = zm_all[w][lo];
+            features(xd, cd.y, cd.z, xm, ymh, zmh, xu, cu.y, cu.z, wy, wz, (int)nuh, (int)ndh, f);
+            const double wgt = ((double)xm - (double)xd) / ((double)xu - (double)xd);
+            const double yu = cu.y, zu = cu.z, yd = cd.y, zd = cd.z;
+            const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
+            const double ym = ymh, zm = zmh;
+            Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
         }
+        stage_row(xs + lane * 40, f);
+        wave_sync();
+        const uint32_t in_round = ptot - base < 64u ? ptot - base : 64u;
+        for (uint32_t T = 0; 16 * T < in_round; ++T) {
+            Act A;
+            forward_tile(F, xs + T * 16 * 40, A);
+            if (lane < 16) lg[16 * T + lane] = A.z3;
+        }
+        wave_sync();
+        const bool keep = has && (double)lg[lane] >= kp.tau;
+        kept += keep;
+        // surviving pairs of the round: a ballot, so that a hit visits only its survivors
+        const uint64_t surv = __ballot(keep && Dv <= kp.nb_cut);
+        dv[lane] = Dv;
+        wave_sync();
+        if (mine) {
+            const uint64_t hi_mask = s1 == 64u ? ~0ull : ((1ull << s1) - 1ull);
+            uint64_t bits = surv & hi_mask & ~((1ull << s0) - 1ull);
+            while (bits) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1ull;
+                const double d = dv[j];
+                const uint32_t idx = base + j - pofs;
+                const uint32_t iu = idx / (uint32_t)nd, id = idx - iu * (uint32_t)nd;
+                const Cand cu = cand[coff + iu], cd = cand[coff + (uint32_t)nu + id];
+                if (d < best || (d == best && (cu.id < bu_id || (cu.id == bu_id && cd.id < bd_id)))) {
+                    best = d;
+                    bu = cu.pos;
+                    bd = cd.pos;
+                    bu_id = cu.id;
+                    bd_id = cd.id;
+                }
+            }
+        }
+        wave_sync();
     }
     if (act) {
         up[p] = bu;
@@ -536,9 +654,9 @@ __global__ __launch_bounds__(64 * kPW) void k_nb_pairs(GridDesc g, KParams kp, c
     const uint32_t linked = bu >= 0;
     uint32_t a = wave_sum(np), b = wave_sum(kept), c = wave_sum(linked);
     if (lane == 0) {
-        if (a) atomicAdd(&counters[C_N_PAIRS], a);
-        if (b) atomicAdd(&counters[C_N_PAIRS_KEPT], b);
-        if (c) atomicAdd(&counters[C_N_LINKS_RAW], c);
+        tally_add(counters, wave, C_N_PAIRS, a);
+        tally_add(counters, wave, C_N_PAIRS_KEPT, b);
+        tally_add(counters, wave, C_N_LINKS_RAW, c);
     }
 }
 
@@ -652,9 +770,9 @@ __device__ void nb_mlp_wave(uint32_t wave, const GridDesc& g, const KParams& kp,
     // per-wave sums (no block barrier needed: one atomic per wave)
     uint32_t a = wave_sum(np), b = wave_sum(kept), c = wave_sum(linked);
     if (lane == 0) {
-        if (a) atomicAdd(&cnt[C_N_PAIRS], a);
-        if (b) atomicAdd(&cnt[C_N_PAIRS_KEPT], b);
-        if (c) atomicAdd(&cnt[C_N_LINKS_RAW], c);
+        tally_add(cnt, wave, C_N_PAIRS, a);
+        tally_add(cnt, wave, C_N_PAIRS_KEPT, b);
+        tally_add(cnt, wave, C_N_LINKS_RAW, c);
     }
 }
 
@@ -888,15 +1006,30 @@ void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hip
 }
 
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
-                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, hipStream_t s) {
+                    uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, void* cand,
+                    uint32_t* nund, uint32_t* wrec, hipStream_t s) {
     const int64_t waves = (n_max + 63) / 64;
     const unsigned nb = (unsigned)((waves + kPW - 1) / kPW > 0 ? (waves + kPW - 1) / kPW : 1);
-    k_nb_pairs<<<nb, 64 * kPW, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, up, dn, ovf);
+    const uint32_t seg_cap = (uint32_t)(nb_cand_entries(n_max) / kTallyLines);
+    k_nb_cand<<<blocks(n_max), kBlock, 0, s>>>(g, kp, hits, bin_off, counters, (Cand*)cand, seg_cap, nund, wrec, up,
+                                                dn, ovf);
+    k_nb_score<<<nb, 64 * kPW, 0, s>>>(g, kp, hits, counters, (const uint8_t*)q, (const Cand*)cand, nund, wrec, up,
+                                       dn);
     // waves whose candidates overflowed the list (normally none): grid-stride over the overflow list
     k_nb_mlp_fallback<<<64, 64 * kNbWaves, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, ovf, up, dn);
 }
 
 size_t nb_overflow_entries(int64_t n_max) { return (size_t)((n_max + 63) / 64 + 1); }
+
+// room for three candidate records per hit (typical events use about two), and
+// at least one full wave list per segment; a wave that does not fit its segment
+// goes to the overflow list
+size_t nb_cand_entries(int64_t n_max) {
+    int64_t e = 3 * n_max;
+    if (e < (int64_t)kTallyLines * kCapC) e = (int64_t)kTallyLines * kCapC;
+    if (e > 0xF0000000ll) e = 0xF0000000ll;
+    return (size_t)(e / kTallyLines * kTallyLines);
+}
 
 void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                    const uint32_t* counters, uint32_t* cnt, hipStream_t s) {

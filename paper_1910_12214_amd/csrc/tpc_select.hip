@@ -173,18 +173,34 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
     }
 }
 
-__global__ void k_finish(const uint32_t* __restrict__ c, int32_t* __restrict__ out) {
-    if (threadIdx.x != 0) return;
+// 256 threads: thread l adds up tally line l.
+__global__ __launch_bounds__(kTallyLines) void k_finish(const uint32_t* __restrict__ c, int32_t* __restrict__ out) {
+    __shared__ uint32_t part[kTallyLines / 64][4];
+    const int l = threadIdx.x, w = l >> 6;
+    const uint32_t* line = c + C_N_COUNTERS + l * kTallyStride;
+    const uint32_t v0 = wave_sum(line[C_N_PAIRS]), v1 = wave_sum(line[C_N_PAIRS_KEPT]);
+    const uint32_t v2 = wave_sum(line[C_N_LINKS_RAW]), v3 = wave_sum(line[C_N_LINKS_CLEAN]);
+    if ((l & 63) == 0) {
+        part[w][0] = v0;
+        part[w][1] = v1;
+        part[w][2] = v2;
+        part[w][3] = v3;
+    }
+    __syncthreads();
+    if (l != 0) return;
+    uint32_t t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < kTallyLines / 64; ++k)
+        for (int j = 0; j < 4; ++j) t[j] += part[k][j];
     out[TPC_CNT_TRACKS] = (int32_t)c[C_N_TRACKS];
     out[TPC_CNT_TRACK_HITS] = (int32_t)c[C_N_TRACK_HITS];
     out[TPC_CNT_TRACKLETS] = (int32_t)c[C_N_STARTS];
     out[TPC_CNT_VALID_TRACKLETS] = (int32_t)c[C_N_VALID_TL];
     out[TPC_CNT_FIT_FAILURES] = (int32_t)c[C_N_FAIL];
-    out[TPC_CNT_LINKS_RAW] = (int32_t)c[C_N_LINKS_RAW];
-    out[TPC_CNT_LINKS_CLEAN] = (int32_t)c[C_N_LINKS_CLEAN];
+    out[TPC_CNT_LINKS_RAW] = (int32_t)(c[C_N_LINKS_RAW] + t[2]);
+    out[TPC_CNT_LINKS_CLEAN] = (int32_t)(c[C_N_LINKS_CLEAN] + t[3]);
     out[TPC_CNT_VALID_CLUSTERS] = (int32_t)c[C_N_VALID_CLU];
-    out[TPC_CNT_PAIRS] = (int32_t)c[C_N_PAIRS];
-    out[TPC_CNT_PAIRS_KEPT] = (int32_t)c[C_N_PAIRS_KEPT];
+    out[TPC_CNT_PAIRS] = (int32_t)(c[C_N_PAIRS] + t[0]);
+    out[TPC_CNT_PAIRS_KEPT] = (int32_t)(c[C_N_PAIRS_KEPT] + t[1]);
 }
 
 inline unsigned sel_blocks(int64_t t_max) {
@@ -226,7 +242,7 @@ void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc,
 }
 
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s) {
-    k_finish<<<1, 64, 0, s>>>(counters, out_counts);
+    k_finish<<<1, kTallyLines, 0, s>>>(counters, out_counts);
 }
 
 }  // namespace tpc
