@@ -92,7 +92,8 @@ enum {
     TPC_CNT_LINKS_CLEAN,      /* reciprocal upward links */
     TPC_CNT_VALID_CLUSTERS,
     TPC_CNT_PAIRS,            /* candidate (down, up) pairs examined */
-    TPC_CNT_PAIRS_KEPT,       /* pairs passing the scorer (== PAIRS without a scorer) */
+    TPC_CNT_PAIRS_KEPT,       /* with a scorer: pairs within the plain criterion's cut whose logit
+                                 reaches tau (the survivors among which the best pair is chosen) */
     TPC_N_COUNTS = 16
 };
 

@@ -43,10 +43,8 @@ constexpr int kQBytes = kB3 + 16;
 constexpr int mW1 = 0, mB1 = 768, mW2 = 832, mB2 = 4928, mW3 = 4992, mB3 = 5056;
 constexpr int kNP = 5057;
 
-__device__ inline uint16_t bf16_bits(float f) {  // round to nearest, ties to even
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+__device__ inline uint16_t bf16_bits(float f) {  // round to nearest, ties to even (v_cvt_pk_bf16_f32)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ inline float bf16_val(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 __device__ inline __bf16 as_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
@@ -163,6 +161,94 @@ __device__ inline void forward_tile(const Frag& F, const uint16_t* __restrict__ 
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
     A.z3 = part + F.b3;
+}
+
+// Weight fragments only; biases and output weights stay in LDS (kSbFloats floats:
+// b1[64], b2[64], w3[64], b3), which keeps two tiles in flight within the register
+// budget of two waves per SIMD.
+struct FragW {
+    bf16x8 w1[4][2];
+    bf16x8 w2[4][2];
+};
+constexpr int kSbFloats = 3 * 64 + 4;
+
+__device__ inline void load_fragw(const uint8_t* __restrict__ q, FragW& F) {
+    const int lane = threadIdx.x & 63;
+    const bf16x8* w1 = (const bf16x8*)(q + kW1A);
+    const bf16x8* w2 = (const bf16x8*)(q + kW2A);
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            F.w1[T][j] = w1[(T * 2 + j) * 64 + lane];
+            F.w2[T][j] = w2[(T * 2 + j) * 64 + lane];
+        }
+}
+
+// Logits of NT tiles at once, the same arithmetic as forward_tile per tile: the
+// tiles' MFMA chains are independent, so the scheduler interleaves them (one
+// tile's conversions run while the other's products are in flight).
+template <int NT>
+__device__ inline void forward_logits(const FragW& F, const float* __restrict__ sb, const uint16_t* const (&xs)[NT],
+                                      float (&z3)[NT]) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    const float* b1 = sb + 4 * g;
+    const float* b2 = sb + 64 + 4 * g;
+    const float* w3 = sb + 128 + 4 * g;
+    f4 c1[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const uint16_t* row = xs[t] + n * 40;
+        const bf16x8 x0 = x_frag(row, 0, g), x1 = x_frag(row, 1, g);
+#pragma unroll
+        for (int T = 0; T < 4; ++T) {
+            f4 c = *(const f4*)(b1 + 16 * T);
+            c = mfma(F.w1[T][0], x0, c);
+            c1[t][T] = mfma(F.w1[T][1], x1, c);
+        }
+    }
+    uint16_t hs[NT][3][4][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int T = 0; T < 4; ++T)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float h = c1[t][T][i] > 0.f ? c1[t][T][i] : 0.f;
+                split3(h, hs[t][0][T][i], hs[t][1][T][i], hs[t][2][T][i]);
+            }
+    f4 c2[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int T2 = 0; T2 < 4; ++T2) c2[t][T2] = *(const f4*)(b2 + 16 * T2);
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bf16x8 b;
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) b[4 * u + i] = as_bf16(hs[t][s][2 * pr + u][i]);
+#pragma unroll
+                for (int T2 = 0; T2 < 4; ++T2) c2[t][T2] = mfma(F.w2[T2][pr], b, c2[t][T2]);
+            }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        float part = 0.f;
+#pragma unroll
+        for (int T2 = 0; T2 < 4; ++T2) {
+            const f4 w = *(const f4*)(w3 + 16 * T2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part += w[i] * (c2[t][T2][i] > 0.f ? c2[t][T2][i] : 0.f);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        z3[t] = part + sb[192];
+    }
 }
 
 // Features of a triplet (down d, middle m, up u), FP32.
@@ -381,10 +467,11 @@ __global__ __launch_bounds__(kBlock) void k_trip_write(GridDesc g, KParams kp, c
 //
 // Scoring (lane = pair, MFMA): the wave copies its candidate records into LDS
 // (coalesced), recomputes the same prefix sums from the per-hit counts, then in
-// rounds of 64 pairs: features from the LDS list, four 16-pair MFMA tiles, and
-// the plain criterion D in FP64; a pair survives if its logit >= tau and
-// D <= cut.  Lane = hit again: the best surviving pair over this round's slots of
-// the hit (smallest D, ties by (id_up, id_down)).
+// rounds of 64 pairs: the plain criterion D in FP64 from the LDS list; the pairs
+// with D <= cut (only they can survive) stage their features into consecutive
+// rows, scored by as many 16-pair MFMA tiles as they fill; a pair survives if
+// also its logit >= tau.  Lane = hit again: the best surviving pair over this
+// round's slots of the hit (smallest D, ties by (id_up, id_down)).
 constexpr int kPW = 4;        // waves per block (scoring)
 constexpr int kCapC = 512;    // candidate records per wave (10-bit offsets and counts)
 constexpr int kListC = 4;     // window candidates held in registers per window
@@ -519,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_cand(GridDesc g, KParams kp, cons
     }
 }
 
-__global__ __launch_bounds__(64 * kPW) void k_nb_score(GridDesc g, KParams kp, const Hit* __restrict__ hits,
+__global__ __launch_bounds__(64 * kPW) __attribute__((amdgpu_waves_per_eu(2))) void k_nb_score(GridDesc g, KParams kp, const Hit* __restrict__ hits,
                                                        uint32_t* __restrict__ counters, const uint8_t* __restrict__ q,
                                                        const Cand* __restrict__ cand_g,
                                                        const uint32_t* __restrict__ nund,
@@ -533,7 +620,11 @@ __global__ __launch_bounds__(64 * kPW) void k_nb_score(GridDesc g, KParams kp, c
     __shared__ float ym_all[kPW][64], zm_all[kPW][64];
     __shared__ float xd_all[kPW][64], xm_all[kPW][64], xu_all[kPW][64];
     __shared__ uint8_t own_all[kPW][64];
+    __shared__ __attribute__((aligned(16))) float sb[kSbFloats];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < kSbFloats; i += blockDim.x)  // b1, b2, w3 (64 each), b3
+        sb[i] = i < 192 ? ((const float*)(q + kB1))[i] : (i == 192 ? *(const float*)(q + kB3) : 0.f);
+    __syncthreads();
     Cand* cand = cand_all[w];
     uint16_t* xs = xs_all[w];
     float* lg = lg_all[w];
@@ -578,8 +669,8 @@ __global__ __launch_bounds__(64 * kPW) void k_nb_score(GridDesc g, KParams kp, c
     uint32_t bu_id = 0xFFFFFFFFu, bd_id = 0xFFFFFFFFu;
     int32_t bu = -1, bd = -1;
     uint32_t kept = 0;
-    Frag F;
-    load_frag(q, F);
+    FragW F;
+    load_fragw(q, F);
     const float wy = (float)kp.win_y, wz = (float)kp.win_z;
     uint8_t* own = own_all[w];
     for (uint32_t base = 0; base < ptot; base += 64) {
@@ -591,39 +682,55 @@ __global__ __launch_bounds__(64 * kPW) void k_nb_score(GridDesc g, KParams kp, c
         const uint32_t s1 = mine ? (pofs + np < base + 64 ? pofs + np - base : 64u) : 0u;
         for (uint32_t sl = s0; sl < s1; ++sl) own[sl] = (uint8_t)lane;  // owner of each slot
         wave_sync();
-        float f[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) f[k] = 0.f;
+        // the plain criterion first: only pairs within its cut need a logit (a pair
+        // survives if D <= cut and logit >= tau, in either order)
         double Dv = -1.0;
+        Cand cu, cd;
+        float xd = 0.f, xm = 0.f, xu = 0.f, ymh = 0.f, zmh = 0.f;
+        uint32_t nuh = 0, ndh = 0;
         if (has) {
             const int lo = own[lane];
             const uint32_t mt = meta[lo];
-            const uint32_t co = mt & 1023u, nuh = (mt >> 10) & 1023u, ndh = mt >> 20;
+            const uint32_t co = mt & 1023u;
+            nuh = (mt >> 10) & 1023u;
+            ndh = mt >> 20;
             const uint32_t idx = t - ps0s[lo];
             const uint32_t iu = idx / ndh, id = idx - iu * ndh;
-            const Cand cu = cand[co + iu], cd = cand[co + nuh + id];
-            const float xd = xd_all[w][lo], xm = xm_all[w][lo], xu = xu_all[w][lo];
-            const float ymh = ym_all[w][lo], zmh = zm_all[w][lo];
-            features(xd, cd.y, cd.z, xm, ymh, zmh, xu, cu.y, cu.z, wy, wz, (int)nuh, (int)ndh, f);
+            cu = cand[co + iu];
+            cd = cand[co + nuh + id];
+            xd = xd_all[w][lo];
+            xm = xm_all[w][lo];
+            xu = xu_all[w][lo];
+            ymh = ym_all[w][lo];
+            zmh = zm_all[w][lo];
             const double wgt = ((double)xm - (double)xd) / ((double)xu - (double)xd);
             const double yu = cu.y, zu = cu.z, yd = cd.y, zd = cd.z;
             const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
             const double ym = ymh, zm = zmh;
             Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
         }
-        stage_row(xs + lane * 40, f);
-        wave_sync();
-        const uint32_t in_round = ptot - base < 64u ? ptot - base : 64u;
-        for (uint32_t T = 0; 16 * T < in_round; ++T) {
-            Act A;
-            forward_tile(F, xs + T * 16 * 40, A);
-            if (lane < 16) lg[16 * T + lane] = A.z3;
+        const bool pass = has && Dv <= kp.nb_cut;
+        const uint64_t pm = __ballot(pass);
+        const uint32_t n_pass = (uint32_t)__builtin_popcountll(pm);
+        // rank among the passing lanes: their features fill tile rows 0 .. n_pass - 1
+        const uint32_t ci = __builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+        if (pass) {
+            float f[12];
+            features(xd, cd.y, cd.z, xm, ymh, zmh, xu, cu.y, cu.z, wy, wz, (int)nuh, (int)ndh, f);
+            stage_row(xs + ci * 40, f);
         }
         wave_sync();
-        const bool keep = has && (double)lg[lane] >= kp.tau;
+        for (uint32_t T = 0; 16 * T < n_pass; ++T) {  // rows past n_pass: stale, their logits unused
+            const uint16_t* const xp[1] = {xs + T * 16 * 40};
+            float z[1];
+            forward_logits<1>(F, sb, xp, z);
+            if (lane < 16) lg[16 * T + lane] = z[0];
+        }
+        wave_sync();
+        const bool keep = pass && (double)lg[ci] >= kp.tau;
         kept += keep;
         // surviving pairs of the round: a ballot, so that a hit visits only its survivors
-        const uint64_t surv = __ballot(keep && Dv <= kp.nb_cut);
+        const uint64_t surv = __ballot(keep);
         dv[lane] = Dv;
         wave_sync();
         if (mine) {
@@ -743,11 +850,11 @@ __device__ void nb_mlp_wave(uint32_t wave, const GridDesc& g, const KParams& kp,
                     const uint32_t sl = slot0 + j++;
                     if (sl < base || sl >= base + lim) return;
                     if (!((double)lg[sl - base] >= kp.tau)) return;
-                    ++kept;
                     const double yu = u.y, zu = u.z, yd = d.y, zd = d.z;
                     const double py = yd + (yu - yd) * wgt, pz = zd + (zu - zd) * wgt;
                     const double Dv = (ym - py) * (ym - py) * kp.ivy15 + (zm - pz) * (zm - pz) * kp.ivz15;
                     if (!(Dv <= kp.nb_cut)) return;
+                    ++kept;
                     if (Dv < best || (Dv == best && (u.id < bu_id || (u.id == bu_id && d.id < bd_id)))) {
                         best = Dv;
                         bu = (int32_t)ku;

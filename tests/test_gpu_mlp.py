@@ -163,7 +163,9 @@ def test_pruned_tracking_parity(ctx, frac):
     rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma)
     c = trk["counts"]
     say(f"[mlp] pruned parity: {rep.line()} pairs={c[tpcca.CNT_PAIRS]} kept={c[tpcca.CNT_PAIRS_KEPT]}")
-    assert 0.3 < c[tpcca.CNT_PAIRS_KEPT] / c[tpcca.CNT_PAIRS] < 0.7
+    # kept = pairs within the plain criterion's cut whose logit reaches tau: below the
+    # half that tau alone keeps, and at least one per linked hit
+    assert c[tpcca.CNT_LINKS_RAW] <= c[tpcca.CNT_PAIRS_KEPT] < 0.7 * c[tpcca.CNT_PAIRS]
     assert rep["tracks_compared"] > 500
 
 
