@@ -94,6 +94,8 @@ enum {
     TPC_CNT_PAIRS,            /* candidate (down, up) pairs examined */
     TPC_CNT_PAIRS_KEPT,       /* with a scorer: pairs within the plain criterion's cut whose logit
                                  reaches tau (the survivors among which the best pair is chosen) */
+    TPC_CNT_NB_OVERFLOW,      /* with a scorer: 64-hit groups whose window candidates exceeded the
+                                 scoring kernel's list and were scored by the per-lane kernel */
     TPC_N_COUNTS = 16
 };
 

@@ -201,6 +201,7 @@ __global__ __launch_bounds__(kTallyLines) void k_finish(const uint32_t* __restri
     out[TPC_CNT_VALID_CLUSTERS] = (int32_t)c[C_N_VALID_CLU];
     out[TPC_CNT_PAIRS] = (int32_t)(c[C_N_PAIRS] + t[0]);
     out[TPC_CNT_PAIRS_KEPT] = (int32_t)(c[C_N_PAIRS_KEPT] + t[1]);
+    out[TPC_CNT_NB_OVERFLOW] = (int32_t)c[C_NB_OVF];
 }
 
 inline unsigned sel_blocks(int64_t t_max) {

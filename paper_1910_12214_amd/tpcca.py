@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libtpcca.so")
 
 TPC_OK, TPC_ERR_ARG, TPC_ERR_CAPACITY, TPC_ERR_HIP, TPC_ERR_STATE = 0, -1, -2, -3, -4
 (CNT_TRACKS, CNT_TRACK_HITS, CNT_TRACKLETS, CNT_VALID_TRACKLETS, CNT_FIT_FAILURES, CNT_LINKS_RAW,
- CNT_LINKS_CLEAN, CNT_VALID_CLUSTERS, CNT_PAIRS, CNT_PAIRS_KEPT) = range(10)
+ CNT_LINKS_CLEAN, CNT_VALID_CLUSTERS, CNT_PAIRS, CNT_PAIRS_KEPT, CNT_NB_OVERFLOW) = range(11)
 N_COUNTS = 16
 (STAGE_HITS, STAGE_ROW_OFF, STAGE_BIN_BASE, STAGE_BIN_OFF, STAGE_UP, STAGE_DN, STAGE_UP_CLEAN, STAGE_DN_CLEAN,
  STAGE_STARTS, STAGE_TL_NHITS, STAGE_TL_HITS, STAGE_TL_STATE, STAGE_TL_COV, STAGE_TL_FLAGS, STAGE_HIT_KEY,

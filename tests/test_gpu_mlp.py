@@ -169,6 +169,38 @@ def test_pruned_tracking_parity(ctx, frac):
     assert rep["tracks_compared"] > 500
 
 
+def test_pruned_parity_when_candidate_lists_overflow(ctx):
+    """The one-sector event with windows three times as wide: some 64-hit groups have more window
+    candidates than the scoring kernel's LDS list holds (or than their list segment has room
+    for); the per-lane kernel scores those groups, and every stage still matches the oracle."""
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.SECTOR_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    prm0 = dict(synth.TRACKER_PARAMS, win_y=6.0, win_z=6.0)
+    theta = theta_random(23)
+    trip, feats = ctx.triplets(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, prm0)
+    lg = ctx.mlp_infer(feats, dev(theta)).cpu().numpy()
+    tau = float(np.quantile(lg, 0.5))
+    out = ctx.track(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ, prm0, mlp=dev(theta),
+                    tau_logit=tau)
+    trk = tpcca.tracks_to_host(out)
+    st = parity.gpu_stages(ctx, synth.N_ROWS)
+    prm = dict(prm0, mlp_tau_logit=tau, mlp_flag_abs=1e-4)
+    qtheta = omlp.quantize(theta)
+    o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=qtheta, n_threads=THREADS)
+    o_fma = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=qtheta, n_threads=THREADS, fma=True)
+    c = trk["counts"]
+    groups = (ev.n + 63) // 64
+    say(f"[mlp] wide windows: {len(trip)} pairs, {c[tpcca.CNT_NB_OVERFLOW]} of {groups} groups overflowed")
+    assert 0 < c[tpcca.CNT_NB_OVERFLOW] <= groups
+    assert c[tpcca.CNT_PAIRS] == len(trip)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma)
+    say(f"[mlp] wide windows parity: {rep.line()}")
+    assert rep["tracks_compared"] > 50
+
+
 def test_trained_scorer_gain_over_untrained(ctx):
     """What the trained network gains over the method without it.  On held-out one-sector events it
     removes about half of the candidate pairs before the automaton, keeps nearly every true triplet
