@@ -1,7 +1,8 @@
 // Device-wide exclusive scan of uint32 and fill kernels.
 //
-// Three passes (block sums -> scan of block sums -> block scan + offset) with
-// 2048 elements per 256-thread block.  The element count may live in device
+// 2048 elements per 256-thread block.  Up to kSmallTiles tiles: two passes (block
+// sums, then each block adds up the sums before it and scans its tile); more:
+// three (block sums -> scan of block sums -> block scan + offset).  The element count may live in device
 // memory (counts produced by an earlier kernel), so the whole chain can be
 // enqueued (and captured in a graph) without a host round trip.
 #include "tpc_internal.h"
@@ -96,6 +97,42 @@ __global__ __launch_bounds__(kBlock) void k_apply(const uint32_t* in, uint32_t* 
     }
 }
 
+// Second pass of the two-pass scan: the tile's offset is the sum of the block sums
+// before it (at most kSmallTiles, read by the whole block), then as k_apply.
+constexpr int64_t kSmallTiles = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_apply_pre(const uint32_t* in, uint32_t* out, int64_t n_max,
+                                                      const uint32_t* __restrict__ n_dev,
+                                                      const uint32_t* __restrict__ part, uint32_t* __restrict__ total) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= n) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0;  // n == 0
+        return;
+    }
+    uint32_t pre = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kBlock) pre += part[k];
+    uint32_t prefix;
+    block_excl_scan(pre, &prefix);
+    const int64_t my = base + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        v[i] = (my + i < n) ? in[my + i] : 0;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot) + prefix;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        if (my + i < n) out[my + i] = off;
+        off += v[i];
+    }
+    // the last tile's last thread holds the grand total
+    if (total && base + kTile >= n && threadIdx.x == kBlock - 1) *total = off;
+}
+
 __global__ void k_fill32(uint32_t* p, uint32_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -122,6 +159,10 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* 
     if (nb < 1) nb = 1;
     uint32_t* part = (uint32_t*)scratch;
     k_reduce<<<(unsigned)nb, kBlock, 0, s>>>(in, n_max, n_dev, part);
+    if (nb <= kSmallTiles) {
+        k_apply_pre<<<(unsigned)nb, kBlock, 0, s>>>(in, out, n_max, n_dev, part, total_dev);
+        return;
+    }
     k_scan_parts<<<1, kBlock, 0, s>>>(part, nb, total_dev);
     k_apply<<<(unsigned)nb, kBlock, 0, s>>>(in, out, n_max, n_dev, part);
 }
