@@ -15,10 +15,11 @@
 // ~1e-5 of tau.  Training's backward pass uses single BF16 operands (its result
 // is a gradient, compared at BF16 tolerance).
 //
-// Fused pruning (neighbour finding with a scorer): each wave enumerates the
-// candidate (down, up) pairs of its 64 hits, stages their features in LDS
-// (ballot-free: slots from a wave prefix sum of per-lane pair counts), scores
-// 16 pairs per MFMA tile, and each lane then chooses its best surviving pair.
+// Neighbour finding with a scorer: a candidate kernel lists the window
+// candidates of each 64-hit group, a scoring kernel numbers the group's
+// (down, up) pairs by a wave prefix sum, applies the plain criterion, scores the
+// pairs within its cut 16 per MFMA tile from LDS-staged features, and each hit
+// then chooses its best surviving pair.
 #include "tpc_device.h"
 #include "tpc_internal.h"
 
@@ -164,8 +165,7 @@ __device__ inline void forward_tile(const Frag& F, const uint16_t* __restrict__ 
 }
 
 // Weight fragments only; biases and output weights stay in LDS (kSbFloats floats:
-// b1[64], b2[64], w3[64], b3), which keeps two tiles in flight within the register
-// budget of two waves per SIMD.
+// b1[64], b2[64], w3[64], b3), 48 registers fewer than Frag.
 struct FragW {
     bf16x8 w1[4][2];
     bf16x8 w2[4][2];
@@ -185,70 +185,55 @@ __device__ inline void load_fragw(const uint8_t* __restrict__ q, FragW& F) {
         }
 }
 
-// Logits of NT tiles at once, the same arithmetic as forward_tile per tile: the
-// tiles' MFMA chains are independent, so the scheduler interleaves them (one
-// tile's conversions run while the other's products are in flight).
-template <int NT>
-__device__ inline void forward_logits(const FragW& F, const float* __restrict__ sb, const uint16_t* const (&xs)[NT],
-                                      float (&z3)[NT]) {
+// Logits of one 16-pair tile (rows xs, stride 40 BF16), the same arithmetic as
+// forward_tile with the biases and output weights read from LDS (sb: b1, b2, w3, b3).
+__device__ inline float tile_logit(const FragW& F, const float* __restrict__ sb, const uint16_t* __restrict__ xs) {
     const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
     const float* b1 = sb + 4 * g;
     const float* b2 = sb + 64 + 4 * g;
     const float* w3 = sb + 128 + 4 * g;
-    f4 c1[NT][4];
+    const uint16_t* row = xs + n * 40;
+    const bf16x8 x0 = x_frag(row, 0, g), x1 = x_frag(row, 1, g);
+    f4 c1[4];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const uint16_t* row = xs[t] + n * 40;
-        const bf16x8 x0 = x_frag(row, 0, g), x1 = x_frag(row, 1, g);
-#pragma unroll
-        for (int T = 0; T < 4; ++T) {
-            f4 c = *(const f4*)(b1 + 16 * T);
-            c = mfma(F.w1[T][0], x0, c);
-            c1[t][T] = mfma(F.w1[T][1], x1, c);
-        }
+    for (int T = 0; T < 4; ++T) {
+        f4 c = *(const f4*)(b1 + 16 * T);
+        c = mfma(F.w1[T][0], x0, c);
+        c1[T] = mfma(F.w1[T][1], x1, c);
     }
-    uint16_t hs[NT][3][4][4];
+    uint16_t hs[3][4][4];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int T = 0; T < 4; ++T)
 #pragma unroll
-        for (int T = 0; T < 4; ++T)
+        for (int i = 0; i < 4; ++i) {
+            const float h = c1[T][i] > 0.f ? c1[T][i] : 0.f;
+            split3(h, hs[0][T][i], hs[1][T][i], hs[2][T][i]);
+        }
+    f4 c2[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float h = c1[t][T][i] > 0.f ? c1[t][T][i] : 0.f;
-                split3(h, hs[t][0][T][i], hs[t][1][T][i], hs[t][2][T][i]);
-            }
-    f4 c2[NT][4];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int T2 = 0; T2 < 4; ++T2) c2[t][T2] = *(const f4*)(b2 + 16 * T2);
+    for (int T2 = 0; T2 < 4; ++T2) c2[T2] = *(const f4*)(b2 + 16 * T2);
 #pragma unroll
     for (int s = 0; s < 3; ++s)
 #pragma unroll
-        for (int pr = 0; pr < 2; ++pr)
+        for (int pr = 0; pr < 2; ++pr) {
+            bf16x8 b;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                bf16x8 b;
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int i = 0; i < 4; ++i) b[4 * u + i] = as_bf16(hs[s][2 * pr + u][i]);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) b[4 * u + i] = as_bf16(hs[t][s][2 * pr + u][i]);
-#pragma unroll
-                for (int T2 = 0; T2 < 4; ++T2) c2[t][T2] = mfma(F.w2[T2][pr], b, c2[t][T2]);
-            }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        float part = 0.f;
-#pragma unroll
-        for (int T2 = 0; T2 < 4; ++T2) {
-            const f4 w = *(const f4*)(w3 + 16 * T2);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) part += w[i] * (c2[t][T2][i] > 0.f ? c2[t][T2][i] : 0.f);
+            for (int T2 = 0; T2 < 4; ++T2) c2[T2] = mfma(F.w2[T2][pr], b, c2[T2]);
         }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        z3[t] = part + sb[192];
+    float part = 0.f;
+#pragma unroll
+    for (int T2 = 0; T2 < 4; ++T2) {
+        const f4 w = *(const f4*)(w3 + 16 * T2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part += w[i] * (c2[T2][i] > 0.f ? c2[T2][i] : 0.f);
     }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    return part + sb[192];
 }
 
 // Features of a triplet (down d, middle m, up u), FP32.
@@ -721,10 +706,8 @@ __global__ __launch_bounds__(64 * kPW) __attribute__((amdgpu_waves_per_eu(2))) v
         }
         wave_sync();
         for (uint32_t T = 0; 16 * T < n_pass; ++T) {  // rows past n_pass: stale, their logits unused
-            const uint16_t* const xp[1] = {xs + T * 16 * 40};
-            float z[1];
-            forward_logits<1>(F, sb, xp, z);
-            if (lane < 16) lg[16 * T + lane] = z[0];
+            const float z = tile_logit(F, sb, xs + T * 16 * 40);
+            if (lane < 16) lg[16 * T + lane] = z;
         }
         wave_sync();
         const bool keep = pass && (double)lg[ci] >= kp.tau;
