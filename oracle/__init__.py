@@ -110,6 +110,9 @@ def _load(path: str = _LIB_PATH):
         lib.or_mlp_logit.restype = ctypes.c_double
         lib.or_features.argtypes = [ctypes.c_double] * 11 + [ctypes.c_int, ctypes.c_int, d]
         lib.or_features.restype = None
+        lib.or_cluster_flags.argtypes = [ctypes.POINTER(_FlagsIn), ctypes.POINTER(ctypes.c_uint8),
+                                         ctypes.POINTER(ctypes.c_uint8)]
+        lib.or_cluster_flags.restype = ctypes.c_int
         _libs[path] = lib
     return lib
 
@@ -265,3 +268,74 @@ def track(y, z, row, sector, geometry: dict, params: dict, bz: float, mlp: np.nd
         res["n_tracks"] = nt
     lib.or_free(ctypes.byref(out))
     return res
+
+
+# ---------------------------------------------------------------- cluster flags (Sec. 4)
+FLAG_ATTACHED, FLAG_ADJACENT, FLAG_PROTECTED, FLAG_REMOVE_A, FLAG_REMOVE_B = 1, 2, 4, 8, 16
+
+
+class _FlagsIn(ctypes.Structure):
+    _P = ctypes.POINTER
+    _fields_ = [("n", ctypes.c_int64), ("y", _P(ctypes.c_float)), ("z", _P(ctypes.c_float)),
+                ("row", _P(ctypes.c_uint8)), ("sector", _P(ctypes.c_uint8)),
+                ("n_rows", ctypes.c_int), ("n_sectors", ctypes.c_int), ("row_x", _P(ctypes.c_float)),
+                ("kq", ctypes.c_double), ("s_max", ctypes.c_double), ("n_tracks", ctypes.c_int32),
+                ("off", _P(ctypes.c_int32)), ("nh", _P(ctypes.c_int32)), ("hits", _P(ctypes.c_int32)),
+                ("trk_sector", _P(ctypes.c_int32)), ("x_ref", _P(ctypes.c_float)), ("state", _P(ctypes.c_float)),
+                ("tube", ctypes.c_double), ("pt_min", ctypes.c_double), ("sin_phi_max", ctypes.c_double)]
+
+
+def tracks_for_flags(o: dict, geometry: dict, sector) -> dict:
+    """The oracle's tracks (from ``track``) in the form ``cluster_flags`` takes: CSR hits,
+    sector of the start hit, x of the reference row and the FP32-rounded state there."""
+    nt = int(o["n_tracks"])
+    off = o["trk_off"][:nt].astype(np.int32)
+    nh = np.diff(o["trk_off"][:nt + 1]).astype(np.int32)
+    hits = o["trk_hits"].astype(np.int32)
+    tl = o["trk_tl"][:nt]
+    rx = np.asarray(geometry["row_x"], dtype=np.float32)
+    sec = np.asarray(sector)[hits[off]] if nt else np.zeros(0, np.int32)
+    return {"off": off, "nh": nh, "hits": hits, "sector": sec.astype(np.int32),
+            "x_ref": rx[o["tl_row_ref"][tl]].astype(np.float32),
+            "state": o["tl_state"][tl].astype(np.float32)}
+
+
+def cluster_flags(y, z, row, sector, geometry: dict, bz: float, tracks: dict, tube: float = 1.5,
+                  pt_min: float = 0.05, phi_max_deg: float = 70.0, s_max: float = 0.999, fma: bool = False):
+    """Attachment / adjacency / protection / removal flags per cluster (Sec. 4).
+
+    tracks: off, nh, hits (CSR of cluster ids, ascending row), sector, x_ref (float32) and
+    state (float32 [n, 5]).  Returns (flags uint8[n], tie uint8[n]); tie marks clusters whose
+    decision lies within 1e-9 (relative) of a cut.
+    """
+    lib = _load(_LIB_FMA_PATH if fma else _LIB_PATH)
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(np.ctypeslib.as_ctypes_type(dt)))
+
+    inp = _FlagsIn()
+    n = int(np.asarray(y).shape[0])
+    inp.n = n
+    inp.y, inp.z = arr(y, np.float32), arr(z, np.float32)
+    inp.row, inp.sector = arr(row, np.uint8), arr(sector, np.uint8)
+    inp.n_rows, inp.n_sectors = int(geometry["n_rows"]), int(geometry["n_sectors"])
+    inp.row_x = arr(geometry["row_x"], np.float32)
+    inp.kq, inp.s_max = KQ_PER_TESLA * float(bz), float(s_max)
+    inp.n_tracks = int(len(tracks["off"]))
+    inp.off, inp.nh, inp.hits = arr(tracks["off"], np.int32), arr(tracks["nh"], np.int32), arr(
+        tracks["hits"] if len(tracks["hits"]) else np.zeros(1), np.int32)
+    inp.trk_sector = arr(tracks["sector"], np.int32)
+    inp.x_ref = arr(tracks["x_ref"], np.float32)
+    inp.state = arr(np.asarray(tracks["state"]).reshape(-1), np.float32)
+    inp.tube, inp.pt_min = float(tube), float(pt_min)
+    inp.sin_phi_max = float(np.sin(np.deg2rad(phi_max_deg)))
+    flags = np.zeros(max(n, 1), dtype=np.uint8)
+    tie = np.zeros(max(n, 1), dtype=np.uint8)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    rc = lib.or_cluster_flags(ctypes.byref(inp), flags.ctypes.data_as(u8), tie.ctypes.data_as(u8))
+    if rc != 0:
+        raise MemoryError("oracle cluster flags: allocation failed")
+    return flags[:n], tie[:n]

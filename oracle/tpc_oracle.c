@@ -746,3 +746,130 @@ int or_track(const or_input_t* in, const or_params_t* P, int stages, or_output_t
     o->n_track_hits = o->trk_off[o->n_tracks];
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Cluster attachment, adjacency and the removal strategies (Sec. 4, cluster removal).
+ *
+ * A cluster is attached to the track it belongs to.  It is adjacent to a track when it lies on
+ * a pad row the track spans (innermost to outermost hit row) within a tube of radius `tube`
+ * around it: (y - y_t)^2 + (z - z_t)^2 <= tube^2 on the row plane, with (y_t, z_t) the track's
+ * helix propagated from its reference state to that row.  Ambiguities go to the higher-momentum
+ * track (smaller |q/pT|, then the smaller track index).  The cluster is protected when that track
+ * has pT > pt_min and a local inclination |phi| < phi_max on the cluster's row; strategy A removes
+ * the unprotected clusters that are attached or adjacent to a track, strategy B every unprotected
+ * cluster.  Tracks are not merged into legs here, so every track counts as a primary leg.
+ * Brute force: every cluster of the track's sector and row is tested.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const float *y, *z;
+    const uint8_t *row, *sector;
+    int n_rows, n_sectors;
+    const float* row_x;
+    double kq, s_max;
+    int32_t n_tracks;
+    const int32_t *off, *nh, *hits, *trk_sector;
+    const float *x_ref, *state;   /* state: 5 per track (y, z, sin phi, dz/ds, q/pT) */
+    double tube, pt_min, sin_phi_max;
+} or_flags_in_t;
+
+enum { OF_ATTACHED = 1, OF_ADJACENT = 2, OF_PROTECTED = 4, OF_REMOVE_A = 8, OF_REMOVE_B = 16 };
+
+/* track k's helix at x: y, z and sin phi; 0 when the helix does not reach x */
+static int or_helix_at(const or_flags_in_t* in, int32_t k, double x, double* yt, double* zt, double* st) {
+    double p0[5], p1[5];
+    for (int i = 0; i < 5; ++i) p0[i] = (double)in->state[5 * k + i];
+    if (or_propagate(p0, (double)in->x_ref[k], x, in->kq, in->s_max, 0.0, p1, NULL, NULL)) return 0;
+    *yt = p1[0];
+    *zt = p1[1];
+    *st = p1[2];
+    return 1;
+}
+
+/* key of track k: larger for higher momentum, then for the smaller index */
+static uint64_t or_track_key(const or_flags_in_t* in, int32_t k) {
+    float a = fabsf(in->state[5 * k + 4]);
+    uint32_t bits;
+    memcpy(&bits, &a, 4);
+    return ((uint64_t)(0xFFFFFFFFu - bits) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+}
+
+/* flags[n]; tie[n] (may be NULL): 1 where a decision lies within 1e-9 (relative) of its cut */
+int or_cluster_flags(const or_flags_in_t* in, uint8_t* flags, uint8_t* tie) {
+    const int64_t n = in->n;
+    const int R = in->n_rows, S = in->n_sectors;
+    uint64_t* best = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    double* best_s = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    uint8_t* att = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    uint8_t* adj = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t* first = (int64_t*)malloc(sizeof(int64_t) * ((size_t)S * R + 1));
+    int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!best || !best_s || !att || !adj || !first || !list) return 1;
+    if (tie) memset(tie, 0, (size_t)n);
+    /* clusters listed per (sector, row) */
+    for (int64_t i = 0; i <= (int64_t)S * R; ++i) first[i] = 0;
+    for (int64_t c = 0; c < n; ++c)
+        if (in->row[c] < R && in->sector[c] < S) ++first[in->sector[c] * R + in->row[c] + 1];
+    for (int64_t i = 0; i < (int64_t)S * R; ++i) first[i + 1] += first[i];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)S * R));
+        for (int64_t i = 0; i < (int64_t)S * R; ++i) fill[i] = first[i];
+        for (int64_t c = 0; c < n; ++c)
+            if (in->row[c] < R && in->sector[c] < S) list[fill[in->sector[c] * R + in->row[c]]++] = c;
+        free(fill);
+    }
+    const double t2 = in->tube * in->tube;
+    for (int32_t k = 0; k < in->n_tracks; ++k) {
+        const uint64_t key = or_track_key(in, k);
+        const int s = in->trk_sector[k];
+        const int32_t* h = in->hits + in->off[k];
+        const int nh = in->nh[k];
+        if (nh <= 0) continue;
+        const int r0 = in->row[h[0]], r1 = in->row[h[nh - 1]];
+        /* adjacency: every cluster of the spanned rows within the tube */
+        for (int r = r0; r <= r1; ++r) {
+            double yt, zt, st;
+            if (!or_helix_at(in, k, (double)in->row_x[r], &yt, &zt, &st)) continue;
+            for (int64_t j = first[s * R + r]; j < first[s * R + r + 1]; ++j) {
+                const int64_t c = list[j];
+                const double dy = (double)in->y[c] - yt, dz = (double)in->z[c] - zt;
+                const double d2 = dy * dy + dz * dz;
+                if (tie && fabs(d2 - t2) <= 1e-9 * t2) tie[c] = 1;
+                if (!(d2 <= t2)) continue;
+                adj[c] = 1;
+                if (key > best[c]) {
+                    best[c] = key;
+                    best_s[c] = st;
+                }
+            }
+        }
+        /* attachment: the track's own clusters, inside the tube or not */
+        for (int i = 0; i < nh; ++i) {
+            const int64_t c = h[i];
+            att[c] = 1;
+            double yt, zt, st;
+            if (!or_helix_at(in, k, (double)in->row_x[in->row[c]], &yt, &zt, &st)) st = 2.0; /* never protected */
+            if (key > best[c]) {
+                best[c] = key;
+                best_s[c] = st;
+            }
+        }
+    }
+    const float qpt_max = (float)(1.0 / in->pt_min);
+    for (int64_t c = 0; c < n; ++c) {
+        uint8_t f = (att[c] ? OF_ATTACHED : 0) | (adj[c] ? OF_ADJACENT : 0);
+        int prot = 0;
+        if (best[c]) {
+            /* the assigned track: its |q/pT| and its sin phi on this row */
+            const int32_t k = (int32_t)(0xFFFFFFFFu - (uint32_t)(best[c] & 0xFFFFFFFFu));
+            const float a = fabsf(in->state[5 * k + 4]);
+            prot = a < qpt_max && fabs(best_s[c]) < in->sin_phi_max;
+            if (tie && fabs(fabs(best_s[c]) - in->sin_phi_max) <= 1e-9) tie[c] = 1;
+            f |= prot ? OF_PROTECTED : OF_REMOVE_A;
+        }
+        if (!prot) f |= OF_REMOVE_B;
+        flags[c] = f;
+    }
+    free(best); free(best_s); free(att); free(adj); free(first); free(list);
+    return 0;
+}
