@@ -119,6 +119,22 @@ typedef struct {
     int32_t* ndf;           /* [cap_tracks] */
 } tpc_tracks_t;
 
+/* Cluster flags (bits of one byte per cluster) written by tpc_cluster_flags. */
+enum {
+    TPC_FLAG_ATTACHED = 1,    /* a hit of a track */
+    TPC_FLAG_ADJACENT = 2,    /* within the tube around a track on a row the track spans */
+    TPC_FLAG_PROTECTED = 4,   /* assigned track has pT > pt_min and local |phi| < phi_max */
+    TPC_FLAG_REMOVE_A = 8,    /* strategy A: attached or adjacent, and not protected */
+    TPC_FLAG_REMOVE_B = 16    /* strategy B: not protected */
+};
+
+/* Cluster-removal settings (Sec. 4).  tpc_flag_params_default: 1.5 cm, 0.05 GeV/c, 70 deg. */
+typedef struct {
+    double tube_cm;         /* adjacency tube radius on the pad-row plane, > 0 */
+    double pt_min;          /* protection needs pT > pt_min (GeV/c), > 0 */
+    double phi_max_deg;     /* protection needs local |phi| < phi_max, in (0, 90) */
+} tpc_flag_params_t;
+
 /* Create a context on HIP device `device`.  *ctx receives the handle. */
 int tpc_ctx_create(tpc_ctx_t** ctx, int device);
 /* Release a context and its scratch memory (waits for its outstanding work). */
@@ -135,6 +151,23 @@ void tpc_params_default(tpc_params_t* p);
 int tpc_track_sectors(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom,
                       double bz_tesla, const tpc_params_t* params, tpc_tracks_t* out, void* stream,
                       int sync_check);
+
+/* Cluster attachment, adjacency, protection and removal flags for a track set
+ * (Sec. 4, cluster removal: the 1.5 cm tube, ambiguities resolved to the
+ * higher-momentum track, protection of tracks above 50 MeV/c with local
+ * |phi| < 70 deg, strategies A and B).  `tracks` is read only: its counts
+ * (TPC_CNT_TRACKS, device), hit_offset, n_hits, hit_ids (ascending row),
+ * sector, x_ref and state; a track's tube covers the rows from its first to
+ * its last hit, on its own sector.  Legs of looping tracks are not merged, so
+ * every track counts as a primary leg.  `flags` (device, caller-owned) gets one
+ * byte per cluster; `params` supplies the grid bin size and s_max (the other
+ * fields are unused).  Enqueued on `stream`, no host synchronisation; returns
+ * TPC_ERR_ARG for invalid arguments. */
+int tpc_cluster_flags(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom,
+                      double bz_tesla, const tpc_params_t* params, const tpc_flag_params_t* flag_params,
+                      const tpc_tracks_t* tracks, uint8_t* flags, void* stream);
+/* The settings of Sec. 4: tube 1.5 cm, pt_min 0.05 GeV/c, phi_max 70 deg. */
+void tpc_flag_params_default(tpc_flag_params_t* p);
 
 /* Track a whole continuous-readout time frame (Sec. 1) in one graph launch:
  * persistent work-queue kernels, captured as a HIP graph per input shape, with

@@ -442,6 +442,48 @@ int tpc_track_sectors(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     return TPC_OK;
 }
 
+void tpc_flag_params_default(tpc_flag_params_t* p) {
+    if (!p) return;
+    p->tube_cm = 1.5;
+    p->pt_min = 0.05;
+    p->phi_max_deg = 70.0;
+}
+
+int tpc_cluster_flags(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz,
+                      const tpc_params_t* p, const tpc_flag_params_t* fp, const tpc_tracks_t* trk, uint8_t* flags,
+                      void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p))) return rc;
+    if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
+    if (!fp || !(fp->tube_cm > 0.0) || !std::isfinite(fp->tube_cm) || !(fp->pt_min > 0.0) ||
+        !std::isfinite(fp->pt_min) || !(fp->phi_max_deg > 0.0) || !(fp->phi_max_deg < 90.0))
+        return fail(c, TPC_ERR_ARG, "flag parameters: need tube_cm > 0, pt_min > 0, 0 < phi_max_deg < 90");
+    if (!trk || trk->cap_tracks < 0 || !trk->counts ||
+        (trk->cap_tracks > 0 && (!trk->hit_offset || !trk->n_hits || !trk->hit_ids || !trk->sector ||
+                                 !trk->x_ref || !trk->state)))
+        return fail(c, TPC_ERR_ARG, "tracks: counts and, for cap_tracks > 0, hit_offset, n_hits, hit_ids, "
+                                    "sector, x_ref and state are required");
+    if (cl->n > 0 && !flags) return fail(c, TPC_ERR_ARG, "flags output is NULL");
+    TPC_HIP(c, hipSetDevice(c->device));
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
+    Scratch s;
+    if ((rc = alloc_scratch(c, pr, &s, false))) return rc;
+    const int64_t n = pr.n > 0 ? pr.n : 1;
+    uint64_t* key = (uint64_t*)buf(c, "fl_key", 8 * n);
+    uint8_t* att = (uint8_t*)buf(c, "fl_att", 4 * ((n + 3) / 4));
+    uint8_t* adj = (uint8_t*)buf(c, "fl_adj", 4 * ((n + 3) / 4));
+    uint8_t* cls = (uint8_t*)buf(c, "fl_cls", 4 * ((n + 3) / 4));
+    if (!key || !att || !adj || !cls) return TPC_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_grid(*cl, pr, s, st);
+    cluster_flags(pr.g, pr.kp, *cl, s.hits, s.bin_off, *trk, *fp, key, att, adj, cls, flags, st);
+    TPC_HIP(c, hipGetLastError());
+    return TPC_OK;
+}
+
 // ------------------------------------------------------------ time frames
 }  // extern "C"
 

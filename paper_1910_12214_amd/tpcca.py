@@ -50,6 +50,13 @@ class Tracks(ctypes.Structure):
                 ("x_ref", _vp), ("state", _vp), ("cov", _vp), ("chi2", _vp), ("ndf", _vp)]
 
 
+class FlagParams(ctypes.Structure):
+    _fields_ = [("tube_cm", ctypes.c_double), ("pt_min", ctypes.c_double), ("phi_max_deg", ctypes.c_double)]
+
+
+FLAG_ATTACHED, FLAG_ADJACENT, FLAG_PROTECTED, FLAG_REMOVE_A, FLAG_REMOVE_B = 1, 2, 4, 8, 16
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("tracklet_chunk", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("best_ms", ctypes.c_float),
@@ -64,7 +71,7 @@ class TrainCfg(ctypes.Structure):
 EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_default", "tpc_track_sectors",
            "tpc_track_timeframe", "tpc_timeframe_tuning", "tpc_timeframe_set_tuning", "tpc_stage_size",
            "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train",
-           "tpc_profile_enable", "tpc_profile_read")
+           "tpc_profile_enable", "tpc_profile_read", "tpc_cluster_flags", "tpc_flag_params_default")
 N_PROF = 5
 PROF_STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "selection")
 
@@ -99,6 +106,11 @@ def load():
         getattr(lib, f).argtypes = [_vp, P(Clusters), P(Geometry), ctypes.c_double, P(Params), P(Tracks), _vp,
                                     ctypes.c_int]
         getattr(lib, f).restype = ctypes.c_int
+    lib.tpc_cluster_flags.argtypes = [_vp, P(Clusters), P(Geometry), ctypes.c_double, P(Params), P(FlagParams),
+                                      P(Tracks), _vp, _vp]
+    lib.tpc_cluster_flags.restype = ctypes.c_int
+    lib.tpc_flag_params_default.argtypes = [P(FlagParams)]
+    lib.tpc_flag_params_default.restype = None
     lib.tpc_timeframe_tuning.argtypes = [_vp, P(Tuning)]
     lib.tpc_timeframe_tuning.restype = ctypes.c_int
     lib.tpc_timeframe_set_tuning.argtypes = [_vp, P(Tuning)]
@@ -246,6 +258,26 @@ class Context:
                 _stream(stream), 1 if sync_check else 0)
         self._check(rc)
         return out
+
+    def cluster_flags(self, y, z, row, sector, geom: dict, bz: float, tracks: dict, params: dict | None = None,
+                      tube_cm: float = 1.5, pt_min: float = 0.05, phi_max_deg: float = 70.0, flags=None,
+                      stream=None):
+        """Attachment / adjacency / protection / removal flags (uint8 per cluster, CUDA tensor) for a
+        track set in the form ``alloc_tracks`` returns (counts, hit_offset, n_hits, hit_ids, sector,
+        x_ref, state are read)."""
+        import torch
+
+        n = int(y.shape[0])
+        if flags is None:
+            flags = torch.empty(max(1, n), dtype=torch.uint8, device=y.device)
+        cl = self._clusters(y, z, row, sector)
+        g, _keep = make_geometry(geom)
+        p = make_params(params)
+        fp = FlagParams(tube_cm, pt_min, phi_max_deg)
+        t = self._tracks_struct(tracks)
+        self._check(self.lib.tpc_cluster_flags(self.h, ctypes.byref(cl), ctypes.byref(g), float(bz), ctypes.byref(p),
+                                               ctypes.byref(fp), ctypes.byref(t), _ptr(flags), _stream(stream)))
+        return flags[:n]
 
     def stage(self, stage: int, dtype) -> np.ndarray:
         nb = ctypes.c_size_t(0)

@@ -1,0 +1,142 @@
+"""Cluster attachment / adjacency / protection / removal flags (Sec. 4) on the GPU vs the
+oracle, on the oracle's own tracks (needs an MI355X)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1910_12214_amd import tpcca
+
+    c = tpcca.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def tracks_to_device(t: dict) -> dict:
+    """an oracle track set (``oracle.tracks_for_flags``) in the binding's track layout"""
+    import torch
+
+    nt = len(t["off"])
+    ct = max(1, nt)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    counts = torch.zeros(16, **i32)
+    counts[0] = nt
+
+    def pad(a, dt, shape):
+        out = np.zeros(shape, dtype=dt)
+        out[:len(a)] = a
+        return dev(out)
+
+    return dict(counts=counts, hit_offset=pad(t["off"], np.int32, ct), n_hits=pad(t["nh"], np.int32, ct),
+                hit_ids=pad(t["hits"], np.int32, max(1, len(t["hits"]))), sector=pad(t["sector"], np.int32, ct),
+                x_ref=pad(t["x_ref"], np.float32, ct), state=pad(np.asarray(t["state"]).reshape(-1, 5), np.float32,
+                                                                (ct, 5)),
+                start_id=torch.zeros(ct, **i32), row_ref=torch.zeros(ct, **i32),
+                cov=torch.zeros(ct, 15, dtype=torch.float32, device="cuda"),
+                chi2=torch.zeros(ct, dtype=torch.float32, device="cuda"), ndf=torch.zeros(ct, **i32),
+                cap_tracks=nt, cap_hits=max(1, len(t["hits"])))
+
+
+def check_invariants(f: np.ndarray, tr_hits: np.ndarray):
+    A, J, P, RA, RB = 1, 2, 4, 8, 16
+    assert np.array_equal((f & RB) > 0, (f & P) == 0), "strategy B must remove exactly the unprotected"
+    assert np.all((f[(f & P) > 0] & (A | J)) > 0), "protected clusters are attached or adjacent"
+    ra = (f & RA) > 0
+    assert np.array_equal(ra, ((f & (A | J)) > 0) & ((f & P) == 0)), "strategy A: attached/adjacent, unprotected"
+    assert np.all((f[tr_hits] & A) > 0), "every track hit is attached"
+
+
+@pytest.mark.parametrize("wl, frac", [("sector_event_200", 1.0), ("pbpb_event_5000", 0.1)])
+def test_flags_match_oracle(ctx, wl, frac):
+    w = synth.WORKLOADS[wl]
+    if frac < 1.0:
+        w = synth.scaled(w, frac)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, synth.TRACKER_PARAMS, synth.BZ, n_threads=THREADS)
+    t = oracle.tracks_for_flags(o, geom, ev.sector)
+    fo, tie = oracle.cluster_flags(ev.y, ev.z, ev.row, ev.sector, geom, synth.BZ, t)
+    fo_fma, _ = oracle.cluster_flags(ev.y, ev.z, ev.row, ev.sector, geom, synth.BZ, t, fma=True)
+    fg = ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ,
+                           tracks_to_device(t), synth.TRACKER_PARAMS).cpu().numpy()
+    near = (tie > 0) | (fo != fo_fma)
+    bad = np.nonzero((fg != fo) & ~near)[0]
+    say(f"[flags] {wl}x{frac}: {ev.n} clusters, {len(t['off'])} tracks; attached {np.mean(fo & 1 > 0):.3f} "
+        f"adjacent {np.mean(fo & 2 > 0):.3f} protected {np.mean(fo & 4 > 0):.3f} remove A {np.mean(fo & 8 > 0):.4f} "
+        f"B {np.mean(fo & 16 > 0):.3f}; near ties {int(near.sum())}, mismatches {bad.size}")
+    assert bad.size == 0, f"flags differ at {bad[:5]}: gpu {fg[bad[:5]]} oracle {fo[bad[:5]]}"
+    check_invariants(fg, t["hits"])
+
+
+def test_flags_on_gpu_tracks_full_event(ctx):
+    """The full Pb-Pb event tracked on the GPU, flagged on the GPU: the invariants of the strategies
+    hold for every cluster."""
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.PBPB_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    y, z, r, s = dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector)
+    out = ctx.track(y, z, r, s, geom, synth.BZ, synth.TRACKER_PARAMS)
+    f = ctx.cluster_flags(y, z, r, s, geom, synth.BZ, out, synth.TRACKER_PARAMS).cpu().numpy()
+    h = tpcca.tracks_to_host(out)
+    check_invariants(f, h["hit_ids"])
+    say(f"[flags] full event: attached {np.mean(f & 1 > 0):.3f} adjacent {np.mean(f & 2 > 0):.3f} "
+        f"protected {np.mean(f & 4 > 0):.3f} remove A {np.mean(f & 8 > 0):.4f} B {np.mean(f & 16 > 0):.3f}")
+    assert 0.5 < np.mean(f & 4 > 0) < 1.0
+
+
+def test_flags_without_tracks(ctx):
+    import torch
+
+    w = synth.scaled(synth.PBPB_EVENT, 0.01)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    t = {"off": np.zeros(0, np.int32), "nh": np.zeros(0, np.int32), "hits": np.zeros(0, np.int32),
+         "sector": np.zeros(0, np.int32), "x_ref": np.zeros(0, np.float32), "state": np.zeros((0, 5), np.float32)}
+    f = ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ, tracks_to_device(t),
+                          synth.TRACKER_PARAMS).cpu().numpy()
+    assert np.all(f == 16)
+    empty = torch.zeros(0, dtype=torch.float32, device="cuda")
+    e8 = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    assert ctx.cluster_flags(empty, empty, e8, e8, geom, synth.BZ, tracks_to_device(t),
+                             synth.TRACKER_PARAMS).numel() == 0
+
+
+def test_flag_argument_errors(ctx):
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.scaled(synth.PBPB_EVENT, 0.01)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    t = {"off": np.zeros(0, np.int32), "nh": np.zeros(0, np.int32), "hits": np.zeros(0, np.int32),
+         "sector": np.zeros(0, np.int32), "x_ref": np.zeros(0, np.float32), "state": np.zeros((0, 5), np.float32)}
+    for kw in (dict(tube_cm=0.0), dict(pt_min=-1.0), dict(phi_max_deg=90.0)):
+        with pytest.raises(tpcca.TpcError):
+            ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ, tracks_to_device(t),
+                              synth.TRACKER_PARAMS, **kw)
