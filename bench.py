@@ -23,6 +23,37 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # 16-byte hit records, each stage reading its inputs and writing its outputs once).
 ALG_BYTES_PER_CLUSTER = {"grid": 32.0, "neighbours": 32.0, "clean_starts": 24.0, "tracklets": 31.0,
                          "selection": 34.0}
+# Cluster flags (Sec. 4): the grid build (32 B per cluster) plus, per cluster, its record read by
+# both tube passes (2 x 16 B), its key written and read (16 B), three byte arrays written and read
+# (6 B) and the flag byte written: 87 B per cluster at minimum.
+FLAG_BYTES_PER_CLUSTER = 87.0
+
+
+def flag_curve(ev, flags, trk):
+    """Cumulative cluster fractions below a true-pT threshold (noise counts as pT 0), as in the
+    paper's cluster attachment figure: all clusters, attached (and attached to a track whose
+    majority particle is another one: fake), attached or adjacent, protected."""
+    import numpy as np
+
+    qpt = ev.exact["qpt"]
+    pt = np.where((ev.particle >= 0) & (qpt != 0), 1.0 / np.maximum(np.abs(qpt), 1e-12), 0.0)
+    fake = np.zeros(ev.n, dtype=bool)
+    off = np.concatenate([[0], np.cumsum(trk["n_hits"])])
+    for k in range(len(trk["n_hits"])):
+        ids = trk["hit_ids"][off[k]:off[k + 1]]
+        part = ev.particle[ids]
+        vals, cnt = np.unique(part[part >= 0], return_counts=True)
+        major = vals[np.argmax(cnt)] if len(vals) else -2
+        fake[ids[part != major]] = True
+    att, adj, prot = (flags & 1) > 0, (flags & 3) > 0, (flags & 4) > 0
+    rows = []
+    for t in (0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 10.0):
+        b = pt < t
+        rows.append({"pt_below": t, "all": round(float(b.mean()), 4), "attached": round(float((b & att).mean()), 4),
+                     "fake_attached": round(float((b & att & fake).mean()), 5),
+                     "attached_or_adjacent": round(float((b & adj).mean()), 4),
+                     "protected": round(float((b & prot).mean()), 4)})
+    return rows
 
 
 def log(*a):
@@ -37,6 +68,7 @@ def parse():
     ap.add_argument("--workload", default="pbpb_event_5000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
+    ap.add_argument("--no-flags", action="store_true", help="skip the cluster-flag measurement")
     ap.add_argument("--sector-path", action="store_true", help="time frames through tpc_track_sectors")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     return ap.parse_args()
@@ -100,7 +132,7 @@ def main():
 
     w = synth.WORKLOADS[args.workload]
     log("generating", w.name)
-    ev = synth.generate(w)
+    ev = synth.generate(w, want_exact=w.t_frame_us == 0)  # events keep the true momenta (flag curve)
     log("generated", ev.n, "clusters")
     geom = synth.geometry(w)
     params = dict(synth.TRACKER_PARAMS)
@@ -195,6 +227,29 @@ def main():
                                  "outputs_equal": same}
         ctx2.close()
         log("timed two in flight")
+    # Cluster attachment / adjacency / protection / removal flags (Sec. 4) for the tracks just
+    # found: not part of the step, timed on its own (the call builds its own grid).
+    if not args.no_flags:
+        fl = ctx.cluster_flags(y, z, r, s, geom, synth.BZ, out, params, stream=stream)  # sizes scratch
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.cluster_flags(y, z, r, s, geom, synth.BZ, out, params, flags=fl, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_f = e0.elapsed_time(e1) / args.steps
+        fh = fl.cpu().numpy()
+        bits = (("attached", 1), ("adjacent", 2), ("protected", 4), ("remove_a", 8), ("remove_b", 16))
+        ach = FLAG_BYTES_PER_CLUSTER * ev.n / (ms_f * 1e-3) / 1e9
+        line["cluster_flags"] = {
+            "value": ev.n / (ms_f * 1e-3), "unit": "clusters/s", "ms": ms_f,
+            "fractions": {k: round(float(np.mean((fh & b) > 0)), 4) for k, b in bits},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_cluster": FLAG_BYTES_PER_CLUSTER}}
+        if getattr(ev, "exact", None) is not None:
+            line["cluster_flags"]["curve"] = flag_curve(ev, fh, tpcca.tracks_to_host(out))
+        log("timed cluster flags")
     # learned pruning (scorer trained on one-sector events; tau from its validation seeds)
     if not args.no_mlp:
         from paper_1910_12214_amd import scorer as sc
