@@ -71,7 +71,8 @@ def check_invariants(f: np.ndarray, tr_hits: np.ndarray):
     assert np.all((f[tr_hits] & A) > 0), "every track hit is attached"
 
 
-@pytest.mark.parametrize("wl, frac", [("sector_event_200", 1.0), ("pbpb_event_5000", 0.1)])
+@pytest.mark.parametrize("wl, frac", [("sector_event_200", 1.0), ("pbpb_event_5000", 0.1),
+                                     ("pbpb_timeframe_570", 0.004)])
 def test_flags_match_oracle(ctx, wl, frac):
     w = synth.WORKLOADS[wl]
     if frac < 1.0:
