@@ -157,8 +157,9 @@ int tpc_track_sectors(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_
  * higher-momentum track, protection of tracks above 50 MeV/c with local
  * |phi| < 70 deg, strategies A and B).  `tracks` is read only: its counts
  * (TPC_CNT_TRACKS, device), hit_offset, n_hits, hit_ids (ascending row),
- * sector, x_ref and state; a track's tube covers the rows from its first to
- * its last hit, on its own sector.  Legs of looping tracks are not merged, so
+ * sector, x_ref and state (entries with offsets beyond cap_hits, or cluster
+ * ids outside [0, n), are skipped); a track's tube covers the rows from its
+ * first to its last hit, on its own sector.  Legs of looping tracks are not merged, so
  * every track counts as a primary leg.  `flags` (device, caller-owned) gets one
  * byte per cluster; `params` supplies the grid bin size and s_max (the other
  * fields are unused).  Enqueued on `stream`, no host synchronisation; returns

@@ -460,7 +460,7 @@ int tpc_cluster_flags(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     if (!fp || !(fp->tube_cm > 0.0) || !std::isfinite(fp->tube_cm) || !(fp->pt_min > 0.0) ||
         !std::isfinite(fp->pt_min) || !(fp->phi_max_deg > 0.0) || !(fp->phi_max_deg < 90.0))
         return fail(c, TPC_ERR_ARG, "flag parameters: need tube_cm > 0, pt_min > 0, 0 < phi_max_deg < 90");
-    if (!trk || trk->cap_tracks < 0 || !trk->counts ||
+    if (!trk || trk->cap_tracks < 0 || trk->cap_hits < 0 || !trk->counts ||
         (trk->cap_tracks > 0 && (!trk->hit_offset || !trk->n_hits || !trk->hit_ids || !trk->sector ||
                                  !trk->x_ref || !trk->state)))
         return fail(c, TPC_ERR_ARG, "tracks: counts and, for cap_tracks > 0, hit_offset, n_hits, hit_ids, "

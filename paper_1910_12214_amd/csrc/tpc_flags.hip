@@ -26,8 +26,9 @@ namespace {
 
 struct FlagArgs {
     const uint8_t* row;  // cluster rows (the grid's hit records give y, z, id)
+    int64_t n;              // clusters
     const int32_t* counts;  // tracks: counts[TPC_CNT_TRACKS] (device)
-    int32_t cap_tracks;
+    int32_t cap_tracks, cap_hits;
     const int32_t *off, *nh, *ids, *sector;
     const float *x_ref, *state;
     double kq, s_max, t2;
@@ -75,10 +76,14 @@ __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, cons
     const int32_t wpb = (int32_t)(blockDim.x >> 6);
     for (int32_t k = (int32_t)blockIdx.x * wpb + (int32_t)(threadIdx.x >> 6); k < n_trk;
          k += (int32_t)gridDim.x * wpb) {  // wave-uniform
-        const int32_t nh = a.nh[k], s = a.sector[k];
-        if (nh <= 0 || s < 0 || s >= g.S) continue;
-        const int32_t* ids = a.ids + a.off[k];
-        const int r0 = a.row[ids[0]], r1 = a.row[ids[nh - 1]];
+        // entries a tracking call could not write (hits beyond cap_hits) may hold anything:
+        // every index is checked before it is used
+        const int32_t nh = a.nh[k], s = a.sector[k], off = a.off[k];
+        if (nh <= 0 || off < 0 || (int64_t)off + nh > (int64_t)a.cap_hits || s < 0 || s >= g.S) continue;
+        const int32_t* ids = a.ids + off;
+        const int32_t c0 = ids[0], c1 = ids[nh - 1];
+        if ((uint64_t)(uint32_t)c0 >= (uint64_t)a.n || (uint64_t)(uint32_t)c1 >= (uint64_t)a.n) continue;
+        const int r0 = a.row[c0], r1 = a.row[c1];
         if (r1 >= g.R || r0 > r1) continue;
         const uint64_t tk = track_key(a, k);
         const bool slow = fabsf(a.state[5 * k + 4]) < a.qpt_max;  // pT > pt_min
@@ -108,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, cons
         // the track's own clusters, inside the tube or not
         for (int i = lane; i < nh; i += 64) {
             const int32_t c = ids[i];
+            if ((uint64_t)(uint32_t)c >= (uint64_t)a.n) continue;
             if (PASS == 0) {
                 att[c] = 1;
                 atomicMax((unsigned long long*)&key[c], (unsigned long long)tk);
@@ -145,8 +151,10 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
     fill_u32((uint32_t*)cls, 0u, (n + 3) / 4, s);
     FlagArgs a;
     a.row = cl.row;
+    a.n = n;
     a.counts = trk.counts;
     a.cap_tracks = trk.cap_tracks;
+    a.cap_hits = trk.cap_hits;
     a.off = trk.hit_offset;
     a.nh = trk.n_hits;
     a.ids = trk.hit_ids;

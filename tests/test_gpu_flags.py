@@ -141,3 +141,33 @@ def test_flag_argument_errors(ctx):
         with pytest.raises(tpcca.TpcError):
             ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ, tracks_to_device(t),
                               synth.TRACKER_PARAMS, **kw)
+
+
+def test_malformed_track_entries_are_skipped(ctx):
+    """Entries a tracking call could not write may hold anything: offsets past cap_hits, cluster ids
+    out of range, a sector past the last one, NaN states.  They are skipped; the valid tracks give
+    the oracle's flags."""
+    w = synth.scaled(synth.PBPB_EVENT, 0.05)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, synth.TRACKER_PARAMS, synth.BZ, n_threads=THREADS)
+    t = oracle.tracks_for_flags(o, geom, ev.sector)
+    fo, tie = oracle.cluster_flags(ev.y, ev.z, ev.row, ev.sector, geom, synth.BZ, t)
+    nh_all = len(t["hits"])
+    bad = {  # appended after the valid tracks, so the valid ones keep their indices
+        "off": [nh_all + 10, -3, 0, 0, 0],
+        "nh": [4, 4, 3, 2, 2],
+        "sector": [0, 0, 0, 99, 0],
+    }
+    hits = np.concatenate([t["hits"], [ev.n + 5, 2 ** 30, -7]]).astype(np.int32)  # out-of-range ids
+    t2 = {"off": np.concatenate([t["off"], bad["off"][:2], [nh_all, 0, 0]]).astype(np.int32),
+          "nh": np.concatenate([t["nh"], bad["nh"]]).astype(np.int32),
+          "hits": hits,
+          "sector": np.concatenate([t["sector"], bad["sector"]]).astype(np.int32),
+          "x_ref": np.concatenate([t["x_ref"], np.full(5, 100.0)]).astype(np.float32),
+          "state": np.concatenate([t["state"], np.full((5, 5), np.nan)]).astype(np.float32)}
+    fg = ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ,
+                           tracks_to_device(t2), synth.TRACKER_PARAMS).cpu().numpy()
+    bad_idx = np.nonzero((fg != fo) & (tie == 0))[0]
+    say(f"[flags] malformed entries: {bad_idx.size} mismatches on {ev.n} clusters")
+    assert bad_idx.size == 0
