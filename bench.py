@@ -247,7 +247,7 @@ def main():
             "fractions": {k: round(float(np.mean((fh & b) > 0)), 4) for k, b in bits},
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_cluster": FLAG_BYTES_PER_CLUSTER}}
-        if getattr(ev, "exact", None) is not None:
+        if "qpt" in (getattr(ev, "exact", None) or {}):  # events only (true momenta kept)
             line["cluster_flags"]["curve"] = flag_curve(ev, fh, tpcca.tracks_to_host(out))
         log("timed cluster flags")
     # learned pruning (scorer trained on one-sector events; tau from its validation seeds)
