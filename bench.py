@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 ALG_BYTES_PER_CLUSTER = {"grid": 32.0, "neighbours": 32.0, "clean_starts": 24.0, "tracklets": 31.0,
                          "selection": 34.0}
 # Cluster flags (Sec. 4): the grid build (32 B per cluster) plus, per cluster, its record read by
-# both tube passes (2 x 16 B), its key written and read (16 B), three byte arrays written and read
-# (6 B) and the flag byte written: 87 B per cluster at minimum.
-FLAG_BYTES_PER_CLUSTER = 87.0
+# the tube walk (16 B), its key written and read (16 B), two byte arrays written and read (4 B)
+# and the flag byte written: 69 B per cluster at minimum.
+FLAG_BYTES_PER_CLUSTER = 69.0
 
 
 def flag_curve(ev, flags, trk):

@@ -475,11 +475,10 @@ int tpc_cluster_flags(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     uint64_t* key = (uint64_t*)buf(c, "fl_key", 8 * n);
     uint8_t* att = (uint8_t*)buf(c, "fl_att", 4 * ((n + 3) / 4));
     uint8_t* adj = (uint8_t*)buf(c, "fl_adj", 4 * ((n + 3) / 4));
-    uint8_t* cls = (uint8_t*)buf(c, "fl_cls", 4 * ((n + 3) / 4));
-    if (!key || !att || !adj || !cls) return TPC_ERR_HIP;
+    if (!key || !att || !adj) return TPC_ERR_HIP;
     hipStream_t st = (hipStream_t)stream;
     enqueue_grid(*cl, pr, s, st);
-    cluster_flags(pr.g, pr.kp, *cl, s.hits, s.bin_off, *trk, *fp, key, att, adj, cls, flags, st);
+    cluster_flags(pr.g, pr.kp, *cl, s.hits, s.bin_off, *trk, *fp, key, att, adj, flags, st);
     TPC_HIP(c, hipGetLastError());
     return TPC_OK;
 }

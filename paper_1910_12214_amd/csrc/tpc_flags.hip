@@ -14,9 +14,9 @@
 //
 // One wave per track, one lane per spanned row (rows of a track are
 // independent: each lane propagates the track's reference state to its row in
-// closed form).  Pass 1 marks adjacency and attachment and raises the cluster
-// keys; pass 2 repeats the walk and lets the one track whose key a cluster holds
-// write its decision; a per-cluster pass assembles the flags.
+// closed form).  One walk marks adjacency and attachment and raises the cluster
+// keys, which carry the candidate track's protection decision in their lowest
+// bit; a per-cluster pass assembles the flags.
 #include "tpc_device.h"
 #include "tpc_internal.h"
 
@@ -60,16 +60,20 @@ __device__ inline bool helix_at(const FlagArgs& a, int32_t k, double x, double& 
     return true;
 }
 
-__device__ inline uint64_t track_key(const FlagArgs& a, int32_t k) {
+// Key of track k for a cluster on a row where the track's protection decision is
+// `prot`: (~bits(|q/pT|), ~k) orders the tracks (higher momentum, then smaller
+// index); the decision rides in the lowest bit, which never decides between two
+// tracks (their upper 63 bits differ), so the maximum over a cluster's
+// candidates carries its assigned track's decision with it.
+__device__ inline uint64_t track_key(const FlagArgs& a, int32_t k, bool prot) {
     const float q = fabsf(a.state[5 * k + 4]);
-    return ((uint64_t)(0xFFFFFFFFu - __float_as_uint(q)) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+    return ((uint64_t)(0xFFFFFFFFu - __float_as_uint(q)) << 32) |
+           ((uint64_t)(0x7FFFFFFFu - (uint32_t)k) << 1) | (prot ? 1ull : 0ull);
 }
 
-template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, const Hit* __restrict__ hits,
-                                                    const uint32_t* __restrict__ bin_off,
-                                                    uint64_t* __restrict__ key, uint8_t* __restrict__ att,
-                                                    uint8_t* __restrict__ adj, uint8_t* __restrict__ cls) {
+                                                    const uint32_t* __restrict__ bin_off, uint64_t* __restrict__ key,
+                                                    uint8_t* __restrict__ att, uint8_t* __restrict__ adj) {
     const int lane = threadIdx.x & 63;
     const int32_t cnt = a.counts[TPC_CNT_TRACKS];
     const int32_t n_trk = cnt < a.cap_tracks ? cnt : a.cap_tracks;
@@ -85,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, cons
         if ((uint64_t)(uint32_t)c0 >= (uint64_t)a.n || (uint64_t)(uint32_t)c1 >= (uint64_t)a.n) continue;
         const int r0 = a.row[c0], r1 = a.row[c1];
         if (r1 >= g.R || r0 > r1) continue;
-        const uint64_t tk = track_key(a, k);
-        const bool slow = fabsf(a.state[5 * k + 4]) < a.qpt_max;  // pT > pt_min
+        const bool fast = fabsf(a.state[5 * k + 4]) < a.qpt_max;  // pT > pt_min
+        const uint64_t k_no = track_key(a, k, false), k_yes = track_key(a, k, true);
         // the rows the track spans
         for (int r = r0 + lane; r <= r1; r += 64) {
             double yt, zt, st;
@@ -94,47 +98,40 @@ __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, cons
             const double rad = sqrt(a.t2);
             const BinRange br = bin_range(g, s, r, yt - rad, yt + rad, zt - rad, zt + rad);
             if (br.empty) continue;
-            const bool prot = slow && fabs(st) < a.sin_phi_max;
+            const uint64_t tk = (fast && fabs(st) < a.sin_phi_max) ? k_yes : k_no;
             for (int iz = br.iz0; iz <= br.iz1; ++iz) {
                 const uint32_t e = bin_off[br.base + iz * br.ny + br.iy1 + 1];
                 for (uint32_t j = bin_off[br.base + iz * br.ny + br.iy0]; j < e; ++j) {
                     const Hit h = hits[j];
                     const double dy = (double)h.y - yt, dz = (double)h.z - zt;
                     if (!(dy * dy + dz * dz <= a.t2)) continue;
-                    if (PASS == 0) {
-                        adj[h.id] = 1;
-                        atomicMax((unsigned long long*)&key[h.id], (unsigned long long)tk);
-                    } else if (key[h.id] == tk) {
-                        cls[h.id] = prot ? 1 : 2;
-                    }
+                    adj[h.id] = 1;
+                    atomicMax((unsigned long long*)&key[h.id], (unsigned long long)tk);
                 }
             }
         }
-        // the track's own clusters, inside the tube or not
+        // the track's own clusters, inside the tube or not (decision on the cluster's row)
         for (int i = lane; i < nh; i += 64) {
             const int32_t c = ids[i];
             if ((uint64_t)(uint32_t)c >= (uint64_t)a.n) continue;
-            if (PASS == 0) {
-                att[c] = 1;
-                atomicMax((unsigned long long*)&key[c], (unsigned long long)tk);
-            } else if (key[c] == tk) {
-                double yt, zt, st;
-                const bool ok = a.row[c] < g.R && helix_at(a, k, (double)g.row_x[a.row[c]], yt, zt, st);
-                cls[c] = (ok && slow && fabs(st) < a.sin_phi_max) ? 1 : 2;
-            }
+            double yt, zt, st;
+            const bool ok = a.row[c] < g.R && helix_at(a, k, (double)g.row_x[a.row[c]], yt, zt, st);
+            att[c] = 1;
+            atomicMax((unsigned long long*)&key[c],
+                      (unsigned long long)((ok && fast && fabs(st) < a.sin_phi_max) ? k_yes : k_no));
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_fl_final(int64_t n, const uint8_t* __restrict__ att,
-                                                     const uint8_t* __restrict__ adj, const uint8_t* __restrict__ cls,
+__global__ __launch_bounds__(kBlock) void k_fl_final(int64_t n, const uint64_t* __restrict__ key,
+                                                     const uint8_t* __restrict__ att, const uint8_t* __restrict__ adj,
                                                      uint8_t* __restrict__ flags) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= n) return;
-    const uint8_t d = cls[c];
+    const uint64_t kk = key[c];
     uint8_t f = (att[c] ? TPC_FLAG_ATTACHED : 0) | (adj[c] ? TPC_FLAG_ADJACENT : 0);
-    f |= d == 1 ? TPC_FLAG_PROTECTED : (d == 2 ? TPC_FLAG_REMOVE_A : 0);
-    f |= d == 1 ? 0 : TPC_FLAG_REMOVE_B;
+    if (kk & 1ull) f |= TPC_FLAG_PROTECTED;
+    else f |= TPC_FLAG_REMOVE_B | (kk ? TPC_FLAG_REMOVE_A : 0);
     flags[c] = f;
 }
 
@@ -142,13 +139,12 @@ __global__ __launch_bounds__(kBlock) void k_fl_final(int64_t n, const uint8_t* _
 
 void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& cl, const Hit* hits,
                    const uint32_t* bin_off, const tpc_tracks_t& trk, const tpc_flag_params_t& fp, uint64_t* key,
-                   uint8_t* att, uint8_t* adj, uint8_t* cls, uint8_t* flags, hipStream_t s) {
+                   uint8_t* att, uint8_t* adj, uint8_t* flags, hipStream_t s) {
     const int64_t n = cl.n;
     if (n <= 0) return;
     fill_u64(key, 0ull, n, s);
     fill_u32((uint32_t*)att, 0u, (n + 3) / 4, s);
     fill_u32((uint32_t*)adj, 0u, (n + 3) / 4, s);
-    fill_u32((uint32_t*)cls, 0u, (n + 3) / 4, s);
     FlagArgs a;
     a.row = cl.row;
     a.n = n;
@@ -169,10 +165,9 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
     if (trk.cap_tracks > 0) {
         int64_t nb = ((int64_t)trk.cap_tracks + kBlock / 64 - 1) / (kBlock / 64);
         if (nb > 65536) nb = 65536;
-        k_fl_tube<0><<<(unsigned)nb, kBlock, 0, s>>>(g, a, hits, bin_off, key, att, adj, cls);
-        k_fl_tube<1><<<(unsigned)nb, kBlock, 0, s>>>(g, a, hits, bin_off, key, att, adj, cls);
+        k_fl_tube<<<(unsigned)nb, kBlock, 0, s>>>(g, a, hits, bin_off, key, att, adj);
     }
-    k_fl_final<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, att, adj, cls, flags);
+    k_fl_final<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, key, att, adj, flags);
 }
 
 }  // namespace tpc

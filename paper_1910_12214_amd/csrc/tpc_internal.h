@@ -207,10 +207,10 @@ void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc,
                   const tpc_tracks_t& out, int64_t t_max, hipStream_t s);
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s);
 
-// flags.hip: key [n] u64, att/adj/cls [n] u8 scratch (cleared here); flags [n] u8 output
+// flags.hip: key [n] u64, att/adj [n] u8 scratch (cleared here); flags [n] u8 output
 void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& cl, const Hit* hits,
                    const uint32_t* bin_off, const tpc_tracks_t& trk, const tpc_flag_params_t& fp, uint64_t* key,
-                   uint8_t* att, uint8_t* adj, uint8_t* cls, uint8_t* flags, hipStream_t s);
+                   uint8_t* att, uint8_t* adj, uint8_t* flags, hipStream_t s);
 
 // mlp.hip
 size_t mlp_q_floats();
