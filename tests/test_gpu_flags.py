@@ -171,3 +171,30 @@ def test_malformed_track_entries_are_skipped(ctx):
     bad_idx = np.nonzero((fg != fo) & (tie == 0))[0]
     say(f"[flags] malformed entries: {bad_idx.size} mismatches on {ev.n} clusters")
     assert bad_idx.size == 0
+
+
+def test_full_pbpb_timeframe_sampled_sectors(ctx):
+    """The full 570-collision frame (72.8M clusters) flagged in one call; the oracle tracks and
+    flags two whole sectors (every step is per sector), and the GPU flags every cluster of the
+    frame with those tracks: equal on the two sectors, removable-by-B only everywhere else."""
+    w = synth.PBPB_TIMEFRAME
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    prm = dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0)
+    sectors = [5, 30]
+    sel = np.isin(ev.sector, sectors)
+    ids = np.nonzero(sel)[0].astype(np.int64)
+    say(f"[flags] full frame: {ev.n} clusters, oracle on sectors {sectors} ({ids.size} clusters)")
+    o = oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, prm, synth.BZ, n_threads=THREADS)
+    t = oracle.tracks_for_flags(o, geom, ev.sector[sel])
+    fo, tie = oracle.cluster_flags(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, synth.BZ, t)
+    fo_fma, _ = oracle.cluster_flags(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, synth.BZ, t, fma=True)
+    tg = dict(t, hits=ids[t["hits"]].astype(np.int32))  # the same tracks on the frame's cluster ids
+    fg = ctx.cluster_flags(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ,
+                           tracks_to_device(tg), prm).cpu().numpy()
+    near = (tie > 0) | (fo != fo_fma)
+    bad = np.nonzero((fg[ids] != fo) & ~near)[0]
+    say(f"[flags] full frame: {len(t['off'])} tracks; near ties {int(near.sum())}, mismatches {bad.size}")
+    assert bad.size == 0, f"flags differ at {ids[bad[:5]]}"
+    assert np.all(fg[~sel] == 16)
+    assert len(t["off"]) > 20000
