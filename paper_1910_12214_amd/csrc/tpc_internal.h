@@ -64,7 +64,7 @@ enum Counter {  // device scratch counters (uint32)
     C_N_PAIRS_KEPT,
     C_N_VALID_CLU,
     C_QUEUE_XCD0,  // 8 per-XCD tracklet queues follow
-    C_NB_OVF = C_QUEUE_XCD0 + 8,  // waves on the fused neighbour kernel's overflow list
+    C_NB_OVF = C_QUEUE_XCD0 + 8,  // 64-hit groups on the scorer's overflow list (per-lane kernel)
     C_N_COUNTERS = 32
 };
 
@@ -72,7 +72,7 @@ enum Counter {  // device scratch counters (uint32)
 // kTallyLines 64-byte lines (slot = counter index) rather than to one address: a
 // device-scope atomic on a single shared address is serialised chip-wide.  The
 // final count kernel adds the lines to the counters.  Slot kSlotCandSeg of line
-// l is the fill level of segment l of the fused neighbour kernel's candidate list.
+// l is the fill level of segment l of the scorer's candidate list.
 constexpr int kTallyLines = 256, kTallyStride = 16, kSlotCandSeg = 15;
 constexpr int kCounterWords = C_N_COUNTERS + kTallyLines * kTallyStride;
 static_assert(C_N_PAIRS < kSlotCandSeg && C_N_LINKS_RAW < kSlotCandSeg && C_N_LINKS_CLEAN < kSlotCandSeg &&
