@@ -107,8 +107,13 @@ def cpu_baseline(ev, geom, params, budget_s: float):
     sel = ev.sector < n_sec
     n_sample = int(sel.sum())
     t0 = time.perf_counter()
-    oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=1)
+    o = oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=1)
     t1 = time.perf_counter() - t0
+    # the cluster flags of the same sample on the oracle's tracks (brute force, one thread)
+    trk = oracle.tracks_for_flags(o, geom, ev.sector[sel])
+    t0 = time.perf_counter()
+    oracle.cluster_flags(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, synth.BZ, trk)
+    tf = time.perf_counter() - t0
     cores = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=cores)
@@ -116,7 +121,8 @@ def cpu_baseline(ev, geom, params, budget_s: float):
     del order
     return {"value": n_sample / t1, "unit": "clusters/s", "cores": 1, "kind": "oracle",
             "sample": f"sectors 0..{n_sec - 1} of {ev.workload.name} ({n_sample} clusters), FP64 C oracle, 1 thread",
-            "value_all_cores": n_sample / tn, "cores_all": cores}
+            "value_all_cores": n_sample / tn, "cores_all": cores,
+            "cluster_flags": {"value": n_sample / tf, "unit": "clusters/s", "cores": 1, "kind": "oracle"}}
 
 
 def main():
