@@ -246,3 +246,34 @@ def test_trained_scorer_gain_over_untrained(ctx):
     assert true_t > 0.95 and true_r < 0.6
     assert plain["efficiency"] - pruned["efficiency"] <= 0.005
     assert pruned["efficiency"] > untrained["efficiency"]
+
+
+def test_full_event_pruned_sampled_sectors(ctx):
+    """The full Pb-Pb event with the Pb-Pb scorer at its validated threshold, in the launch the
+    benchmark times (candidate + scoring kernels, all 36 sectors); the oracle, with the same
+    BF16 scorer in FP64, checks two whole sectors stage by stage."""
+    from paper_1910_12214_amd import scorer as sc
+    from paper_1910_12214_amd import tpcca
+    from tests.test_gpu_timeframe import lift
+
+    w = synth.PBPB_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    theta, tau = sc.load(sc.PBPB_CKPT)
+    out = ctx.track(dev(ev.y), dev(ev.z), dev(ev.row), dev(ev.sector), geom, synth.BZ, synth.TRACKER_PARAMS,
+                    mlp=dev(theta), tau_logit=tau)
+    trk = tpcca.tracks_to_host(out)
+    st = parity.gpu_stages(ctx, synth.N_ROWS)
+    sectors = [7, 25]
+    sel = np.isin(ev.sector, sectors)
+    ids = np.nonzero(sel)[0]
+    prm = dict(synth.TRACKER_PARAMS, mlp_tau_logit=tau, mlp_flag_abs=1e-4)
+    q = omlp.quantize(theta.astype(np.float64))
+    args = (ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, prm, synth.BZ)
+    o = lift(oracle.track(*args, mlp=q, n_threads=THREADS), ids, ev.n)
+    o_fma = lift(oracle.track(*args, mlp=q, n_threads=THREADS, fma=True), ids, ev.n)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma)
+    c = trk["counts"]
+    say(f"[mlp] full event, tau {tau}, sectors {sectors}: {rep.line()} pairs={c[tpcca.CNT_PAIRS]} "
+        f"kept={c[tpcca.CNT_PAIRS_KEPT]} overflow groups={c[tpcca.CNT_NB_OVERFLOW]}")
+    assert rep["tracks_compared"] > 500
