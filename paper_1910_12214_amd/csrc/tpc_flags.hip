@@ -25,8 +25,7 @@ namespace tpc {
 namespace {
 
 struct FlagArgs {
-    const float *y, *z;  // clusters
-    const uint8_t *row, *sec;
+    const uint8_t* row;  // cluster rows (the grid's hit records give y, z, id)
     int64_t n;              // clusters
     const int32_t* counts;  // tracks: counts[TPC_CNT_TRACKS] (device)
     int32_t cap_tracks, cap_hits;
@@ -111,19 +110,13 @@ __global__ __launch_bounds__(kBlock) void k_fl_tube(GridDesc g, FlagArgs a, cons
                 }
             }
         }
-        // the track's own clusters (decision on the cluster's row); those the walk above
-        // found inside the tube (same sector, a spanned row, the same test on the same
-        // values) already hold this key
+        // the track's own clusters, inside the tube or not (decision on the cluster's row)
         for (int i = lane; i < nh; i += 64) {
             const int32_t c = ids[i];
             if ((uint64_t)(uint32_t)c >= (uint64_t)a.n) continue;
-            att[c] = 1;
             double yt, zt, st;
             const bool ok = a.row[c] < g.R && helix_at(a, k, (double)g.row_x[a.row[c]], yt, zt, st);
-            if (ok && a.sec[c] == s && a.row[c] >= r0 && a.row[c] <= r1) {
-                const double dy = (double)a.y[c] - yt, dz = (double)a.z[c] - zt;
-                if (dy * dy + dz * dz <= a.t2) continue;
-            }
+            att[c] = 1;
             atomicMax((unsigned long long*)&key[c],
                       (unsigned long long)((ok && fast && fabs(st) < a.sin_phi_max) ? k_yes : k_no));
         }
@@ -155,9 +148,6 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
     FlagArgs a;
     a.row = cl.row;
     a.n = n;
-    a.y = cl.y;
-    a.z = cl.z;
-    a.sec = cl.sector;
     a.counts = trk.counts;
     a.cap_tracks = trk.cap_tracks;
     a.cap_hits = trk.cap_hits;
