@@ -110,6 +110,9 @@ def _load(path: str = _LIB_PATH):
         lib.or_mlp_logit.restype = ctypes.c_double
         lib.or_features.argtypes = [ctypes.c_double] * 11 + [ctypes.c_int, ctypes.c_int, d]
         lib.or_features.restype = None
+        lib.or_follow_search.argtypes = [ctypes.POINTER(_Input), ctypes.POINTER(_Params), ctypes.c_int, ctypes.c_int,
+                                         d, d, ctypes.POINTER(ctypes.c_int)]
+        lib.or_follow_search.restype = ctypes.c_int64
         lib.or_cluster_flags.argtypes = [ctypes.POINTER(_FlagsIn), ctypes.POINTER(ctypes.c_uint8),
                                          ctypes.POINTER(ctypes.c_uint8)]
         lib.or_cluster_flags.restype = ctypes.c_int
@@ -180,6 +183,50 @@ def full_to_sym15(M) -> np.ndarray:
     return np.array([M[i, j] for i in range(5) for j in range(i + 1)])
 
 
+def _make_input(y, z, row, sector, geometry: dict, bz: float, n_threads: int, keep: list) -> "_Input":
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    row = np.ascontiguousarray(row, dtype=np.uint8)
+    sector = np.ascontiguousarray(sector, dtype=np.uint8)
+    rx = np.ascontiguousarray(geometry["row_x"], dtype=np.float32)
+    keep += [y, z, row, sector, rx]
+    inp = _Input()
+    inp.n = y.shape[0]
+    inp.y = y.ctypes.data_as(_P(ctypes.c_float)); inp.z = z.ctypes.data_as(_P(ctypes.c_float))
+    inp.row = row.ctypes.data_as(_P(ctypes.c_uint8)); inp.sector = sector.ctypes.data_as(_P(ctypes.c_uint8))
+    inp.n_rows = int(geometry["n_rows"]); inp.row_x = rx.ctypes.data_as(_P(ctypes.c_float))
+    inp.tan_half = float(geometry["tan_half"]); inp.n_sectors = int(geometry["n_sectors"])
+    inp.z_min = float(geometry["z_min"]); inp.z_max = float(geometry["z_max"])
+    inp.bz = float(bz); inp.n_threads = int(n_threads)
+    return inp
+
+
+def _make_params(params: dict) -> "_Params":
+    prm = _Params()
+    for f, _ in _Params._fields_:
+        if f in params and f != "mlp":
+            setattr(prm, f, params[f])
+    prm.tie_rel = params.get("tie_rel", 1e-5)
+    return prm
+
+
+def follow_search(y, z, row, sector, geometry: dict, params: dict, s: int, r: int, p, c15):
+    """The oracle's following search of row-sector (s, r) on its own: the cluster id of the
+    smallest chi2 inside the cut (ties: smallest id), or -1, and the near-tie flag bits."""
+    lib = _load(_LIB_PATH)
+    keep: list = []
+    inp = _make_input(y, z, row, sector, geometry, 0.0, 1, keep)
+    prm = _make_params(params)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    cc = np.ascontiguousarray(c15, dtype=np.float64)
+    fl = ctypes.c_int(0)
+    rc = lib.or_follow_search(ctypes.byref(inp), ctypes.byref(prm), int(s), int(r), _dptr(pp), _dptr(cc),
+                              ctypes.byref(fl))
+    if rc < -1:
+        raise ValueError("oracle rejected its input")
+    return int(rc), int(fl.value)
+
+
 STAGE_GRID, STAGE_NEIGHBOURS, STAGE_CLEAN, STAGE_TRACKLETS, STAGE_SELECT = 1, 2, 4, 8, 16
 ALL_STAGES = 31
 
@@ -194,24 +241,9 @@ def track(y, z, row, sector, geometry: dict, params: dict, bz: float, mlp: np.nd
     fma: run the FMA-contracted build (same arithmetic, different rounding).
     """
     lib = _load(_LIB_FMA_PATH if fma else _LIB_PATH)
-    y = np.ascontiguousarray(y, dtype=np.float32)
-    z = np.ascontiguousarray(z, dtype=np.float32)
-    row = np.ascontiguousarray(row, dtype=np.uint8)
-    sector = np.ascontiguousarray(sector, dtype=np.uint8)
-    rx = np.ascontiguousarray(geometry["row_x"], dtype=np.float32)
-    inp = _Input()
-    inp.n = y.shape[0]
-    inp.y = y.ctypes.data_as(_P(ctypes.c_float)); inp.z = z.ctypes.data_as(_P(ctypes.c_float))
-    inp.row = row.ctypes.data_as(_P(ctypes.c_uint8)); inp.sector = sector.ctypes.data_as(_P(ctypes.c_uint8))
-    inp.n_rows = int(geometry["n_rows"]); inp.row_x = rx.ctypes.data_as(_P(ctypes.c_float))
-    inp.tan_half = float(geometry["tan_half"]); inp.n_sectors = int(geometry["n_sectors"])
-    inp.z_min = float(geometry["z_min"]); inp.z_max = float(geometry["z_max"])
-    inp.bz = float(bz); inp.n_threads = int(n_threads)
-    prm = _Params()
-    for f, _ in _Params._fields_:
-        if f in params and f != "mlp":
-            setattr(prm, f, params[f])
-    prm.tie_rel = params.get("tie_rel", 1e-5)
+    keep: list = []
+    inp = _make_input(y, z, row, sector, geometry, bz, n_threads, keep)
+    prm = _make_params(params)
     mlp_arr = None
     if mlp is not None:
         mlp_arr = np.ascontiguousarray(mlp, dtype=np.float64)

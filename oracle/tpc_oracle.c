@@ -311,7 +311,10 @@ static void build_grid(ctx_t* g) {
 }
 
 /* Calls fn(id) for every hit of row-sector (s,r) in the bins overlapping
- * [y0,y1] x [z0,z1] (one extra bin on every side: the window tests are exact). */
+ * [y0,y1] x [z0,z1] (one extra bin on every side: the window tests are exact).
+ * Hits beyond the grid's range sit in its edge bins, so the bin range is clamped
+ * to the grid: a box beyond the grid visits the edge bins (bins only enumerate
+ * candidates, whatever the coordinates).  NaN bounds visit nothing. */
 typedef void (*visit_fn)(void* st, uint32_t id);
 static void visit_box(const ctx_t* g, int s, int r, double y0, double y1, double z0, double z1, visit_fn fn, void* st) {
     const or_output_t* o = g->out;
@@ -320,9 +323,11 @@ static void visit_box(const ctx_t* g, int s, int r, double y0, double y1, double
     double fy1 = floor((y1 - (double)g->ymin[r]) * (double)g->inv_by) + 1;
     double fz0 = floor((z0 - (double)g->in->z_min) * (double)g->inv_bz) - 1;
     double fz1 = floor((z1 - (double)g->in->z_min) * (double)g->inv_bz) + 1;
-    if (!(fy1 >= 0) || !(fz1 >= 0) || !(fy0 <= ny - 1) || !(fz0 <= nz - 1)) return;
-    int iy0 = fy0 < 0 ? 0 : (int)fy0, iy1 = fy1 > ny - 1 ? ny - 1 : (int)fy1;
-    int iz0 = fz0 < 0 ? 0 : (int)fz0, iz1 = fz1 > nz - 1 ? nz - 1 : (int)fz1;
+    if (!(fy0 <= fy1) || !(fz0 <= fz1)) return;
+    int iy0 = fy0 < 0 ? 0 : (fy0 > ny - 1 ? ny - 1 : (int)fy0);
+    int iy1 = fy1 < 0 ? 0 : (fy1 > ny - 1 ? ny - 1 : (int)fy1);
+    int iz0 = fz0 < 0 ? 0 : (fz0 > nz - 1 ? nz - 1 : (int)fz0);
+    int iz1 = fz1 < 0 ? 0 : (fz1 > nz - 1 ? nz - 1 : (int)fz1);
     uint32_t base = o->bin_base[s * g->R + r];
     for (int iz = iz0; iz <= iz1; ++iz) {
         uint32_t b0 = base + (uint32_t)(iz * ny + iy0), b1 = base + (uint32_t)(iz * ny + iy1);
@@ -643,37 +648,56 @@ void or_free(or_output_t* o) {
     memset(o, 0, sizeof *o);
 }
 
-/* stage mask: 1 grid, 2 neighbours, 4 cleaning+starts, 8 tracklets, 16 selection */
-int or_track(const or_input_t* in, const or_params_t* P, int stages, or_output_t* o) {
+/* Row tables of the grid (x, fp32 y origin, bins per row) in caller storage; 1 = invalid input. */
+typedef struct { double x[256]; float ymin[256]; int32_t ny[256]; } rowtab_t;
+static int setup_ctx(ctx_t* g, const or_input_t* in, const or_params_t* P, or_output_t* o, rowtab_t* t) {
     memset(o, 0, sizeof *o);
-    if (in->n_rows < 3 || in->n_rows > 255 || in->n_sectors < 1 || in->n_sectors > 256 || in->n < 0) return -1;
-    if (!(P->bin_y > 0) || !(P->bin_z > 0) || !(in->z_max > in->z_min)) return -1;
-    if (P->l_min_chain < 2) return -1; /* a start needs a first link to seed its direction */
-    ctx_t g;
-    memset(&g, 0, sizeof g);
-    g.in = in; g.prm = P; g.out = o;
-    g.R = in->n_rows; g.S = in->n_sectors;
-    g.kq = -0.00299792458 * in->bz;
-    double xs[256];
-    float ym[256];
-    int32_t nys[256];
-    g.x = xs; g.ymin = ym; g.ny = nys;
-    for (int r = 0; r < g.R; ++r) {
-        xs[r] = (double)in->row_x[r];
+    if (in->n_rows < 3 || in->n_rows > 255 || in->n_sectors < 1 || in->n_sectors > 256 || in->n < 0) return 1;
+    if (!(P->bin_y > 0) || !(P->bin_z > 0) || !(in->z_max > in->z_min)) return 1;
+    memset(g, 0, sizeof *g);
+    g->in = in; g->prm = P; g->out = o;
+    g->R = in->n_rows; g->S = in->n_sectors;
+    g->kq = -0.00299792458 * in->bz;
+    g->x = t->x; g->ymin = t->ymin; g->ny = t->ny;
+    for (int r = 0; r < g->R; ++r) {
+        t->x[r] = (double)in->row_x[r];
         float hw = in->row_x[r] * in->tan_half;
-        ym[r] = -hw;
+        t->ymin[r] = -hw;
         double v = ceil((2.0 * (double)hw) / (double)P->bin_y);
-        nys[r] = v < 1 ? 1 : (v > 65535 ? 65535 : (int32_t)v);
+        t->ny[r] = v < 1 ? 1 : (v > 65535 ? 65535 : (int32_t)v);
     }
     {
         double v = ceil(((double)in->z_max - (double)in->z_min) / (double)P->bin_z);
-        g.nz = v < 1 ? 1 : (v > 1048576 ? 1048576 : (int32_t)v);
+        g->nz = v < 1 ? 1 : (v > 1048576 ? 1048576 : (int32_t)v);
     }
-    g.inv_by = 1.0f / P->bin_y;
-    g.inv_bz = 1.0f / P->bin_z;
+    g->inv_by = 1.0f / P->bin_y;
+    g->inv_bz = 1.0f / P->bin_z;
+    build_grid(g);
+    return 0;
+}
+
+/* The following search of one row on its own (for tests): the cluster id chosen in row-sector
+ * (s, r) for the predicted state p with covariance c, or -1; *flag gets the near-tie bits. */
+int64_t or_follow_search(const or_input_t* in, const or_params_t* P, int s, int r, const double p[5],
+                         const double c[15], int* flag) {
+    ctx_t g;
+    rowtab_t t;
+    or_output_t o;
+    *flag = 0;
+    if (setup_ctx(&g, in, P, &o, &t) || s < 0 || s >= g.S || r < 0 || r >= g.R) { or_free(&o); return -2; }
+    int64_t id = follow_search(&g, s, r, p, c, flag);
+    or_free(&o);
+    return id;
+}
+
+/* stage mask: 1 grid, 2 neighbours, 4 cleaning+starts, 8 tracklets, 16 selection */
+int or_track(const or_input_t* in, const or_params_t* P, int stages, or_output_t* o) {
+    if (P->l_min_chain < 2) { memset(o, 0, sizeof *o); return -1; } /* a start needs a first link */
+    ctx_t g;
+    rowtab_t tabs;
+    if (setup_ctx(&g, in, P, o, &tabs)) return -1;
     int64_t n = in->n;
     size_t n1 = (size_t)(n > 0 ? n : 1);
-    build_grid(&g);
     if (!(stages & 2)) return 0;
     o->up = (int32_t*)malloc(4 * n1); o->dn = (int32_t*)malloc(4 * n1);
     o->up_c = (int32_t*)malloc(4 * n1); o->dn_c = (int32_t*)malloc(4 * n1);

@@ -10,6 +10,9 @@ namespace tpc {
 // coordinate V(y) = (y - ymin) * inv_bin that this range is computed from, so a
 // margin of 1e-6 |V| + 1e-6 (bin units) keeps every hit inside [y0, y1] in the
 // range; the caller's window tests are exact, so the margin only adds candidates.
+// Hits outside the grid's y or z range are stored in its edge bins, so the range
+// is clamped to the grid, never dropped: a box lying beyond the grid visits the
+// edge bins.  Only NaN bounds give an empty range.
 struct BinRange {
     int iy0, iy1, iz0, iz1, ny;
     uint32_t base;
@@ -35,11 +38,12 @@ __device__ inline BinRange bin_range(const GridDesc& g, const RowBins& rb, doubl
     const double vz0 = (z0 - zmin) * ibz, vz1 = (z1 - zmin) * ibz;
     const double fy0 = floor(vy0 - (1e-6 * fabs(vy0) + 1e-6)), fy1 = floor(vy1 + (1e-6 * fabs(vy1) + 1e-6));
     const double fz0 = floor(vz0 - (1e-6 * fabs(vz0) + 1e-6)), fz1 = floor(vz1 + (1e-6 * fabs(vz1) + 1e-6));
-    b.empty = !(fy1 >= 0.0) || !(fz1 >= 0.0) || !(fy0 <= (double)(b.ny - 1)) || !(fz0 <= (double)(g.nz - 1));
-    b.iy0 = fy0 < 0.0 ? 0 : (int)fy0;
-    b.iy1 = fy1 > (double)(b.ny - 1) ? b.ny - 1 : (int)fy1;
-    b.iz0 = fz0 < 0.0 ? 0 : (int)fz0;
-    b.iz1 = fz1 > (double)(g.nz - 1) ? g.nz - 1 : (int)fz1;
+    b.empty = !(fy0 <= fy1) || !(fz0 <= fz1);
+    const double ym = (double)(b.ny - 1), zm = (double)(g.nz - 1);
+    b.iy0 = fy0 < 0.0 ? 0 : (fy0 > ym ? b.ny - 1 : (int)fy0);
+    b.iy1 = fy1 < 0.0 ? 0 : (fy1 > ym ? b.ny - 1 : (int)fy1);
+    b.iz0 = fz0 < 0.0 ? 0 : (fz0 > zm ? g.nz - 1 : (int)fz0);
+    b.iz1 = fz1 < 0.0 ? 0 : (fz1 > zm ? g.nz - 1 : (int)fz1);
     b.base = rb.base;
     return b;
 }

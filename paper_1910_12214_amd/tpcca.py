@@ -152,6 +152,88 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def need(t, name: str, dtype, numel: int | None = None, min_numel: int | None = None, cols: int | None = None,
+         on_gpu: bool = True):
+    """Reject a tensor the library cannot read as a plain device array of this type and size:
+    dtype, contiguity, size (exact, minimum, or rows of `cols` values), then that it lives on a GPU.
+    Raised before any pointer reaches the C ABI, so a wrong argument never becomes a bad access."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TpcError(TPC_ERR_ARG, f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise TpcError(TPC_ERR_ARG, f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise TpcError(TPC_ERR_ARG, f"{name}: must be contiguous")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise TpcError(TPC_ERR_ARG, f"{name}: shape {tuple(t.shape)}, expected (n, {cols})")
+    if numel is not None and t.numel() != numel:
+        raise TpcError(TPC_ERR_ARG, f"{name}: {t.numel()} elements, expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise TpcError(TPC_ERR_ARG, f"{name}: {t.numel()} elements, need at least {min_numel}")
+    if on_gpu:
+        need_gpu(t, name)
+    return t
+
+
+def need_gpu(t, name: str):
+    if not t.is_cuda:
+        raise TpcError(TPC_ERR_ARG, f"{name}: must be on a GPU (device memory), got {t.device}")
+
+
+def check_clusters(y, z, row, sector) -> int:
+    """Cluster arrays: float32 y, z and uint8 row, sector, 1-D, contiguous, equal lengths, on one GPU."""
+    import torch
+
+    n = int(y.shape[0]) if hasattr(y, "shape") and len(y.shape) == 1 else -1
+    if n < 0:
+        raise TpcError(TPC_ERR_ARG, "y: expected a 1-D tensor")
+    arrays = ((y, "y", torch.float32), (z, "z", torch.float32), (row, "row", torch.uint8),
+              (sector, "sector", torch.uint8))
+    for t, nm, dt in arrays:
+        need(t, nm, dt, numel=n, on_gpu=False)
+        if t.dim() != 1:
+            raise TpcError(TPC_ERR_ARG, f"{nm}: expected a 1-D tensor")
+    for t, nm, _ in arrays:
+        need_gpu(t, nm)
+    if len({t.device for t in (y, z, row, sector)}) != 1:
+        raise TpcError(TPC_ERR_ARG, "cluster arrays must be on the same device")
+    return n
+
+
+def check_mlp(mlp):
+    """Scorer parameters: 5057 float32 values on the GPU."""
+    import torch
+
+    if mlp is not None:
+        need(mlp, "mlp", torch.float32, numel=MLP_N_PARAMS)
+
+
+def check_rows(idx, n_rows: int, name: str):
+    """Row indices must address rows of the feature array (checked on the device, one sync)."""
+    if idx.numel() and (int(idx.min()) < 0 or int(idx.max()) >= n_rows):
+        raise TpcError(TPC_ERR_ARG, f"{name}: row indices must lie in [0, {n_rows})")
+
+
+def check_tracks(o: dict):
+    """A track output (as ``Context.alloc_tracks`` returns): every array large enough for its capacity."""
+    import torch
+
+    ct, ch = int(o["cap_tracks"]), int(o["cap_hits"])
+    if ct < 0 or ch < 0 or ct >= 2 ** 31 or ch >= 2 ** 31:
+        raise TpcError(TPC_ERR_ARG, "capacities must be in [0, 2^31)")
+    arrays = (("counts", torch.int32, N_COUNTS, 0), ("hit_offset", torch.int32, 0, 1), ("n_hits", torch.int32, 0, 1),
+              ("start_id", torch.int32, 0, 1), ("sector", torch.int32, 0, 1), ("row_ref", torch.int32, 0, 1),
+              ("x_ref", torch.float32, 0, 1), ("state", torch.float32, 0, 5), ("cov", torch.float32, 0, 15),
+              ("chi2", torch.float32, 0, 1), ("ndf", torch.int32, 0, 1))
+    for k, dt, fixed, per in arrays:
+        need(o[k], k, dt, min_numel=fixed + per * ct, on_gpu=False)
+    need(o["hit_ids"], "hit_ids", torch.int32, min_numel=ch, on_gpu=False)
+    for k, *_ in arrays:
+        need_gpu(o[k], k)
+    need_gpu(o["hit_ids"], "hit_ids")
+
+
 def _stream(stream) -> int:
     import torch
 
@@ -227,6 +309,7 @@ class Context:
 
     @staticmethod
     def _tracks_struct(o: dict) -> Tracks:
+        check_tracks(o)
         t = Tracks()
         t.cap_tracks = o["cap_tracks"]
         t.cap_hits = o["cap_hits"]
@@ -238,7 +321,7 @@ class Context:
     @staticmethod
     def _clusters(y, z, row, sector) -> Clusters:
         c = Clusters()
-        c.n = int(y.shape[0])
+        c.n = check_clusters(y, z, row, sector)
         c.y, c.z, c.row, c.sector = _ptr(y), _ptr(z), _ptr(row), _ptr(sector)
         return c
 
@@ -246,10 +329,11 @@ class Context:
               tau_logit: float = 0.0, out: dict | None = None, stream=None, sync_check: bool = True,
               timeframe: bool = False) -> dict:
         """Track clusters given as CUDA tensors (float32 y, z; uint8 row, sector)."""
-        n = int(y.shape[0])
+        cl = self._clusters(y, z, row, sector)
+        check_mlp(mlp)
+        n = int(cl.n)
         if out is None:
             out = self.alloc_tracks(max(16, n // 8), max(16, n))
-        cl = self._clusters(y, z, row, sector)
         g, _keep = make_geometry(geom)
         p = make_params(params, mlp, tau_logit)
         t = self._tracks_struct(out)
@@ -267,10 +351,11 @@ class Context:
         x_ref, state are read)."""
         import torch
 
-        n = int(y.shape[0])
+        cl = self._clusters(y, z, row, sector)
+        n = int(cl.n)
         if flags is None:
             flags = torch.empty(max(1, n), dtype=torch.uint8, device=y.device)
-        cl = self._clusters(y, z, row, sector)
+        need(flags, "flags", torch.uint8, min_numel=n)
         g, _keep = make_geometry(geom)
         p = make_params(params)
         fp = FlagParams(tube_cm, pt_min, phi_max_deg)
@@ -315,9 +400,14 @@ class Context:
     def mlp_infer(self, feats, mlp, logits=None, stream=None):
         import torch
 
+        need(feats, "feats", torch.float32, cols=12)
+        check_mlp(mlp)
+        if mlp is None:
+            raise TpcError(TPC_ERR_ARG, "mlp is required")
         n = int(feats.shape[0])
         if logits is None:
             logits = torch.empty(max(1, n), dtype=torch.float32, device=feats.device)
+        need(logits, "logits", torch.float32, min_numel=n)
         self._check(self.lib.tpc_mlp_infer(self.h, _ptr(feats), n, _ptr(mlp), _ptr(logits), _stream(stream)))
         return logits[:n]
 
@@ -325,12 +415,12 @@ class Context:
                  stream=None):
         import torch
 
-        n = int(y.shape[0])
+        cl = self._clusters(y, z, row, sector)
+        n = int(cl.n)
         cap = cap or max(64, 4 * n)
         dev = y.device
         trip = torch.empty(cap, 3, dtype=torch.int32, device=dev)
         feats = torch.empty(cap, 12, dtype=torch.float32, device=dev)
-        cl = self._clusters(y, z, row, sector)
         g, _keep = make_geometry(geom)
         p = make_params(params)
         nout = ctypes.c_int64(0)
@@ -343,6 +433,13 @@ class Context:
     def mlp_grad(self, feats, labels, idx, mlp, stream=None):
         import torch
 
+        need(feats, "feats", torch.float32, cols=12)
+        need(labels, "labels", torch.uint8, numel=int(feats.shape[0]))
+        need(idx, "idx", torch.int32)
+        if idx.dim() != 1:
+            raise TpcError(TPC_ERR_ARG, "idx: expected a 1-D tensor")
+        check_mlp(mlp)
+        check_rows(idx, int(feats.shape[0]), "idx")
         grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=feats.device)
         loss = torch.empty(1, dtype=torch.float32, device=feats.device)
         self._check(self.lib.tpc_mlp_grad(self.h, _ptr(feats), _ptr(labels), _ptr(idx), int(idx.shape[0]), _ptr(mlp),
@@ -353,6 +450,12 @@ class Context:
                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
         import torch
 
+        need(feats, "feats", torch.float32, cols=12)
+        need(labels, "labels", torch.uint8, numel=int(feats.shape[0]))
+        need(order, "order", torch.int32, min_numel=int(batch) * int(n_steps))
+        for t, nm in ((mlp, "mlp"), (m, "m"), (v, "v")):
+            need(t, nm, torch.float32, numel=MLP_N_PARAMS)
+        check_rows(order[:int(batch) * int(n_steps)], int(feats.shape[0]), "order")
         loss = torch.empty(max(1, n_steps), dtype=torch.float32, device=feats.device)
         cfg = TrainCfg(batch=batch, n_steps=n_steps, step0=step0, lr=lr, beta1=beta1, beta2=beta2, eps=eps)
         self._check(self.lib.tpc_mlp_train(self.h, _ptr(feats), _ptr(labels), _ptr(order), ctypes.byref(cfg),

@@ -8,6 +8,8 @@ Rules (DESIGN.md, near-ties):
   link taints its start and tracklet, a flagged tracklet taints its hits, and a track that
   touches a tainted hit is excluded; every exclusion is counted and reported;
 * track parameters: |a - b| <= 1e-4 max(|b|, floor) with floors (1 cm, 1 cm, 1e-2, 1e-2, 1e-2);
+* covariances: every GPU output covariance is symmetric positive definite (Cholesky), and each
+  element agrees within 1e-4 of its scale sqrt(C_ii C_jj); see ``compare`` for the one widening;
 * efficiency, fake and clone rates: within 0.1% absolute.
 """
 from __future__ import annotations
@@ -82,14 +84,50 @@ def cov_scale_err(c, co):
     return np.abs(c - co) / np.maximum(scale, 1e-300)
 
 
+# Covariance tolerance widening (see ``compare``): where it may apply, and its cap.
+COV_TOL = 1e-4
+COV_WIDEN_FACTOR = 10.0
+COV_WIDEN_CAP = 1e-3
+COV_WIDEN_MIN_SINPHI = 0.99
+
+
+def max_abs_sinphi(state, x_ref: float, xs, bz: float) -> float:
+    """Largest |sin phi| of the oracle's fitted helix at the given pad-row radii (the track's hits)."""
+    import oracle
+
+    m = abs(float(state[2]))
+    for x in xs:
+        p1, _, failed = oracle.propagate(state, float(x_ref), float(x), bz)
+        m = max(m, 1.0 if failed else abs(float(p1[2])))
+    return m
+
+
+def assert_spd(cov15, what: str = "track") -> None:
+    """Every covariance (rows of 15, packed lower triangle) is symmetric positive definite."""
+    cov15 = np.atleast_2d(np.asarray(cov15, dtype=np.float64))
+    M = np.zeros((cov15.shape[0], 5, 5))
+    M[:, COV_I, COV_J] = cov15
+    M[:, COV_J, COV_I] = cov15
+    for k in range(M.shape[0]):
+        try:
+            np.linalg.cholesky(M[k])
+        except np.linalg.LinAlgError:
+            raise AssertionError(f"{what} {k}: covariance not positive definite: {cov15[k]}") from None
+
+
 def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: int = 3,
-            check_rates: bool = True, sectors=None, sector_of=None, o_fma: dict | None = None) -> Report:
+            check_rates: bool = True, sectors=None, sector_of=None, o_fma: dict | None = None,
+            row_of=None, row_x=None, bz: float = 0.5) -> Report:
     """Assert GPU == oracle under the near-tie rules; return the counts of exclusions.
 
-    Covariances must agree within 1e-4 of their scale sqrt(C_ii C_jj), widened for a track to
-    10x the change of the oracle's own result between its plain and FMA-contracted builds
-    (``o_fma``): near a looper's turning point (|sin phi| -> 1) the x-parametrised model
-    amplifies rounding, and no FP64 implementation can be closer than the oracle is to itself.
+    Covariances must agree within 1e-4 of their scale sqrt(C_ii C_jj).  One reading widens this:
+    near a looper's turning point (|sin phi| -> s_max) the x-parametrised model amplifies rounding,
+    and no FP64 implementation can be closer to the oracle than the oracle is to itself.  With the
+    oracle's FMA-contracted build (``o_fma``) given, a track's tolerance becomes 10x the change of the
+    oracle's own covariance between its two builds, capped at 1e-3, and only for a track whose fitted
+    helix reaches |sin phi| >= 0.99 on one of its hit rows (asserted: needs ``row_of`` and
+    ``row_x``).  On the Pb-Pb event every track below |sin phi| 0.95 changes by < 2e-9 between the
+    builds, and all 37 widened tracks reach |sin phi| >= 0.997.
 
     ``sectors`` restricts the comparison to clusters/tracks of those sectors (sampled
     comparison at full size: sectors are independent in every step)."""
@@ -187,6 +225,11 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
     gtr = {int(tracks["start_id"][k]): k for k in range(nt)}
     n_tr = n_tr_ex = n_widened = 0
     worst = worst_cov = 0.0
+    worst_sphi_widened = 1.0
+    # every GPU output covariance of the compared sectors is SPD
+    gsel = [k for k in range(nt) if sel[int(tracks["start_id"][k])]]
+    if gsel:
+        assert_spd(np.asarray(tracks["cov"])[gsel], "GPU track")
     for k in range(o["n_tracks"]):
         t = int(o["trk_tl"][k])
         s = int(o["start_id"][t])
@@ -209,12 +252,17 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
         c = tracks["cov"][kg].astype(np.float64)
         co = o["tl_cov"][t]
         cerr = cov_scale_err(c, co)[0]
-        tol = 1e-4
-        if o_fma is not None:
+        tol = COV_TOL
+        if o_fma is not None and float(cerr.max()) > COV_TOL:
             self_err = float(cov_scale_err(o_fma["tl_cov"][t], co)[0].max())
-            if 10 * self_err > tol:
-                tol = 10 * self_err
+            if COV_WIDEN_FACTOR * self_err > tol:
+                assert row_of is not None and row_x is not None, "widening needs the rows of the hits"
+                sphi = max_abs_sinphi(o["tl_state"][t], row_x[o["tl_row_ref"][t]], row_x[row_of[oh]], bz)
+                assert sphi >= COV_WIDEN_MIN_SINPHI, \
+                    f"track {s}: covariance tolerance would widen at max |sin phi| {sphi:.4f}"
+                tol = min(COV_WIDEN_FACTOR * self_err, COV_WIDEN_CAP)
                 n_widened += 1
+                worst_sphi_widened = min(worst_sphi_widened, sphi)
         worst_cov = max(worst_cov, float(cerr.max()))
         assert np.all(cerr <= tol), f"track {s}: covariance differs, element {int(np.argmax(cerr))}: {c} vs {co}"
         n_tr += 1
@@ -230,6 +278,9 @@ def compare(o: dict, st: dict, tracks: dict, n: int, R: int, leg=None, l_min: in
     rep["track_state_worst_rel"] = worst
     rep["track_cov_worst"] = worst_cov
     rep["track_cov_tol_widened"] = n_widened
+    if n_widened:
+        rep["track_cov_widened_min_sinphi"] = round(worst_sphi_widened, 5)
+    rep["gpu_tracks_spd"] = len(gsel)
     # ---- rates
     if check_rates and leg is not None and sectors is None:
         mo = metrics.match(leg, o["trk_off"], o["trk_hits"])

@@ -160,7 +160,8 @@ def test_pruned_tracking_parity(ctx, frac):
     qtheta = omlp.quantize(theta)
     o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=qtheta, n_threads=THREADS)
     o_fma = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=qtheta, n_threads=THREADS, fma=True)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
     c = trk["counts"]
     say(f"[mlp] pruned parity: {rep.line()} pairs={c[tpcca.CNT_PAIRS]} kept={c[tpcca.CNT_PAIRS_KEPT]}")
     # kept = pairs within the plain criterion's cut whose logit reaches tau: below the
@@ -196,7 +197,8 @@ def test_pruned_parity_when_candidate_lists_overflow(ctx):
     say(f"[mlp] wide windows: {len(trip)} pairs, {c[tpcca.CNT_NB_OVERFLOW]} of {groups} groups overflowed")
     assert 0 < c[tpcca.CNT_NB_OVERFLOW] <= groups
     assert c[tpcca.CNT_PAIRS] == len(trip)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
     say(f"[mlp] wide windows parity: {rep.line()}")
     assert rep["tracks_compared"] > 50
 
@@ -272,7 +274,8 @@ def test_full_event_pruned_sampled_sectors(ctx):
     args = (ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, prm, synth.BZ)
     o = lift(oracle.track(*args, mlp=q, n_threads=THREADS), ids, ev.n)
     o_fma = lift(oracle.track(*args, mlp=q, n_threads=THREADS, fma=True), ids, ev.n)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
     c = trk["counts"]
     say(f"[mlp] full event, tau {tau}, sectors {sectors}: {rep.line()} pairs={c[tpcca.CNT_PAIRS]} "
         f"kept={c[tpcca.CNT_PAIRS_KEPT]} overflow groups={c[tpcca.CNT_NB_OVERFLOW]}")

@@ -56,7 +56,8 @@ def check(ctx, w, ev, params=None, label=""):
     st = parity.gpu_stages(ctx, synth.N_ROWS)
     o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, params, synth.BZ, n_threads=THREADS)
     o_fma = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, params, synth.BZ, n_threads=THREADS, fma=True)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, l_min=params["l_min_chain"], o_fma=o_fma)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, l_min=params["l_min_chain"], o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
     c = trk["counts"]
     assert c[0] == o["n_tracks"] or rep["track_near_ties"] > 0
     say(f"[parity] {label or w.name}: {rep.line()} gpu_tracks={c[0]} oracle_tracks={o['n_tracks']}")
@@ -187,3 +188,42 @@ def test_argument_errors(ctx):
     g2 = dict(geom, row_x=geom["row_x"][::-1].copy())
     with pytest.raises(tpcca.TpcError):
         ctx.track(y, z, r, s, g2, synth.BZ, synth.TRACKER_PARAMS)
+
+
+@pytest.mark.parametrize("bins", [(8.0, 8.0), (0.9, 1.7)])
+def test_clusters_outside_the_grid_range(ctx, bins):
+    """Clusters beyond the grid's y range (lines that leave the sector, clusters far past the edge)
+    and outside its z range are stored in the edge bins; every step must still find them exactly as
+    the oracle does, for any bin size (a query box beyond the grid visits the edge bins)."""
+    rng = np.random.default_rng(77)
+    ev = synth.generate(synth.SECTOR_EVENT)
+    rx = synth.row_x().astype(np.float64)
+    th = float(synth.tan_half())
+    extra_y, extra_z, extra_r = [], [], []
+    # two straight lines leaving the sector on either side, clusters on every row
+    for y0, slope, z0, tz in ((-3.0, 0.35, 40.0, 0.2), (4.0, -0.42, 120.0, -0.1)):
+        c = 1.0 / np.sqrt(1.0 + slope * slope)
+        extra_y += list(y0 + slope * (rx - 85.0)); extra_z += list(z0 + tz * (rx - 85.0) / c)
+        extra_r += list(range(synth.N_ROWS))
+    # a line running below z_min and one above z_max
+    for z0, tz in ((5.0, -0.3), (240.0, 0.35)):
+        extra_y += list(0.02 * (rx - 85.0)); extra_z += list(z0 + tz * (rx - 85.0)); extra_r += list(range(synth.N_ROWS))
+    # scattered clusters far beyond the edges, in y and in z
+    k = 400
+    rr = rng.integers(0, synth.N_ROWS, k)
+    side = rng.choice([-1.0, 1.0], k)
+    extra_y += list(side * (rx[rr] * th + rng.uniform(0.5, 60.0, k))); extra_z += list(rng.uniform(-30, 280, k))
+    extra_r += list(rr)
+    y = np.concatenate([ev.y, np.array(extra_y, np.float32)])
+    z = np.concatenate([ev.z, np.array(extra_z, np.float32)])
+    row = np.concatenate([ev.row, np.array(extra_r, np.uint8)])
+    sec = np.zeros_like(row)
+    leg = np.concatenate([ev.leg, np.full(len(extra_y), -1, np.int32)])
+    evx = dataclasses.replace(ev, y=y, z=z, row=row, sector=sec, leg=leg)
+    rep, trk, o = check(ctx, synth.SECTOR_EVENT, evx, dict(bin_y=bins[0], bin_z=bins[1]), label=f"outside{bins}")
+    # the lines beyond the edge are tracked up to the edge stop, the z lines in full
+    assert rep["tracks_compared"] > 100
+    n_out = int(((np.abs(y) > synth.row_x()[row] * synth.tan_half()) | (z < 0) | (z > 250)).sum())
+    on_tracks = np.isin(np.arange(ev.n, y.size), trk["hit_ids"]).sum()
+    say(f"[parity] outside{bins}: {n_out} clusters outside the grid, {on_tracks} added clusters on tracks")
+    assert on_tracks > 300

@@ -138,7 +138,8 @@ def test_full_pbpb_timeframe_sampled_sectors(ctx):
                          fma=True)
     o = lift(o, ids, ev.n)
     o_fma = lift(o_fma, ids, ev.n)
-    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, sectors=sectors, sector_of=ev.sector, o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
     say(f"[tf] full frame sectors {sectors}: {rep.line()}")
     assert rep["tracks_compared"] > 20000
 
@@ -195,3 +196,41 @@ def test_pp_timeframe_with_fused_scorer_equals_sector_path(ctx):
     c = a["counts"]
     say(f"[tf] pp frame {ev.n} clusters: pairs {c[tpcca.CNT_PAIRS]} kept {c[tpcca.CNT_PAIRS_KEPT]} tracks {c[0]}")
     assert c[tpcca.CNT_PAIRS_KEPT] < c[tpcca.CNT_PAIRS]
+
+
+@pytest.mark.parametrize("pruned", [False, True])
+def test_pp_timeframe_slice_equals_oracle(ctx, pruned):
+    """A tenth of the pp time frame (1140 collisions over 1.14 ms, Poisson(12) each, 10% noise), in
+    one graph launch of the time-frame entry point, plain and with the pp scorer fused into
+    neighbour finding, equals the oracle stage by stage (with the same BF16 scorer in FP64)."""
+    from oracle import mlp as omlp
+    from paper_1910_12214_amd import scorer as sc
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.scaled(synth.PP_TIMEFRAME, 0.1)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    prm = dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0)
+    kw, q = {}, None
+    if pruned:
+        theta, tau = sc.load(sc.PP_CKPT)
+        kw = dict(mlp=dev(theta), tau_logit=tau)
+        q = omlp.quantize(theta.astype(np.float64))
+        prm.update(mlp_tau_logit=tau, mlp_flag_abs=1e-4)
+    say(f"[tf] pp slice {ev.n} clusters, pruned={pruned}")
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=2, blocks_per_cu=6, waves_per_simd=3))
+    out = ctx.alloc_tracks(ev.n // 8, ev.n)
+    ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True, **kw)
+    ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True, **kw)  # graph replay
+    ctx.set_tuning(None)
+    trk = tpcca.tracks_to_host(out)
+    st = parity.gpu_stages(ctx, synth.N_ROWS)
+    o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=q, n_threads=THREADS)
+    o_fma = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, prm, synth.BZ, mlp=q, n_threads=THREADS, fma=True)
+    rep = parity.compare(o, st, trk, ev.n, synth.N_ROWS, leg=ev.leg, o_fma=o_fma,
+                         row_of=ev.row, row_x=synth.row_x(), bz=synth.BZ)
+    c = trk["counts"]
+    say(f"[tf] pp slice parity (pruned={pruned}): {rep.line()} pairs={c[tpcca.CNT_PAIRS]} "
+        f"kept={c[tpcca.CNT_PAIRS_KEPT]}")
+    assert rep["tracks_compared"] > 5000
