@@ -621,9 +621,13 @@ int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geomet
         enqueue_chain(c, *cl, pr, s, *out, q, blocks, t.chunk, t.waves, st);
         TPC_HIP(c, hipGetLastError());
     } else {
-        // every kernel argument is part of the key: a replay runs exactly the captured chain
+        // every kernel argument is part of the key (the prepared grid description and kernel
+        // parameters as the kernels receive them, z range included): a replay runs exactly the
+        // captured chain
         std::string key = bytes_of(cl, sizeof *cl) + bytes_of(&p2, sizeof p2) + bytes_of(out, sizeof *out) +
                           bytes_of(&bz, sizeof bz) + bytes_of(&t, sizeof t) + bytes_of(&c->buf_gen, sizeof c->buf_gen) +
+                          bytes_of(&pr.g, sizeof pr.g) + bytes_of(&pr.kp, sizeof pr.kp) + bytes_of(&pr.n, sizeof pr.n) +
+                          bytes_of(&pr.t_max, sizeof pr.t_max) + bytes_of(&pr.slab_bins, sizeof pr.slab_bins) +
                           c->geo_key;
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {

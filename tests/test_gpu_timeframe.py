@@ -234,3 +234,36 @@ def test_pp_timeframe_slice_equals_oracle(ctx, pruned):
     say(f"[tf] pp slice parity (pruned={pruned}): {rep.line()} pairs={c[tpcca.CNT_PAIRS]} "
         f"kept={c[tpcca.CNT_PAIRS_KEPT]}")
     assert rep["tracks_compared"] > 5000
+
+
+def test_graph_replay_with_shifted_z_window(ctx):
+    """The same clusters shifted in z by D, tracked with the z window [z_min + D, z_max + D] of the
+    same width: the grid has the same number of z bins and every buffer stays where it is, so only
+    the z origin differs between the two calls.  The second call must not replay the first graph
+    (whose kernels would place every cluster in the wrong bins): its tracks are the same as the
+    unshifted ones, with z shifted, and equal the per-sector path's."""
+    import torch
+
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.scaled(synth.PBPB_TIMEFRAME, 0.01)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    D = 400.0
+    geom2 = dict(geom, z_min=geom["z_min"] + D, z_max=geom["z_max"] + D)
+    # z on a 2^-13 cm lattice, so that z and z + D are both exact in FP32 (z + D < 2048)
+    zq = (np.round(ev.z.astype(np.float64) * 8192.0) / 8192.0).astype(np.float32)
+    assert np.array_equal((zq + np.float32(D)) - np.float32(D), zq)
+    ten = [dev(a) for a in (ev.y, zq, ev.row, ev.sector)]
+    out = ctx.alloc_tracks(ev.n // 4, ev.n)
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=8))
+    ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True)
+    a = tpcca.tracks_to_host(out)
+    ten[1].copy_(torch.from_numpy(zq + np.float32(D)))
+    ctx.track(*ten, geom2, synth.BZ, synth.TRACKER_PARAMS, out=out, timeframe=True)
+    b = tpcca.tracks_to_host(out)
+    ctx.set_tuning(None)
+    ref = tpcca.tracks_to_host(ctx.track(*ten, geom2, synth.BZ, dict(synth.TRACKER_PARAMS, bin_y=8.0, bin_z=16.0)))
+    same(b, ref)
+    assert a["counts"][0] > 100
+    assert np.array_equal(a["hit_ids"], b["hit_ids"]) and np.array_equal(a["n_hits"], b["n_hits"])
