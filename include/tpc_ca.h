@@ -18,6 +18,12 @@
  *  - Work is enqueued on the given HIP stream (hipStream_t passed as void*;
  *    NULL = the null stream).  Calls return once the work is enqueued unless
  *    stated otherwise.
+ *  - A context serves one stream at a time: every call on a context reuses the
+ *    same scratch buffers, so two calls on one context whose work overlaps on
+ *    different streams race (wrong results, no error).  Work that should run
+ *    concurrently uses one context per stream; consecutive calls on one context
+ *    with different streams must be ordered by the caller (events or a
+ *    synchronisation).  Contexts never share scratch.
  *  - Return value: TPC_OK (0) or a negative TPC_ERR_* code; tpc_last_error()
  *    gives a message.  No exception crosses the ABI.
  *  - Units: cm, Tesla, GeV/c.  Clusters are in each sector's local frame:
