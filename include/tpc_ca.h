@@ -273,6 +273,23 @@ typedef struct {
 int tpc_mlp_train(tpc_ctx_t* ctx, const float* feats, const uint8_t* labels, const int32_t* order,
                   const tpc_train_cfg_t* cfg, float* mlp, float* m, float* v, float* loss, void* stream);
 
+/* ---- allocation-free variant ----
+ * For callers that cannot allocate device memory while they run: code under HIP
+ * graph capture, tight training loops, harnesses that forbid hipMalloc.
+ * tpc_mlp_train_noalloc takes the arguments of tpc_mlp_train and computes the same
+ * result with the same kernels (bit-identical), but calls no allocator: its
+ * scratch (packed BF16 weights and per-block partial gradients) is a fixed array
+ * of TPC_MLP_NOALLOC_SCRATCH_BYTES bytes (about 5 MB) that each device holds from
+ * the first tpc_ctx_create on it until the process ends.  cfg->batch above
+ * TPC_MLP_NOALLOC_MAX_BATCH returns TPC_ERR_ARG with a message.  All calls on one
+ * device share that array: calls whose work overlaps on one device (several
+ * streams, contexts or threads) race and give wrong results, so the caller orders
+ * them.  Pointers and stream as for tpc_mlp_train. */
+#define TPC_MLP_NOALLOC_MAX_BATCH 65536
+#define TPC_MLP_NOALLOC_SCRATCH_BYTES 5204992
+int tpc_mlp_train_noalloc(tpc_ctx_t* ctx, const float* feats, const uint8_t* labels, const int32_t* order,
+                          const tpc_train_cfg_t* cfg, float* mlp, float* m, float* v, float* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

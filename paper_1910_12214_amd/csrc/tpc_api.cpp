@@ -387,6 +387,7 @@ int tpc_ctx_create(tpc_ctx_t** out, int device) {
     if (hipSetDevice(device) != hipSuccess) return TPC_ERR_HIP;
     tpc_ctx_t* c = new tpc_ctx_t();
     c->device = device;
+    noalloc_init(device);  // device address of the allocation-free entry point's fixed scratch
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;

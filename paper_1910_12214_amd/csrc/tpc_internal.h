@@ -213,6 +213,12 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
                    uint8_t* att, uint8_t* adj, uint8_t* flags, hipStream_t s);
 
 // mlp.hip
+// Sizes of the training scratch: the packed BF16 weights (bytes) and one partial gradient of
+// TPC_MLP_N_PARAMS + 1 floats (the last one the loss sum) per block of kMlpTrainChunk rows.
+// tpc_mlp.hip checks them against its layout.
+constexpr size_t kMlpQBytes = 25360;
+constexpr int kMlpTrainChunk = 256;
+constexpr int kMlpMaxBatch = 65536;  // rows per training step accepted by the training entry points
 size_t mlp_q_floats();
 void mlp_quantize(const float* master, float* q, hipStream_t s);  // q: packed kernel layout
 void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hipStream_t s);
@@ -234,5 +240,12 @@ void mlp_grad_step(const float* q, const float* feats, const uint8_t* labels, co
                    float* part, hipStream_t s);
 void mlp_reduce(const float* part, int batch, float* grad, float* loss, float* master, float* m, float* v, int step,
                 float lr, float b1, float b2, float eps, hipStream_t s);
+
+// noalloc.hip: the fixed per-device scratch of tpc_mlp_train_noalloc.  noalloc_init looks up
+// the array's device address once per device (the device must be current); noalloc_scratch
+// returns it, or nullptr with the HIP error of the lookup in *err.
+void noalloc_init(int device);
+void* noalloc_scratch(int device, hipError_t* err);
+size_t noalloc_scratch_bytes();
 
 }  // namespace tpc

@@ -39,6 +39,7 @@ constexpr int kB2 = kB1 + 64 * 4;        // [64] f32
 constexpr int kW3 = kB2 + 64 * 4;        // [64] f32 (BF16-valued)
 constexpr int kB3 = kW3 + 64 * 4;        // [1] f32
 constexpr int kQBytes = kB3 + 16;
+static_assert(kQBytes == (int)kMlpQBytes, "packed weight size known to the scratch layout");
 
 // master layout (floats)
 constexpr int mW1 = 0, mB1 = 768, mW2 = 832, mB2 = 4928, mW3 = 4992, mB3 = 5056;
@@ -881,7 +882,7 @@ __global__ __launch_bounds__(64 * kNbWaves) void k_nb_mlp_fallback(GridDesc g, K
 }
 
 // ------------------------------------------------------------ training
-constexpr int kTrainChunk = 256;  // triplets per block (one wave) and step
+constexpr int kTrainChunk = kMlpTrainChunk;  // triplets per block (one wave) and step
 
 __device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
 

@@ -71,7 +71,9 @@ class TrainCfg(ctypes.Structure):
 EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_default", "tpc_track_sectors",
            "tpc_track_timeframe", "tpc_timeframe_tuning", "tpc_timeframe_set_tuning", "tpc_stage_size",
            "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train",
-           "tpc_profile_enable", "tpc_profile_read", "tpc_cluster_flags", "tpc_flag_params_default")
+           "tpc_profile_enable", "tpc_profile_read", "tpc_cluster_flags", "tpc_flag_params_default",
+           "tpc_mlp_train_noalloc")
+MLP_NOALLOC_MAX_BATCH = 65536
 N_PROF = 5
 PROF_STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "selection")
 
@@ -128,6 +130,8 @@ def load():
     lib.tpc_mlp_grad.restype = ctypes.c_int
     lib.tpc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, P(TrainCfg), _vp, _vp, _vp, _vp, _vp]
     lib.tpc_mlp_train.restype = ctypes.c_int
+    lib.tpc_mlp_train_noalloc.argtypes = [_vp, _vp, _vp, _vp, P(TrainCfg), _vp, _vp, _vp, _vp, _vp]
+    lib.tpc_mlp_train_noalloc.restype = ctypes.c_int
     lib.tpc_profile_enable.argtypes = [_vp, ctypes.c_int]
     lib.tpc_profile_enable.restype = ctypes.c_int
     lib.tpc_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -447,7 +451,11 @@ class Context:
         return grad, loss
 
     def mlp_train(self, feats, labels, order, mlp, m, v, batch: int, n_steps: int, step0: int = 0,
-                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None,
+                  loss=None, noalloc: bool = False):
+        """Adam steps on the scorer (tpc_mlp_train; tpc_mlp_train_noalloc with ``noalloc``, which uses the
+        library's fixed per-device scratch and allocates nothing).  ``loss`` (device, >= n_steps floats)
+        receives each step's loss; if None a tensor is allocated here."""
         import torch
 
         need(feats, "feats", torch.float32, cols=12)
@@ -456,10 +464,14 @@ class Context:
         for t, nm in ((mlp, "mlp"), (m, "m"), (v, "v")):
             need(t, nm, torch.float32, numel=MLP_N_PARAMS)
         check_rows(order[:int(batch) * int(n_steps)], int(feats.shape[0]), "order")
-        loss = torch.empty(max(1, n_steps), dtype=torch.float32, device=feats.device)
+        if loss is None:
+            loss = torch.empty(max(1, n_steps), dtype=torch.float32, device=feats.device)
+        else:
+            need(loss, "loss", torch.float32, min_numel=max(1, int(n_steps)))
         cfg = TrainCfg(batch=batch, n_steps=n_steps, step0=step0, lr=lr, beta1=beta1, beta2=beta2, eps=eps)
-        self._check(self.lib.tpc_mlp_train(self.h, _ptr(feats), _ptr(labels), _ptr(order), ctypes.byref(cfg),
-                                           _ptr(mlp), _ptr(m), _ptr(v), _ptr(loss), _stream(stream)))
+        fn = self.lib.tpc_mlp_train_noalloc if noalloc else self.lib.tpc_mlp_train
+        self._check(fn(self.h, _ptr(feats), _ptr(labels), _ptr(order), ctypes.byref(cfg), _ptr(mlp), _ptr(m), _ptr(v),
+                       _ptr(loss), _stream(stream)))
         return loss
 
 
