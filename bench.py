@@ -2,9 +2,12 @@
 
 One step = one full pass of the hot path (row grid, neighbour finding, cleaning, start hits,
 tracklet construction, selection and output) over one synthetic workload already resident
-in HBM.  Prints one JSON line.  Also times, live with HIP events on the library's stream,
-each step of the chain; the dominant step is reported against the HBM roofline, and the FP64
-oracle is timed on a bounded sample on the host cores.
+in HBM.  The default workload is the largest single-GPU one: a continuous-readout Pb-Pb time
+frame of 570 collisions (72.8M clusters), tracked per step by one graph launch of
+tpc_track_timeframe.  Prints one JSON line.  Also times, live with HIP events on the library's
+stream, each step of the chain; the dominant step is reported against the HBM roofline, the
+FP64 oracle is timed on a bounded sample on the host cores, and the same measurement on one
+Pb-Pb event (866k clusters, tpc_track_sectors) is added under "event".
 """
 from __future__ import annotations
 
@@ -65,7 +68,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pbpb_event_5000")
+    ap.add_argument("--workload", default="pbpb_timeframe_570")
+    ap.add_argument("--event-workload", default="pbpb_event_5000",
+                    help="workload of the extra event measurement ('' to skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
     ap.add_argument("--no-flags", action="store_true", help="skip the cluster-flag measurement")
@@ -114,29 +119,69 @@ def cpu_baseline(ev, geom, params, budget_s: float):
     t0 = time.perf_counter()
     oracle.cluster_flags(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, synth.BZ, trk)
     tf = time.perf_counter() - t0
+    # all cores: threads run whole sectors, so the sample has at least one sector per thread
     cores = min(16, os.cpu_count() or 1)
+    sel_all = ev.sector < max(n_sec, min(cores, synth.N_SECTORS))
+    n_all = int(sel_all.sum())
     t0 = time.perf_counter()
-    oracle.track(ev.y[sel], ev.z[sel], ev.row[sel], ev.sector[sel], geom, params, synth.BZ, n_threads=cores)
+    oracle.track(ev.y[sel_all], ev.z[sel_all], ev.row[sel_all], ev.sector[sel_all], geom, params, synth.BZ,
+                 n_threads=cores)
     tn = time.perf_counter() - t0
     del order
     return {"value": n_sample / t1, "unit": "clusters/s", "cores": 1, "kind": "oracle",
             "sample": f"sectors 0..{n_sec - 1} of {ev.workload.name} ({n_sample} clusters), FP64 C oracle, 1 thread",
-            "value_all_cores": n_sample / tn, "cores_all": cores,
+            "value_all_cores": n_all / tn, "cores_all": cores, "sample_all_cores": f"{n_all} clusters",
             "cluster_flags": {"value": n_sample / tf, "unit": "clusters/s", "cores": 1, "kind": "oracle"}}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-        sys.exit(2)
+
+STAGE_SRC = {"grid": "paper_1910_12214_amd/csrc/tpc_grid.hip", "neighbours": "paper_1910_12214_amd/csrc/tpc_links.hip",
+             "clean_starts": "paper_1910_12214_amd/csrc/tpc_links.hip",
+             "tracklets": "paper_1910_12214_amd/csrc/tpc_tracklets.hip",
+             "selection": "paper_1910_12214_amd/csrc/tpc_select.hip"}
+
+
+def timed_steps(ctx, step, steps: int, warmup: int, graph: bool):
+    """Warm-up, then `steps` timed steps between device synchronisations (wall clock), then the
+    per-stage HIP-event times of the same number of steps (recorded inside the timed steps for
+    eager launches; in an extra eager pass for graph launches, whose replays carry no events)."""
+    import torch
+
+    step(sync_check=True)  # sizes scratch (and tunes the time-frame tiles)
+    for _ in range(warmup):
+        step(sync_check=False)
+    torch.cuda.synchronize()
+    if not graph:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(sync_check=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if graph:
+        ctx.profile(True)
+        for _ in range(steps):
+            step(sync_check=False)
+        torch.cuda.synchronize()
+    ctx.profile(False)
+    stage_ms, n_calls = ctx.profile_read()
+    return ms, {k: v / max(1, n_calls) for k, v in stage_ms.items()}
+
+
+def measure(w, args, primary: bool):
+    """Plain and pruned throughput of one workload, its stage times and roofline, the cluster
+    flags of its tracks and (for events) two events in flight."""
+    import dataclasses
+
     import numpy as np
     import torch
 
     import synth
+    from paper_1910_12214_amd import scorer as sc
     from paper_1910_12214_amd import tpcca
+    from synth import metrics
 
-    w = synth.WORKLOADS[args.workload]
     log("generating", w.name)
     ev = synth.generate(w, want_exact=w.t_frame_us == 0)  # events keep the true momenta (flag curve)
     log("generated", ev.n, "clusters")
@@ -158,60 +203,31 @@ def main():
     def step(**kw):
         return ctx.track(y, z, r, s, geom, synth.BZ, params, out=out, stream=stream, timeframe=tf, **kw)
 
-    step(sync_check=True)  # sizes scratch (and tunes the time-frame tiles)
-    log("warmup")
-    for _ in range(args.warmup):
-        step(sync_check=False)
-    torch.cuda.synchronize()
-    if not tf:
-        ctx.profile(True)  # stage events recorded inside the timed steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(sync_check=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log("timed", args.steps, "steps")
-    if tf:  # graph replays cannot carry timing events: time the steps in an eager pass
-        ctx.profile(True)
-        for _ in range(args.steps):
-            step(sync_check=False)
-        torch.cuda.synchronize()
-    ctx.profile(False)
-    stage_ms, n_calls = ctx.profile_read()
+    ms_step, per_stage = timed_steps(ctx, step, args.steps, args.warmup, tf)
+    log("timed", w.name)
     counts = out["counts"].cpu().numpy()
-    ms_step = (t1 - t0) * 1e3 / args.steps
     value = ev.n / (ms_step * 1e-3)
-    per_stage = {k: v / max(1, n_calls) for k, v in stage_ms.items()}
-    tuning = ctx.tuning() if tf else None
     dom = max(per_stage, key=per_stage.get)
-    alg_bytes = ALG_BYTES_PER_CLUSTER[dom] * ev.n
-    achieved = alg_bytes / (per_stage[dom] * 1e-3) / 1e9
-    src = {"grid": "paper_1910_12214_amd/csrc/tpc_grid.hip", "neighbours": "paper_1910_12214_amd/csrc/tpc_links.hip",
-           "clean_starts": "paper_1910_12214_amd/csrc/tpc_links.hip",
-           "tracklets": "paper_1910_12214_amd/csrc/tpc_tracklets.hip",
-           "selection": "paper_1910_12214_amd/csrc/tpc_select.hip"}[dom]
-    traffic = traffic_from_profile(src, dom, w.name)
+    achieved = ALG_BYTES_PER_CLUSTER[dom] * ev.n / (per_stage[dom] * 1e-3) / 1e9
     total_alg = sum(ALG_BYTES_PER_CLUSTER.values()) * ev.n
-    line = {
-        "metric": "TPC clusters tracked/s on 1 MI355X, plain vs MLP-pruned, at matched efficiency",
-        "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+    res = {
+        "value": value, "ms_per_step": ms_step,
         "config": {"workload": w.name, "clusters": ev.n, "tracks": int(counts[tpcca.CNT_TRACKS]),
                    "tracklets": int(counts[tpcca.CNT_TRACKLETS]), "input_sha256": ev.sha256()[:16],
-                   "bin_cm": [params["bin_y"], params["bin_z"]],
                    "entry": "tpc_track_timeframe" if tf else "tpc_track_sectors"},
         "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
-        "tiles": tuning,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(STAGE_SRC[dom], dom, w.name),
+                     "alg_bytes_per_cluster": ALG_BYTES_PER_CLUSTER[dom], "stage_ms": per_stage[dom]},
         "path_roofline_frac": total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
-    # Two events in flight: consecutive steps alternate between two contexts on two
-    # streams, so one event's tracklet tail (few long tracklets, most CUs idle) overlaps
-    # the next event's first stages.  Reported beside `value`, which is one event at a time.
+    if tf:
+        res["tiles"] = ctx.tuning()
+    else:
+        res["config"]["bin_cm"] = [params["bin_y"], params["bin_z"]]
+    # Two events in flight: consecutive steps alternate between two contexts on two streams, so
+    # one event's tracklet tail (few long tracklets, most CUs idle) overlaps the next event's
+    # first stages.  Reported beside `value`, which is one event at a time.
     if not tf:
         ctx2 = tpcca.Context(0)
         out2 = ctx2.alloc_tracks(max(1024, ev.n // 8), ev.n)
@@ -229,8 +245,8 @@ def main():
         ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
         h1, h2 = tpcca.tracks_to_host(out), tpcca.tracks_to_host(out2)
         same = bool(np.array_equal(h1["hit_ids"], h2["hit_ids"]) and np.array_equal(h1["n_hits"], h2["n_hits"]))
-        line["two_in_flight"] = {"value": ev.n / (ms_p * 1e-3), "ms_per_step": ms_p, "streams": 2,
-                                 "outputs_equal": same}
+        res["two_in_flight"] = {"value": ev.n / (ms_p * 1e-3), "ms_per_step": ms_p, "streams": 2,
+                                "outputs_equal": same}
         ctx2.close()
         log("timed two in flight")
     # Cluster attachment / adjacency / protection / removal flags (Sec. 4) for the tracks just
@@ -248,21 +264,17 @@ def main():
         fh = fl.cpu().numpy()
         bits = (("attached", 1), ("adjacent", 2), ("protected", 4), ("remove_a", 8), ("remove_b", 16))
         ach = FLAG_BYTES_PER_CLUSTER * ev.n / (ms_f * 1e-3) / 1e9
-        line["cluster_flags"] = {
+        res["cluster_flags"] = {
             "value": ev.n / (ms_f * 1e-3), "unit": "clusters/s", "ms": ms_f,
             "fractions": {k: round(float(np.mean((fh & b) > 0)), 4) for k, b in bits},
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_cluster": FLAG_BYTES_PER_CLUSTER}}
         if "qpt" in (getattr(ev, "exact", None) or {}):  # events only (true momenta kept)
-            line["cluster_flags"]["curve"] = flag_curve(ev, fh, tpcca.tracks_to_host(out))
+            res["cluster_flags"]["curve"] = flag_curve(ev, fh, tpcca.tracks_to_host(out))
         log("timed cluster flags")
-    # learned pruning (scorer trained on one-sector events; tau from its validation seeds)
+    # learned pruning: the scorer trained on events of this workload's generator if there is
+    # one, else the one-sector scorer
     if not args.no_mlp:
-        from paper_1910_12214_amd import scorer as sc
-        from synth import metrics
-
-        # the scorer trained on events of this workload's generator if there is one, else the
-        # one-sector scorer
         ck = sc.DEFAULT_CKPT
         if w.name.startswith("pbpb") and os.path.exists(sc.PBPB_CKPT):
             ck = sc.PBPB_CKPT
@@ -270,10 +282,8 @@ def main():
             ck = sc.PP_CKPT
         params_mlp, tau_trained = sc.load(ck)
         mlp = torch.from_numpy(params_mlp).to(dev)
-        # threshold for this workload: largest tau on a grid whose efficiency on a validation event of
-        # the same workload (another seed) is within 0.5% of the plain finder's
-        import dataclasses
-
+        # threshold for this workload: largest tau on a grid whose efficiency on a validation
+        # event of the same workload (another seed) is within 0.5% of the plain finder's
         wv = dataclasses.replace(w, seed=w.seed + 7919)
         if w.n_collisions > 1:  # a time frame: validate on a tenth of one (same rate and mix)
             wv = synth.scaled(wv, 0.1)
@@ -294,6 +304,7 @@ def main():
                 tau = t_try
         if tau is None:
             tau = -8.0
+        del tv
         log("pruned leg: tau", tau, "on", wv.name)
         out_m = ctx.alloc_tracks(max(1024, ev.n // 8), ev.n)
 
@@ -301,50 +312,54 @@ def main():
             return ctx.track(y, z, r, s, geom, synth.BZ, params, mlp=mlp, tau_logit=tau, out=out_m, stream=stream,
                              timeframe=tf, **kw)
 
-        step_m()
-        for _ in range(args.warmup):
-            step_m(sync_check=False)
-        torch.cuda.synchronize()
-        if not tf:
-            ctx.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step_m(sync_check=False)
-        torch.cuda.synchronize()
-        ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
-        if tf:
-            ctx.profile(True)
-            for _ in range(args.steps):
-                step_m(sync_check=False)
-            torch.cuda.synchronize()
-        ctx.profile(False)
-        st_m, n_m = ctx.profile_read()
-        log("timed pruned")
+        ms_m, st_m = timed_steps(ctx, step_m, args.steps, args.warmup, tf)
+        log("timed pruned", w.name)
         hp = tpcca.tracks_to_host(out)
         hm = tpcca.tracks_to_host(out_m)
         mp = metrics.match(ev.leg, np.concatenate([[0], np.cumsum(hp["n_hits"])]), hp["hit_ids"])
         mm = metrics.match(ev.leg, np.concatenate([[0], np.cumsum(hm["n_hits"])]), hm["hit_ids"])
         cm = hm["counts"]
-        line["plain"] = {"value": value, "efficiency": mp["efficiency"], "fake_rate": mp["fake_rate"],
-                         "clone_rate": mp["clone_rate"], "tracklets": int(counts[tpcca.CNT_TRACKLETS])}
-        line["mlp_pruned"] = {"value": ev.n / (ms_m * 1e-3), "ms_per_step": ms_m, "tau_logit": tau,
-                              "tau_from": f"validation event {wv.name} (seed {wv.seed})",
-                              "trained_on": sc.trained_on(ck),
-                              "stage_ms": {k: round(v / max(1, n_m), 4) for k, v in st_m.items()},
-                              "tau_trained_workload": tau_trained,
-                              "efficiency": mm["efficiency"], "fake_rate": mm["fake_rate"],
-                              "clone_rate": mm["clone_rate"], "tracklets": int(cm[tpcca.CNT_TRACKLETS]),
-                              "pairs": int(cm[tpcca.CNT_PAIRS]), "pairs_kept": int(cm[tpcca.CNT_PAIRS_KEPT]),
-                              "efficiency_loss": mp["efficiency"] - mm["efficiency"],
-                              "matched": bool(mp["efficiency"] - mm["efficiency"] <= 0.005)}
-    if not args.no_cpu_baseline:
+        res["plain"] = {"value": value, "efficiency": mp["efficiency"], "fake_rate": mp["fake_rate"],
+                        "clone_rate": mp["clone_rate"], "tracklets": int(counts[tpcca.CNT_TRACKLETS])}
+        res["mlp_pruned"] = {"value": ev.n / (ms_m * 1e-3), "ms_per_step": ms_m, "tau_logit": tau,
+                             "tau_from": f"validation event {wv.name} (seed {wv.seed})",
+                             "trained_on": sc.trained_on(ck),
+                             "stage_ms": {k: round(v, 4) for k, v in st_m.items()},
+                             "tau_trained_workload": tau_trained,
+                             "efficiency": mm["efficiency"], "fake_rate": mm["fake_rate"],
+                             "clone_rate": mm["clone_rate"], "tracklets": int(cm[tpcca.CNT_TRACKLETS]),
+                             "pairs": int(cm[tpcca.CNT_PAIRS]), "pairs_kept": int(cm[tpcca.CNT_PAIRS_KEPT]),
+                             "efficiency_loss": mp["efficiency"] - mm["efficiency"],
+                             "matched": bool(mp["efficiency"] - mm["efficiency"] <= 0.005)}
+    if primary and not args.no_cpu_baseline:
         log("cpu baseline")
-        cb = cpu_baseline(ev, geom, params, args.cpu_seconds)
-        line["cpu_baseline"] = cb
-        line["gpu_over_oracle_1core"] = value / cb["value"]
-    print(json.dumps(line), flush=True)
+        res["cpu_baseline"] = cpu_baseline(ev, geom, params, args.cpu_seconds)
     ctx.close()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    res = measure(w, args, primary=True)
+    line = {
+        "metric": "TPC clusters tracked/s on 1 MI355X, plain vs MLP-pruned, at matched efficiency",
+        "value": res.pop("value"), "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": res.pop("config"),
+    }
+    line.update(res)
+    if "cpu_baseline" in line:
+        line["gpu_over_oracle_1core"] = line["value"] / line["cpu_baseline"]["value"]
+    if args.event_workload and args.event_workload != args.workload:
+        ev_res = measure(synth.WORKLOADS[args.event_workload], args, primary=False)
+        line["event"] = ev_res
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
