@@ -25,10 +25,10 @@ N_MLP_PARAMS = 5057
 
 def build() -> None:
     """Compile the oracle with gcc (no fast-math, no FMA contraction), and its FMA-contracted twin."""
-    src = os.path.join(_HERE, "tpc_oracle.c")
+    srcs = [os.path.join(_HERE, "tpc_oracle.c"), os.path.join(_HERE, "tpc_codec.c")]
     for path, fl in ((_LIB_PATH, ["-ffp-contract=off"]), (_LIB_FMA_PATH, ["-ffp-contract=fast", "-mfma"])):
         tmp = path + ".tmp"
-        subprocess.check_call(["gcc", "-O2", *fl, "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, src, "-lm",
+        subprocess.check_call(["gcc", "-O2", *fl, "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, *srcs, "-lm",
                                "-lpthread"])
         os.replace(tmp, path)
 

@@ -271,6 +271,26 @@ def generate(w: Workload, want_exact: bool = False, n_threads: int | None = None
     return ev
 
 
+def cluster_properties(ev: Event, seed: int = 0x51CE) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Seeded synthetic charge and widths of every cluster (the generator's clusters carry only
+    positions): total charge in ADC counts (uint16), log-normal around 120 for track clusters and
+    40 for noise, and the widths along y and z in units of 1/64 cm (uint8), around 0.20 cm and
+    0.30 cm, the z width growing with the drift distance 250 - (z mod 250) as diffusion does.
+    Independent of the positions' random stream."""
+    rng = np.random.Generator(np.random.PCG64([seed, ev.workload.seed, ev.n]))
+    n = ev.n
+    noise = ev.particle < 0
+    mu = np.where(noise, np.log(40.0), np.log(120.0))
+    q = np.exp(mu + 0.4 * rng.standard_normal(n))
+    qtot = np.clip(np.rint(q), 1, 65535).astype(np.uint16)
+    drift = 250.0 - np.mod(ev.z.astype(np.float64), 250.0)
+    sy = 0.20 * np.exp(0.15 * rng.standard_normal(n))
+    sz = np.sqrt(0.25 ** 2 + (0.0012 * drift)) * np.exp(0.15 * rng.standard_normal(n))
+    sig_y = np.clip(np.rint(sy * 64.0), 1, 255).astype(np.uint8)
+    sig_z = np.clip(np.rint(sz * 64.0), 1, 255).astype(np.uint8)
+    return qtot, sig_y, sig_z
+
+
 def uniform01(seed: int, n: int) -> np.ndarray:
     """Seeded uniform draws in [0, 1) for host-side sampling decisions (subsampling, batch order,
     initial weights).  numpy's PCG64 is used: these draws never reach a kernel except as inputs."""

@@ -77,12 +77,12 @@ def test_oracle_and_generator_are_clean_under_asan_and_ubsan():
         san = ["gcc", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                "-fno-omit-frame-pointer", "-fno-fast-math", "-fPIC", "-shared"]
         libs = {}
-        for name, src, extra in (("synth", os.path.join(ROOT, "synth", "tpcsynth.c"), []),
-                                 ("oracle", os.path.join(ROOT, "oracle", "tpc_oracle.c"), ["-ffp-contract=off"]),
-                                 ("oracle_fma", os.path.join(ROOT, "oracle", "tpc_oracle.c"),
-                                  ["-ffp-contract=fast", "-mfma"])):
+        osrc = [os.path.join(ROOT, "oracle", "tpc_oracle.c"), os.path.join(ROOT, "oracle", "tpc_codec.c")]
+        for name, src, extra in (("synth", [os.path.join(ROOT, "synth", "tpcsynth.c")], []),
+                                 ("oracle", osrc, ["-ffp-contract=off"]),
+                                 ("oracle_fma", osrc, ["-ffp-contract=fast", "-mfma"])):
             libs[name] = os.path.join(tmp, f"lib{name}_san.so")
-            subprocess.check_call(san + extra + ["-o", libs[name], src, "-lm", "-lpthread"])
+            subprocess.check_call(san + extra + ["-o", libs[name], *src, "-lm", "-lpthread"])
         env = dict(os.environ)
         env["LD_PRELOAD"] = _asan_runtime()
         env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1:abort_on_error=1"
