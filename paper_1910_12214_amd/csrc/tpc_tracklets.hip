@@ -59,25 +59,43 @@ __device__ inline double sqrt_pos(double x) {
     return x == 0.0 ? 0.0 : s;
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate and two Newton-Raphson steps
+// (r <- r (3 - x r^2) / 2); x < 0 gives NaN.
+__device__ inline double rsq_pos(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-0.5 * x, r * r, 1.5);
+    return r * fma(-0.5 * x, r * r, 1.5);
+}
+
 // g(u) = asin(u)/u and g'(u).  Row steps keep |u| = |k L / 2| well below 0.05
 // (0.02 for the lowest momenta), where the Maclaurin series of asin(u)/u to u^12
-// is exact to rounding (the first omitted term is below 1e-18 relative).
+// is exact to rounding (the first omitted term is below 1e-18 relative).  Larger
+// |u| (fit states far from any real track) are first brought below 0.05 by the
+// half-angle identity asin(u) = 2 asin(u / sqrt(2 (1 + sqrt(1 - u^2)))), at most
+// five times for |u| <= 1; |u| > 1 gives NaN, as asin does.
+__device__ inline double asin_series(double u2) {  // asin(u)/u as a series in u^2
+    return 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0 + u2 * (35.0 / 1152.0 +
+           u2 * (63.0 / 2816.0 + u2 * (231.0 / 13312.0))))));
+}
+
 __device__ inline void asin_over(double u, double& g, double& gp) {
+    const double u2 = u * u;
     if (fabs(u) < 0.05) {
-        const double u2 = u * u;
-        g = 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0 + u2 * (35.0 / 1152.0 +
-            u2 * (63.0 / 2816.0 + u2 * (231.0 / 13312.0))))));
+        g = asin_series(u2);
         gp = u * (1.0 / 3.0 + u2 * (3.0 / 10.0 + u2 * (15.0 / 56.0 + u2 * (35.0 / 144.0 +
              u2 * (315.0 / 1408.0 + u2 * (693.0 / 3328.0 + u2 * (1001.0 / 5120.0)))))));
     } else {
-        const double a = asin(u);
-        g = a / u;
-        gp = (u / sqrt(1.0 - u * u) - a) / (u * u);
+        double v = u, m = 1.0;
+        for (int i = 0; i < 8 && fabs(v) >= 0.05; ++i) {
+            v *= rsq_pos(2.0 * (1.0 + sqrt_pos(1.0 - v * v)));
+            m *= 2.0;
+        }
+        const double a = m * v * asin_series(v * v);  // asin(u); NaN for |u| > 1
+        const double iu = rcp(u);
+        g = a * iu;
+        gp = (u * rsq_pos(1.0 - u2) - a) * iu * iu;
     }
 }
-
-// symmetric element (i, j) of the packed lower triangle
-#define CS(i, j) C[((i) >= (j)) ? ((i) * ((i) + 1) / 2 + (j)) : ((j) * ((j) + 1) / 2 + (i))]
 
 // Propagate state and covariance from x0 to x1.  false = |sin phi| reached s_max;
 // then p and C hold meaningless values (the caller ends the pass and discards
@@ -114,26 +132,31 @@ __device__ inline bool propagate(double p[5], double C[15], double x0, double x1
     p[0] += dy;
     p[1] += t * arc;
     p[2] = s1;
-    // G = F C
-    double G[5][5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        G[0][j] = CS(0, j) + a * CS(2, j) + b * CS(4, j);
-        G[1][j] = CS(1, j) + c * CS(2, j) + d * CS(3, j) + e * CS(4, j);
-        G[2][j] = CS(2, j) + f * CS(4, j);
-        G[3][j] = CS(3, j);
-        G[4][j] = CS(4, j);
-    }
-    // C' = G F^T (lower triangle)
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const double r0 = G[i][0] + a * G[i][2] + b * G[i][4];
-        const double r1 = G[i][1] + c * G[i][2] + d * G[i][3] + e * G[i][4];
-        const double r2 = G[i][2] + f * G[i][4];
-        const double rr[5] = {r0, r1, r2, G[i][3], G[i][4]};
-#pragma unroll
-        for (int j = 0; j <= i; ++j) C[i * (i + 1) / 2 + j] = rr[j];
-    }
+    // C' = F C F^T with F = I + {(0,2)=a, (0,4)=b, (1,2)=c, (1,3)=d, (1,4)=e, (2,4)=f}, written
+    // element by element on the packed lower triangle (index i(i+1)/2 + j): rows 3 and 4 of F C
+    // equal those of C, and each new element is formed while the old ones it needs are still there.
+    const double C00 = C[0], C10 = C[1], C11 = C[2], C20 = C[3], C21 = C[4], C22 = C[5];
+    const double C30 = C[6], C31 = C[7], C32 = C[8], C33 = C[9];
+    const double C40 = C[10], C41 = C[11], C42 = C[12], C43 = C[13], C44 = C[14];
+    // rows of N = F C that differ from C (only the columns the products below need)
+    const double n00 = C00 + a * C20 + b * C40, n02 = C20 + a * C22 + b * C42, n04 = C40 + a * C42 + b * C44;
+    const double n10 = C10 + c * C20 + d * C30 + e * C40, n11 = C11 + c * C21 + d * C31 + e * C41;
+    const double n12 = C21 + c * C22 + d * C32 + e * C42, n13 = C31 + c * C32 + d * C33 + e * C43;
+    const double n14 = C41 + c * C42 + d * C43 + e * C44;
+    const double n20 = C20 + f * C40, n21 = C21 + f * C41, n22 = C22 + f * C42, n23 = C32 + f * C43;
+    const double n24 = C42 + f * C44;
+    C[0] = n00 + a * n02 + b * n04;
+    C[1] = n10 + a * n12 + b * n14;
+    C[2] = n11 + c * n12 + d * n13 + e * n14;
+    C[3] = n20 + a * n22 + b * n24;
+    C[4] = n21 + c * n22 + d * n23 + e * n24;
+    C[5] = n22 + f * n24;
+    C[6] = C30 + a * C32 + b * C43;
+    C[7] = C31 + c * C32 + d * C33 + e * C43;
+    C[8] = C32 + f * C43;
+    C[10] = C40 + a * C42 + b * C44;
+    C[11] = C41 + c * C42 + d * C43 + e * C44;
+    C[12] = C42 + f * C44;
     return ok;
 }
 
@@ -269,12 +292,17 @@ __device__ inline RowBins row_bins_lds(const RowTab& rt, int s, int r) {
 
 // Per-lane tracklet state between row steps.
 // Rarely touched per-lane values live in LDS, not registers: pass A's direction
-// and curvature at its outermost hit, and pass B's state at its innermost hit.
+// and curvature at its outermost hit, pass B's state at its innermost hit and its
+// chi2 sum, and the slot chunk being filled.  The register state is kept to what
+// every row step reads, and the x of the state's row is taken from the row table
+// rather than kept, so the kernel fits three waves per SIMD without spills.
 struct Spare {
     double pl[3];      // pass A at its outermost hit: sin phi, dz/ds, q/pT
     float ly, lz;      // that hit's coordinates
     int32_t lpos;      // and grid position
     float pin[5], cin[15];
+    double chi2;       // pass B's chi2 sum
+    int32_t w[8];      // the slot's current aligned 8-entry chunk, stored once complete
 };
 
 // Start of one tracklet, precomputed in processing order (three 16-byte loads).
@@ -290,12 +318,11 @@ struct alignas(16) Seed {
 struct Lane {
     int phase;  // 0 needs work, 1 pass A, 2 pass B, 3 retired
     uint32_t k;
-    int s, r0, r, last, inner, nA, nB, ia, miss, ndf;
-    int32_t next;
-    int32_t pf;  // pass B: position of pass A's hit number ia (loaded one step ahead)
-    int32_t w[8];  // the slot's current aligned 8-entry chunk, stored once complete
+    int s, r0, r, edge, nh, ia, miss;  // edge: last row of pass A, then innermost row of pass B;
+                                       // nh: hits of the current pass (pass B's ndf is 2 (nh - 1))
+    int32_t link;  // pass A: the chain's next hit; pass B: position of pass A's hit number ia
+                   // (loaded one step ahead)
     bool on, fail;
-    double x, chi2;
     double p[5], C[15];
     Spare* sp;
 };
@@ -328,8 +355,8 @@ constexpr int kSlotChunk = 8;
 __device__ inline void slot_flush(const Lane& L, int32_t* slot, int idx, bool wide) {
     if (!wide) return;
     int4* c = (int4*)(slot + (idx & ~(kSlotChunk - 1)));
-    c[0] = make_int4(L.w[0], L.w[1], L.w[2], L.w[3]);
-    c[1] = make_int4(L.w[4], L.w[5], L.w[6], L.w[7]);
+    c[0] = make_int4(L.sp->w[0], L.sp->w[1], L.sp->w[2], L.sp->w[3]);
+    c[1] = make_int4(L.sp->w[4], L.sp->w[5], L.sp->w[6], L.sp->w[7]);
 }
 
 __device__ inline void slot_put(Lane& L, int32_t* slot, int idx, int32_t v, bool wide, bool last_in_chunk) {
@@ -337,9 +364,7 @@ __device__ inline void slot_put(Lane& L, int32_t* slot, int idx, int32_t v, bool
         slot[idx] = v;
         return;
     }
-    const int q = idx & (kSlotChunk - 1);
-#pragma unroll
-    for (int i = 0; i < kSlotChunk; ++i) L.w[i] = q == i ? v : L.w[i];
+    L.sp->w[idx & (kSlotChunk - 1)] = v;
     if (last_in_chunk) slot_flush(L, slot, idx, true);
 }
 
@@ -356,14 +381,13 @@ __device__ inline void start_pass_a(Lane& L, const Seed& sd, const GridDesc& g, 
     L.p[4] = 0.0;
     c0_init(L.C, kp);
     slot_put(L, o.hits + (size_t)sd.k * R, 0, sd.p0, (R & (kSlotChunk - 1)) == 0, false);
-    L.nA = 1;
-    L.last = L.r0;
+    L.nh = 1;
+    L.edge = L.r0;
     save_dir(L, sd.y0, sd.z0, sd.p0);
-    L.next = sd.p1;
+    L.link = sd.p1;
     L.on = true;
     L.fail = false;
     L.miss = 0;
-    L.x = rt.x[L.r0];
     L.r = L.r0 + 1;
     L.phase = 1;
 }
@@ -380,33 +404,30 @@ __device__ inline void start_pass_b(Lane& L, const GridDesc& g, const RowTab& rt
     L.p[4] = L.sp->pl[2];
     c0_init(L.C, kp);
     const bool wide = (R & (kSlotChunk - 1)) == 0;
-    if ((L.nA & (kSlotChunk - 1)) != 0) slot_flush(L, slot, L.nA - 1, wide);  // pass A's last, partial chunk
+    if ((L.nh & (kSlotChunk - 1)) != 0) slot_flush(L, slot, L.nh - 1, wide);  // pass A's last, partial chunk
     slot_put(L, slot, R - 1, pb, wide, ((R - 1) & (kSlotChunk - 1)) == 0);
-    L.nB = 1;
-    L.inner = L.last;
-    L.chi2 = 0.0;
-    L.ndf = 0;
+    L.ia = L.nh - 2;
+    L.nh = 1;
+    L.sp->chi2 = 0.0;
     save_inner(L);
-    L.x = rt.x[L.last];
     L.miss = 0;
-    L.ia = L.nA - 2;
-    L.pf = L.ia >= 0 ? slot[L.ia] : -1;
-    L.r = L.last - 1;
+    L.link = L.ia >= 0 ? slot[L.ia] : -1;
+    L.r = L.edge - 1;
     L.phase = 2;
 }
 
 // Writes the tracklet's outputs; returns bit0 = valid, bit1 = fit failure.
 __device__ inline uint32_t finish(Lane& L, int R, const KParams& kp, const TrackletOut& o) {
     const bool fail = L.fail;
-    if (L.phase == 2 && !fail && ((R - L.nB) & (kSlotChunk - 1)) != 0)
-        slot_flush(L, o.hits + (size_t)L.k * R, R - L.nB, (R & (kSlotChunk - 1)) == 0);
-    const int nB = fail ? 0 : L.nB;
+    if (L.phase == 2 && !fail && ((R - L.nh) & (kSlotChunk - 1)) != 0)
+        slot_flush(L, o.hits + (size_t)L.k * R, R - L.nh, (R & (kSlotChunk - 1)) == 0);
+    const int nB = fail ? 0 : L.nh;
     const bool valid = !fail && nB >= kp.n_min_tl;
     const uint32_t k = L.k;
     o.nhits[k] = nB;
-    o.chi2[k] = fail ? 0.f : (float)L.chi2;
-    o.ndf[k] = fail ? 0 : L.ndf;
-    o.row_ref[k] = L.phase == 2 ? L.inner : L.last;
+    o.chi2[k] = fail ? 0.f : (float)L.sp->chi2;
+    o.ndf[k] = fail ? 0 : 2 * (nB - 1);
+    o.row_ref[k] = L.edge;
     o.flags[k] = (valid ? 1u : 0u) | (fail ? 2u : 0u);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -447,22 +468,23 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const 
     // entry of the pass-A hit after it.
     const double xr = rt.x[rc];
     const RowBins rb = row_bins_lds(rt, L.s, rc);
-    const int32_t cand = A ? (L.on ? L.next : -1) : ((r >= L.r0 && L.ia >= 0) ? L.pf : -1);
+    const int32_t cand = A ? (L.on ? L.link : -1) : ((r >= L.r0 && L.ia >= 0) ? L.link : -1);
     const int32_t cc = cand < 0 ? 0 : cand;
     const Hit hc = hits[cc];
     const int32_t cand_up = upc[cc];
     const int ia1 = L.ia < 1 ? 0 : (L.ia > R ? R - 1 : L.ia - 1);
     const int32_t pf_next = A ? -1 : slot[ia1];  // pass A lanes load nothing (no slot lines into L2)
-    end = end || !propagate(L.p, L.C, L.x, xr, kp);
-    L.x = xr;
+    // x of the row the state is at: the row before this one in the pass's direction
+    const double x0 = rt.x[A ? r - 1 : r + 1];
+    end = end || !propagate(L.p, L.C, x0, xr, kp);
     end = end || fabs(L.p[0]) > xr * kp.tan_half + kp.edge;
     const bool on_row = (cand >= 0) & ((int)(hc.rs % (uint32_t)R) == r);
     const bool link = A & L.on & on_row & (chi2_of(L.p, L.C, hc.y, hc.z, kp) <= kp.fol_cut);
     const bool reused = !A & on_row;
     L.on = A ? link : L.on;
-    L.next = link ? cand_up : L.next;
+    L.link = link ? cand_up : L.link;
     L.ia = reused ? L.ia - 1 : L.ia;
-    L.pf = reused ? pf_next : L.pf;
+    L.link = reused ? pf_next : L.link;
     int32_t acc = (link || reused) ? cand : -1;
     float hy = hc.y, hz = hc.z;
     if (!end && (A ? !link : r < L.r0)) acc = search_row(g, kp, hits, bin_off, rb, L.p, L.C, hy, hz);
@@ -478,15 +500,12 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const 
     if (good) {
         // pass A appends from the front of the slot, pass B from the back; the saved
         // direction only matters in pass A and the saved inner state only in pass B
-        const int idx = A ? L.nA : R - 1 - L.nB;
+        const int idx = A ? L.nh : R - 1 - L.nh;
         slot_put(L, slot, idx, acc, (R & (kSlotChunk - 1)) == 0,
                  A ? (idx & (kSlotChunk - 1)) == kSlotChunk - 1 : (idx & (kSlotChunk - 1)) == 0);
-        L.nA += A ? 1 : 0;
-        L.nB += A ? 0 : 1;
-        L.last = A ? r : L.last;
-        L.inner = A ? L.inner : r;
-        L.chi2 += A ? 0.0 : c2;
-        L.ndf += A ? 0 : 2;
+        L.nh += 1;
+        L.edge = r;
+        if (!A) L.sp->chi2 += c2;
         save_dir(L, hy, hz, acc);
         save_inner(L);
     }
@@ -529,10 +548,12 @@ __global__ __launch_bounds__(kBlock) void k_seeds(GridDesc g, const Hit* __restr
 // dispatched to XCD b mod 8 and drains that XCD's slice first, then steals from
 // the others, so the tracklets an XCD builds at any moment read the hits of one
 // sector and a narrow z range, which its L2 holds.  A wave reserves 64 * chunk
-// entries per atomic and hands them to its idle lanes by rank.  A lane that
-// receives an entry issues the loads of its seed record before the row step of
-// the busy lanes and starts pass A after it, so the load latency hides behind
-// that step instead of stalling the wave.
+// entries per atomic and hands them to its idle lanes by rank; a lane that
+// receives an entry starts pass A after the row step of the busy lanes.  With two
+// waves per SIMD its seed record is loaded before that step, so the load latency
+// hides behind it; with three it is loaded after the step: held across the step,
+// the record's twelve registers were what kept the kernel from three waves per
+// SIMD without spills, and three waves hide the load behind each other's work.
 template <int WAVES>
 __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES))) void k_tracklets(
     GridDesc g, KParams kp, const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
@@ -559,12 +580,11 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
     Lane L;
     L.phase = 0;  // 0 idle, 1 pass A, 2 pass B, 3 retired, 4 seed loading
     L.k = 0;
-    L.s = L.r0 = L.r = L.last = L.inner = L.nA = L.nB = L.ia = L.miss = L.ndf = 0;
-    L.next = L.pf = -1;
-    for (int i = 0; i < kSlotChunk; ++i) L.w[i] = -1;
+    L.s = L.r0 = L.r = L.edge = L.nh = L.ia = L.miss = 0;
+    L.link = -1;
     L.on = L.fail = false;
-    L.x = L.chi2 = 0.0;
     L.sp = &spare[threadIdx.x];
+    for (int i = 0; i < kSlotChunk; ++i) L.sp->w[i] = -1;
     uint32_t plo = 0, phi = 0;  // wave-uniform: reserved, not yet handed out
     uint32_t my_j = 0;
     int cur = 0;                // slices this wave has found empty (wave-uniform)
@@ -598,7 +618,7 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
         if (L.phase == 0) L.phase = 3;  // every slice is drained
         if (!__ballot(L.phase == 1 || L.phase == 2 || L.phase == 4)) break;
         Seed sd;
-        if (L.phase == 4) sd = seeds[my_j];
+        if (WAVES == 2 && L.phase == 4) sd = seeds[my_j];  // two waves: the load hides behind the step
         if ((L.phase == 1 || L.phase == 2) && step(L, g, rt, kp, hits, bin_off, upc, o)) {
             if (L.phase == 1 && !L.fail) {
                 start_pass_b(L, g, rt, kp, o);
@@ -608,7 +628,10 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
                 n_fail += (f >> 1) & 1u;
             }
         }
-        if (L.phase == 4) start_pass_a(L, sd, g, rt, kp, o);
+        if (L.phase == 4) {
+            if (WAVES != 2) sd = seeds[my_j];
+            start_pass_a(L, sd, g, rt, kp, o);
+        }
     }
     __shared__ uint32_t sv[kTlBlock / 64], sf[kTlBlock / 64];
     const uint32_t wv = wave_sum(n_valid), wf = wave_sum(n_fail);
@@ -640,10 +663,9 @@ void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, cons
     const unsigned nb = (unsigned)((t_max + kBlock - 1) / kBlock > 0 ? (t_max + kBlock - 1) / kBlock : 1);
     k_seeds<<<nb, kBlock, 0, s>>>(g, hits, upc, starts, proc, counters, sd);
     grid_blocks = (grid_blocks + kXcd - 1) / kXcd * kXcd;
-    // occupancy variants: 2 waves per SIMD keeps the whole state in registers, 3 and 4 spill some of it
-    if (waves >= 4)
-        k_tracklets<4><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
-    else if (waves == 3)
+    // occupancy variants: 3 waves per SIMD (168 registers, no spills) or 2 (more registers for the
+    // compiler's schedule)
+    if (waves >= 3)
         k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
     else
         k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
