@@ -134,8 +134,35 @@ def training_set(ctx, workloads=None, max_triplets=MAX_TRIPLETS, subsample_seed=
     return F, Y
 
 
-def train(ctx, F, Y, epochs=5, batch=4096, lr=1e-3, seed=5, log=None):
-    """Adam training on the GPU; returns (params as numpy float32, per-epoch mean loss)."""
+STATE_KEYS = ("params", "m", "v", "step", "epoch", "loss_per_epoch", "seed", "batch", "lr", "n_rows")
+
+
+def save_state(path: str, **st) -> None:
+    """Write a training state (master parameters, Adam moments, step and epoch counters, the
+    settings that fix the batch order) atomically: a crash leaves the previous state intact."""
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, **{k: np.asarray(st[k]) for k in STATE_KEYS})
+    os.replace(tmp, path)
+
+
+def load_state(path: str) -> dict:
+    ck = np.load(path)  # plain arrays only (no pickled objects)
+    st = {k: ck[k] for k in STATE_KEYS}
+    for k in ("step", "epoch", "seed", "batch", "n_rows"):
+        st[k] = int(st[k])
+    st["lr"] = float(st["lr"])
+    st["loss_per_epoch"] = [float(x) for x in np.atleast_1d(st["loss_per_epoch"])]
+    return st
+
+
+def train(ctx, F, Y, epochs=5, batch=4096, lr=1e-3, seed=5, log=None, state_path=None):
+    """Adam training on the GPU; returns (params as numpy float32, per-epoch mean loss).
+
+    With ``state_path`` the state is saved after every epoch, and a state already there is resumed
+    (same rows, batch, learning rate and seed required): the epochs it holds are skipped and the
+    run continues with identical batches, so an interrupted run ends with the same parameters as
+    an uninterrupted one."""
     import torch
 
     import synth
@@ -147,13 +174,29 @@ def train(ctx, F, Y, epochs=5, batch=4096, lr=1e-3, seed=5, log=None):
     steps = n // batch
     hist = []
     step0 = 0
-    for ep in range(epochs):
+    ep0 = 0
+    if state_path and os.path.exists(state_path):
+        st = load_state(state_path)
+        if (st["n_rows"], st["batch"], st["seed"]) != (n, batch, seed) or st["lr"] != float(lr):
+            raise ValueError(f"{state_path}: saved for rows/batch/seed/lr {st['n_rows']}/{st['batch']}/"
+                             f"{st['seed']}/{st['lr']}, not {n}/{batch}/{seed}/{lr}")
+        params = _dev(st["params"].astype(np.float32))
+        m = _dev(st["m"].astype(np.float32))
+        v = _dev(st["v"].astype(np.float32))
+        step0, ep0, hist = st["step"], st["epoch"], list(st["loss_per_epoch"])
+        if log:
+            log(f"resumed {state_path} after epoch {ep0} (Adam step {step0})")
+    for ep in range(ep0, epochs):
         order = synth.permutation(seed * 1000 + ep, n)[: steps * batch].astype(np.int32)
         loss = ctx.mlp_train(F, Y, _dev(order), params, m, v, batch=batch, n_steps=steps, step0=step0, lr=lr)
         step0 += steps
         hist.append(float(loss.mean().item()))
         if log:
             log(f"epoch {ep}: mean loss {hist[-1]:.5f} ({steps} steps)")
+        if state_path:
+            save_state(state_path, params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(),
+                       step=step0, epoch=ep + 1, loss_per_epoch=np.array(hist), seed=seed, batch=batch, lr=lr,
+                       n_rows=n)
     return params.cpu().numpy(), hist
 
 
@@ -225,6 +268,8 @@ def main(argv=None):
     t.add_argument("--out", default=None, help="checkpoint (default: the set's file in the package)")
     t.add_argument("--epochs", type=int, default=5)
     t.add_argument("--report", default=None, help="write the training/validation/test summary as JSON")
+    t.add_argument("--state", default=None,
+                   help="training state file: saved after every epoch, resumed if present")
     e = sub.add_parser("eval")
     e.add_argument("--ckpt", default=DEFAULT_CKPT)
     args = ap.parse_args(argv)
@@ -244,7 +289,7 @@ def main(argv=None):
         log(f"training set: {F.shape[0]} triplets from {len(train_w)} events, positives "
             f"{float(Y.float().mean()):.3f} ({time.perf_counter() - t0:.1f} s)")
         t0 = time.perf_counter()
-        params, hist = train(ctx, F, Y, epochs=args.epochs, log=log)
+        params, hist = train(ctx, F, Y, epochs=args.epochs, log=log, state_path=args.state)
         log(f"trained in {time.perf_counter() - t0:.2f} s")
         tau, plain_val = choose_tau(ctx, params, va(), log=log)
         log(f"tau = {tau}")

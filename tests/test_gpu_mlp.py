@@ -280,3 +280,24 @@ def test_full_event_pruned_sampled_sectors(ctx):
     say(f"[mlp] full event, tau {tau}, sectors {sectors}: {rep.line()} pairs={c[tpcca.CNT_PAIRS]} "
         f"kept={c[tpcca.CNT_PAIRS_KEPT]} overflow groups={c[tpcca.CNT_NB_OVERFLOW]}")
     assert rep["tracks_compared"] > 500
+
+
+def test_interrupted_training_resumes_to_the_same_parameters(ctx, tmp_path):
+    """Two epochs in one run, and one epoch, a saved state, then a second run that resumes it for the
+    second epoch: identical parameters and losses (deterministic kernels, same batch order)."""
+    from paper_1910_12214_amd import scorer
+
+    rng = np.random.default_rng(17)
+    N = 24576
+    X = rng.normal(0, 1.0, (N, 12)).astype(np.float32)
+    y = ((X @ rng.normal(0, 1, 12) + 0.3 * rng.normal(size=N)) > 0).astype(np.uint8)
+    F, Y = dev(X), dev(y)
+    p_full, h_full = scorer.train(ctx, F, Y, epochs=2, batch=2048, lr=2e-3, seed=9)
+    state = str(tmp_path / "state.npz")
+    p_one, h_one = scorer.train(ctx, F, Y, epochs=1, batch=2048, lr=2e-3, seed=9, state_path=state)
+    assert scorer.load_state(state)["epoch"] == 1 and not np.array_equal(p_one, p_full)
+    p_res, h_res = scorer.train(ctx, F, Y, epochs=2, batch=2048, lr=2e-3, seed=9, state_path=state)
+    assert np.array_equal(p_res, p_full) and h_res == h_full
+    assert scorer.load_state(state)["epoch"] == 2
+    with pytest.raises(ValueError):  # a state saved for other settings is refused
+        scorer.train(ctx, F, Y, epochs=3, batch=1024, lr=2e-3, seed=9, state_path=state)

@@ -1,8 +1,10 @@
 """Host-side parts of the learned scorer driver (no GPU)."""
 import math
+import os
 
 import numpy as np
 
+from paper_1910_12214_amd import scorer
 from synth import metrics
 
 
@@ -43,3 +45,23 @@ def test_pp_checkpoint_is_present_and_well_formed():
     p, tau = scorer.load(scorer.PP_CKPT)
     assert p.shape == (5057,) and p.dtype == np.float32 and np.isfinite(p).all() and np.isfinite(tau)
     assert "pp-like" in scorer.trained_on(scorer.PP_CKPT)
+
+
+def test_training_state_round_trip(tmp_path):
+    """A saved training state reads back exactly, holds plain arrays only, and is replaced
+    atomically (no temporary file left behind)."""
+    rng = np.random.default_rng(3)
+    st = dict(params=rng.normal(size=5057).astype(np.float32), m=rng.normal(size=5057).astype(np.float32),
+              v=rng.random(5057).astype(np.float32), step=1234, epoch=3, loss_per_epoch=np.array([0.5, 0.4, 0.3]),
+              seed=5, batch=4096, lr=1e-3, n_rows=5 * 10 ** 6)
+    path = str(tmp_path / "state.npz")
+    scorer.save_state(path, **st)
+    scorer.save_state(path, **dict(st, epoch=4))
+    assert not os.path.exists(path + ".tmp")
+    got = scorer.load_state(path)
+    for k in ("params", "m", "v"):
+        assert np.array_equal(got[k], st[k]) and got[k].dtype == np.float32
+    assert (got["step"], got["epoch"], got["seed"], got["batch"], got["n_rows"]) == (1234, 4, 5, 4096, 5 * 10 ** 6)
+    assert got["lr"] == 1e-3 and got["loss_per_epoch"] == [0.5, 0.4, 0.3]
+    with np.load(path) as z:  # readable without pickle
+        assert set(z.files) == set(scorer.STATE_KEYS)
