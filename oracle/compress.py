@@ -7,7 +7,8 @@ the integer and codec parts are in ``tpc_codec.c`` (plain C), the rest is numpy.
 Readings (the paper gives the steps, not their constants):
 * Step 2.  Positions become integers in quanta of sigma/8 of the cluster resolution
   (Q_Y = 0.0075 cm, Q_Z = 0.0125 cm): yq = rint(y * (1 / Q_Y)) in FP64 from the FP32 coordinate,
-  ties to even, the same for z.  Charge and the two widths keep the leading one and the n bits
+  ties to even, the same for z.  Clusters with row or sector out of range, or |yq| or |zq| >= 2^29
+  (differences must fit 31 bits), are skipped and counted.  Charge and the two widths keep the leading one and the n bits
   after it, rounded (n = 4 for the charge, 3 for the widths); stored as (e << (n+1)) | (v >> e).
 * Step 3.  A track's clusters (the tracker's hit lists, ascending rows) are stored as the row
   step from the previous hit (from the track's reference row for the first) and the residuals of
@@ -36,6 +37,7 @@ ALPHABET, ESC = 4096, 4095
 PROB_BITS, BLOCK = 14, 4096
 STREAMS = ("a_drow", "a_ry", "a_rz", "u_n", "u_dz", "u_dy", "q", "sy", "sz")
 TIE_ABS = 1e-6  # a prediction within this many quanta of a rounding boundary is flagged
+Q_LIMIT = 2.0 ** 29  # clusters (and predictions) at |yq| or |zq| >= 2^29 are not representable
 
 _lib = None
 
@@ -141,12 +143,26 @@ def compress(y, z, row, sector, qtot, sig_y, sig_z, geometry: dict, bz: float, t
     row = np.asarray(row, dtype=np.int64)
     sector = np.asarray(sector, dtype=np.int64)
     n = len(row)
-    valid = (row < R) & (sector < S)
-    yq, zq = quantise(y, INV_QY), quantise(z, INV_QZ)
-    # clusters on tracks, in track order
+    with np.errstate(invalid="ignore"):
+        fy = np.rint(np.asarray(y, dtype=np.float32).astype(np.float64) * INV_QY)
+        fz = np.rint(np.asarray(z, dtype=np.float32).astype(np.float64) * INV_QZ)
+        valid = (row < R) & (sector < S) & (np.abs(fy) < Q_LIMIT) & (np.abs(fz) < Q_LIMIT)
+    yq = np.where(valid, fy, 0).astype(np.int64)
+    zq = np.where(valid, fz, 0).astype(np.int64)
+    # clusters on tracks, in track order; a track with an unusable entry (offset beyond the hit
+    # list, id out of range or of a skipped cluster, sector or reference row out of range) is
+    # left out and its clusters count as others
     off = np.asarray(tracks["hit_offset"], dtype=np.int64)
-    nh = np.asarray(tracks["n_hits"], dtype=np.int64)
+    nh = np.asarray(tracks["n_hits"], dtype=np.int64).copy()
     hid = np.asarray(tracks["hit_ids"], dtype=np.int64)
+    for k in range(len(nh)):
+        ok = off[k] >= 0 and nh[k] >= 0 and off[k] + nh[k] <= len(hid) and 0 <= tracks["sector"][k] < S and \
+            0 <= tracks["row_ref"][k] < R
+        if ok:
+            ids = hid[off[k]:off[k] + nh[k]]
+            ok = bool(np.all((ids >= 0) & (ids < n))) and bool(np.all(valid[np.clip(ids, 0, max(n - 1, 0))]))
+        if not ok:
+            nh[k] = 0
     n_trk = len(nh)
     t_of = np.repeat(np.arange(n_trk), nh)
     a_ids = np.concatenate([hid[off[k]:off[k] + nh[k]] for k in range(n_trk)]) if n_trk else np.zeros(0, np.int64)
@@ -158,6 +174,9 @@ def compress(y, z, row, sector, qtot, sig_y, sig_z, geometry: dict, bz: float, t
     rref = np.asarray(tracks["row_ref"], dtype=np.int64)[t_of]
     a_row = row[a_ids]
     yp, zp, fail = predict(st, xref, row_x[a_row].astype(np.float64), bz, s_max)
+    with np.errstate(invalid="ignore"):
+        fail |= ~(np.abs(np.rint(yp * INV_QY)) < Q_LIMIT) | ~(np.abs(np.rint(zp * INV_QZ)) < Q_LIMIT)
+    yp, zp = np.where(fail, 0.0, yp), np.where(fail, 0.0, zp)
     py, pz = np.rint(yp * INV_QY).astype(np.int64), np.rint(zp * INV_QZ).astype(np.int64)
     tie = (np.abs(np.abs(yp * INV_QY - np.floor(yp * INV_QY)) - 0.5) < TIE_ABS) | \
           (np.abs(np.abs(zp * INV_QZ - np.floor(zp * INV_QZ)) - 0.5) < TIE_ABS)
@@ -191,7 +210,7 @@ def compress(y, z, row, sector, qtot, sig_y, sig_z, geometry: dict, bz: float, t
     streams, escapes = {}, {}
     for k in STREAMS:
         streams[k], escapes[k] = _to_symbols(vals[k])
-    return {"streams": streams, "escapes": escapes, "order": order, "n_attached": len(a_ids),
+    return {"streams": streams, "escapes": escapes, "order": order, "n_attached": len(a_ids), "track_len": nh,
             "n_unattached": len(u_ids), "n_skipped": int((~valid).sum()), "tie": np.nonzero(tie)[0],
             "pred_fail": int(fail.sum()), "yq": yq, "zq": zq}
 
@@ -206,7 +225,7 @@ def decompress(streams: dict, escapes: dict, tracks: dict, geometry: dict, bz: f
         s[s == ESC] = np.asarray(escapes[k], dtype=np.int64)
         return s
 
-    nh = np.asarray(tracks["n_hits"], dtype=np.int64)
+    nh = np.asarray(tracks.get("track_len", tracks["n_hits"]), dtype=np.int64)
     drow, ry, rz = unzigzag(values("a_drow")), unzigzag(values("a_ry")), unzigzag(values("a_rz"))
     st = np.asarray(tracks["state"], dtype=np.float32).reshape(-1, 5)
     out_s, out_r, out_y, out_z = [], [], [], []
@@ -217,7 +236,9 @@ def decompress(streams: dict, escapes: dict, tracks: dict, geometry: dict, bz: f
         for j in range(int(nh[k])):
             r = r + int(drow[i])
             yp, zp, fl = predict(st[k:k + 1].astype(np.float64), [float(np.float32(tracks["x_ref"][k]))],
-                                 [float(row_x[r])], bz, s_max)
+                                 [float(row_x[min(max(r, 0), R - 1)])], bz, s_max)
+            with np.errstate(invalid="ignore"):
+                fl = fl | ~(np.abs(np.rint(yp * INV_QY)) < Q_LIMIT) | ~(np.abs(np.rint(zp * INV_QZ)) < Q_LIMIT)
             if not fl[0]:
                 py, pz = int(np.rint(yp[0] * INV_QY)), int(np.rint(zp[0] * INV_QZ))
             yq, zq = py + int(ry[i]), pz + int(rz[i])
