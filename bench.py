@@ -26,6 +26,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # 16-byte hit records, each stage reading its inputs and writing its outputs once).
 ALG_BYTES_PER_CLUSTER = {"grid": 32.0, "neighbours": 32.0, "clean_starts": 24.0, "tracklets": 31.0,
                          "selection": 34.0}
+# Cluster compression (Sec. 4, steps 2-4), minimum traffic per cluster: the cluster's position,
+# row, sector, charge and widths read (14 B), its quantised position written and read (16 B), its
+# five symbols written as values and read back (40 B), written as symbols and read by the histogram
+# and the coder (30 B), and about 4 coded bytes written: 104 B.
+CMP_BYTES_PER_CLUSTER = 104.0
 # Cluster flags (Sec. 4): the grid build (32 B per cluster) plus, per cluster, its record read by
 # the tube walk (16 B), its key written and read (16 B), two byte arrays written and read (4 B)
 # and the flag byte written: 69 B per cluster at minimum.
@@ -74,6 +79,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
     ap.add_argument("--no-flags", action="store_true", help="skip the cluster-flag measurement")
+    ap.add_argument("--no-compress", action="store_true", help="skip the cluster-compression measurement")
     ap.add_argument("--sector-path", action="store_true", help="time frames through tpc_track_sectors")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     return ap.parse_args()
@@ -167,6 +173,57 @@ def timed_steps(ctx, step, steps: int, warmup: int, graph: bool):
     ctx.profile(False)
     stage_ms, n_calls = ctx.profile_read()
     return ms, {k: v / max(1, n_calls) for k, v in stage_ms.items()}
+
+
+def measure_compression(ctx, ev, ten, geom, params, trk, stream, steps: int) -> dict:
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1910_12214_amd import tpcca
+
+    q, sy, sz = synth.cluster_properties(ev)
+    props = [torch.from_numpy(a).to(ten[0].device) for a in (q.view(np.int16), sy, sz)]
+    comp = ctx.compress(*ten, *props, geom, synth.BZ, trk, params, stream=stream)  # sizes scratch, checks capacity
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.compress(*ten, *props, geom, synth.BZ, trk, params, out=comp, stream=stream, sync_check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bits = ctx.compress_sizes(comp)
+    cnt = comp["counts"].cpu().numpy()
+    tot = cnt[tpcca.N_CSTREAMS * tpcca.CSC_N:]
+    n_esc = int(sum(cnt[s * tpcca.CSC_N + 1] for s in range(tpcca.N_CSTREAMS)))
+    n_blk = int(sum(cnt[s * tpcca.CSC_N + 3] for s in range(tpcca.N_CSTREAMS)))
+    freq = comp["freq"].cpu().numpy().reshape(tpcca.N_CSTREAMS, -1)
+    n_trk = int(trk["counts"][tpcca.CNT_TRACKS].item())
+    # side information: escapes (4 B), track headers (sector, row, hits, 5 FP32: 24 B), bytes per
+    # block (4 B), frequency tables (4 B per present symbol)
+    side = 4 * n_esc + 24 * n_trk + 4 * n_blk + 4 * int((freq > 0).sum())
+    ans_b = bits[:, 2].sum() / 8 + side
+    huf_b = bits[:, 1].sum() / 8 + side
+    raw = 14 * ev.n
+    # decoder: once, for the time and a check that every cluster comes back
+    torch.cuda.synchronize()
+    d0 = time.perf_counter()
+    d = ctx.decompress(comp, geom, synth.BZ, trk, params)
+    torch.cuda.synchronize()
+    ms_d = (time.perf_counter() - d0) * 1e3
+    n_all = int(tot[tpcca.CST_ATTACHED] + tot[tpcca.CST_UNATTACHED])
+    order = comp["order"][:n_all].cpu().numpy()
+    yq = np.rint(ev.y[order].astype(np.float64) * (1.0 / 0.0075)).astype(np.int64)
+    ok = bool(d["n"] == n_all and np.array_equal(d["yq"][:n_all].cpu().numpy(), yq))
+    ach = CMP_BYTES_PER_CLUSTER * ev.n / (ms * 1e-3) / 1e9
+    return {"value": ev.n / (ms * 1e-3), "unit": "clusters/s", "ms": ms, "decode_ms_once": ms_d,
+            "decoded_equal": ok, "on_tracks": int(tot[tpcca.CST_ATTACHED]), "others": int(tot[tpcca.CST_UNATTACHED]),
+            "raw_bytes": raw, "ans_bytes": ans_b, "huffman_bytes": huf_b, "entropy_bytes": bits[:, 0].sum() / 8 + side,
+            "factor_ans": raw / ans_b, "ans_gain_over_huffman": 1.0 - ans_b / huf_b,
+            "bits_per_stream": {n: [round(float(v), 1) for v in bits[i]] for i, n in enumerate(tpcca.CSTREAMS)},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_cluster": CMP_BYTES_PER_CLUSTER}}
 
 
 def measure(w, args, primary: bool):
@@ -272,6 +329,11 @@ def measure(w, args, primary: bool):
         if "qpt" in (getattr(ev, "exact", None) or {}):  # events only (true momenta kept)
             res["cluster_flags"]["curve"] = flag_curve(ev, fh, tpcca.tracks_to_host(out))
         log("timed cluster flags")
+    # Cluster compression of the clusters with the tracks just found (Sec. 4, steps 2-4): timed on
+    # its own, sizes per stream (entropy, Huffman, range ANS) and the decoder checked once.
+    if not args.no_compress:
+        res["compression"] = measure_compression(ctx, ev, (y, z, r, s), geom, params, out, stream, args.steps)
+        log("timed compression")
     # learned pruning: the scorer trained on events of this workload's generator if there is
     # one, else the one-sector scorer
     if not args.no_mlp:

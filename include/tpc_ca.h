@@ -191,11 +191,17 @@ typedef struct {
     float bin_y, bin_z;
     int32_t tracklet_chunk;  /* tracklets taken per queue pop (per wave) */
     int32_t blocks_per_cu;   /* persistent grid size / number of CUs */
-    int32_t waves_per_simd;  /* tracklet kernel occupancy variant: 2 (no spills), 3 or 4 */
+    int32_t waves_per_simd;  /* tracklet kernel occupancy variant: 2 or 3 waves per SIMD */
     float best_ms;           /* autotune measurement of the chosen candidate */
     int32_t n_candidates;
 } tpc_tuning_t;
 int tpc_timeframe_tuning(tpc_ctx_t* ctx, tpc_tuning_t* out);
+/* Persist the time-frame tiles across processes: with a file path (host string), every shape the
+ * context tunes is appended to that text file, and a shape found there (same shape, device and
+ * library build) is used without tuning.  NULL or "" turns the cache off.  An unreadable file or a
+ * malformed line only means that the shape is tuned again; write failures are ignored.  The
+ * context also remembers every shape it tuned, so returning to an earlier shape never re-tunes. */
+int tpc_timeframe_tune_cache(tpc_ctx_t* ctx, const char* path);
 /* Force the time-frame tiles (disables tuning) or, with NULL, re-enable tuning. */
 int tpc_timeframe_set_tuning(tpc_ctx_t* ctx, const tpc_tuning_t* tiles);
 
@@ -272,6 +278,100 @@ typedef struct {
  * loss[n_steps] (device) receives each step's loss. */
 int tpc_mlp_train(tpc_ctx_t* ctx, const float* feats, const uint8_t* labels, const int32_t* order,
                   const tpc_train_cfg_t* cfg, float* mlp, float* m, float* v, float* loss, void* stream);
+
+/* ---- cluster compression (Sec. 4, TPC data reduction, steps 2-4) ----
+ * Step 2: positions become integers in fixed quanta (yq = rint(y / q_y), zq likewise, FP64 from
+ * the FP32 coordinates, ties to even); the charge and the two widths keep their leading one and
+ * the n bits after it, rounded to nearest (half up), coded as (e << (n+1)) | (v >> e).
+ * Step 3: the clusters of tracks (a track set as the tracking calls write it: hits in ascending
+ * rows) are stored as the row step from the previous hit (from row_ref for the first) and the
+ * residuals of their quantised positions to the quantised prediction of the track's helix,
+ * carried in closed form from its reference state to the hit's row (the previous hit's position
+ * where that fails).  Every other cluster is stored per (sector, row) in ascending (zq, yq,
+ * cluster id): the number of such clusters of each row, and per cluster the differences of zq and
+ * yq to the previous one of its row (the first: zq and yq themselves).  Charges and widths follow
+ * the cluster order of the streams (track clusters first, in track order).
+ * Step 4: each stream is coded by range ANS (31-bit state, byte output, 14-bit probabilities,
+ * blocks of 4096 symbols).  Signed values are zigzag-mapped (0, -1, 1, ... -> 0, 1, 2, ...);
+ * values >= 4095 are the escape symbol 4095 and go raw to the stream's escape list. */
+enum {
+    TPC_CS_A_DROW = 0, /* track clusters: row step */
+    TPC_CS_A_RY,       /* track clusters: y residual (zigzag) */
+    TPC_CS_A_RZ,       /* track clusters: z residual (zigzag) */
+    TPC_CS_U_N,        /* other clusters per (sector, row): count (one symbol per row, all rows) */
+    TPC_CS_U_DZ,       /* other clusters: z difference (first of a row: zigzag(zq)) */
+    TPC_CS_U_DY,       /* other clusters: y difference (zigzag) */
+    TPC_CS_Q,          /* charge codes, n_charge bits */
+    TPC_CS_SY,         /* y-width codes, n_width bits */
+    TPC_CS_SZ,         /* z-width codes, n_width bits */
+    TPC_N_CSTREAMS
+};
+#define TPC_CS_ALPHABET 4096
+#define TPC_CS_BLOCK 4096
+#define TPC_CS_PROB_BITS 14
+
+/* Cluster properties besides the position.  (device) [n] each */
+typedef struct {
+    const uint16_t* qtot;    /* total charge, ADC counts */
+    const uint8_t* sigma_y;  /* width along y, 1/64 cm */
+    const uint8_t* sigma_z;  /* width along z, 1/64 cm */
+} tpc_cluster_props_t;
+
+/* Compression settings; tpc_compress_params_default: 0.0075 cm, 0.0125 cm (sigma/8), 4, 3. */
+typedef struct {
+    double q_y, q_z;          /* position quanta (cm), > 0 */
+    int32_t n_charge, n_width; /* bits kept after the leading one, 0 .. 15 */
+} tpc_compress_params_t;
+
+/* Per-stream counts, int64 each: counts[s * TPC_CSC_N + field]. */
+enum { TPC_CSC_SYMBOLS = 0, TPC_CSC_ESCAPES, TPC_CSC_BYTES, TPC_CSC_BLOCKS, TPC_CSC_N };
+/* counts[TPC_N_CSTREAMS * TPC_CSC_N + k]: clusters on tracks, other clusters, clusters skipped
+ * (row or sector out of range, or |yq|, |zq| >= 2^23), track hits whose prediction failed. */
+enum { TPC_CST_ATTACHED = 0, TPC_CST_UNATTACHED, TPC_CST_SKIPPED, TPC_CST_PRED_FAIL, TPC_CST_N };
+
+/* Compressed clusters.  All pointers (device), caller-owned.  cap_sym >= n + n_sectors * n_rows
+ * holds every stream; cap_esc bounds each stream's escapes; cap_bytes bounds all coded bytes
+ * (2 * cap_sym + 4 per block is always enough). */
+typedef struct {
+    int64_t cap_sym, cap_esc, cap_bytes;
+    int64_t* counts;         /* [TPC_N_CSTREAMS * TPC_CSC_N + TPC_CST_N] */
+    uint16_t* sym;           /* [TPC_N_CSTREAMS * cap_sym] symbols, stream after stream */
+    uint32_t* esc;           /* [TPC_N_CSTREAMS * cap_esc] escaped values in stream order */
+    uint32_t* freq;          /* [TPC_N_CSTREAMS * TPC_CS_ALPHABET] ANS frequencies (sum 2^14) */
+    uint32_t* block_bytes;   /* [TPC_N_CSTREAMS * (cap_sym / TPC_CS_BLOCK + 1)] coded bytes per block */
+    uint8_t* bytes;          /* [cap_bytes] coded blocks, stream after stream */
+    int32_t* order;          /* [n] cluster id of each stream position (track clusters first) */
+    int32_t* track_len;      /* [tracks->cap_tracks] hits of each track in the streams (0: track left
+                                out because an entry was unusable; its clusters are stored as others) */
+} tpc_compressed_t;
+
+void tpc_compress_params_default(tpc_compress_params_t* p);
+
+/* Compress the clusters of one event or time frame given its tracks (read as for
+ * tpc_cluster_flags: counts, hit_offset, n_hits, hit_ids, sector, row_ref, x_ref, state; hit
+ * entries outside [0, n) or beyond cap_hits leave their track out, and its clusters are stored as
+ * others).  params supplies s_max.  Enqueued on `stream`; with sync_check nonzero the call waits
+ * and returns TPC_ERR_CAPACITY when a capacity was too small (counts hold the sizes), and
+ * TPC_ERR_ARG when a cluster is on more than one track (the streams are then not valid). */
+int tpc_compress(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_cluster_props_t* props,
+                 const tpc_geometry_t* geom, double bz_tesla, const tpc_params_t* params,
+                 const tpc_compress_params_t* cparams, const tpc_tracks_t* tracks, tpc_compressed_t* out,
+                 void* stream, int sync_check);
+
+/* Sizes of the last tpc_compress call on this context, whose output is `c` (host; synchronises):
+ * per stream, bits[3 * s + 0] = the entropy of its symbols (sum over the symbols of -log2 of their
+ * relative frequency), [3 s + 1] = their Huffman-coded length, [3 s + 2] = their range-ANS length;
+ * escapes and code tables are not included.  bits has 3 * TPC_N_CSTREAMS entries. */
+int tpc_compress_sizes(tpc_ctx_t* ctx, const tpc_compressed_t* c, double* bits);
+
+/* Decode the ANS blocks of `in` back into symbols (syms: [TPC_N_CSTREAMS * in->cap_sym], device)
+ * and, from the symbols, the escapes and the same tracks, the clusters in stream order:
+ * sector, row (uint8), yq, zq (int32), charge (uint16), widths (uint8), each [n_total] (device).
+ * Enqueued on `stream`. */
+int tpc_decompress(tpc_ctx_t* ctx, const tpc_compressed_t* in, const tpc_geometry_t* geom, double bz_tesla,
+                   const tpc_params_t* params, const tpc_compress_params_t* cparams, const tpc_tracks_t* tracks,
+                   uint16_t* syms, uint8_t* sector, uint8_t* row, int32_t* yq, int32_t* zq, uint16_t* qtot,
+                   uint8_t* sigma_y, uint8_t* sigma_z, void* stream);
 
 /* ---- allocation-free variant ----
  * For callers that cannot allocate device memory while they run: code under HIP

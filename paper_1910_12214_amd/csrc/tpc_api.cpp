@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <functional>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -34,6 +37,27 @@ void* buf(tpc_ctx_t* c, const char* name, size_t bytes) {
     }
     b.bytes = want;
     return b.p;
+}
+
+// Length in bits of the optimal prefix (Huffman) code of symbols with these counts: the
+// sum of the weights of the merged nodes when the two lightest subtrees are merged until
+// one is left (one present symbol: one bit each).
+uint64_t huffman_bits(const uint32_t* count, int n_sym) {
+    std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> q;
+    for (int i = 0; i < n_sym; ++i)
+        if (count[i]) q.push(count[i]);
+    if (q.empty()) return 0;
+    if (q.size() == 1) return q.top();
+    uint64_t bits = 0;
+    while (q.size() > 1) {
+        const uint64_t a = q.top();
+        q.pop();
+        const uint64_t b = q.top();
+        q.pop();
+        bits += a + b;
+        q.push(a + b);
+    }
+    return bits;
 }
 
 void* buf_peek(tpc_ctx_t* c, const char* name, size_t* bytes) {
@@ -389,8 +413,10 @@ int tpc_ctx_create(tpc_ctx_t** out, int device) {
     c->device = device;
     noalloc_init(device);  // device address of the allocation-free entry point's fixed scratch
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
         c->n_cu = prop.multiProcessorCount;
+        c->arch = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    }
     *out = c;
     return TPC_OK;
 }
@@ -484,6 +510,141 @@ int tpc_cluster_flags(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry
     return TPC_OK;
 }
 
+void tpc_compress_params_default(tpc_compress_params_t* p) {
+    if (!p) return;
+    p->q_y = 0.0075;
+    p->q_z = 0.0125;
+    p->n_charge = 4;
+    p->n_width = 3;
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_compress_params(tpc_ctx_t* c, const tpc_compress_params_t* cp) {
+    if (!cp || !finite_pos(cp->q_y) || !finite_pos(cp->q_z) || cp->n_charge < 0 || cp->n_charge > 15 ||
+        cp->n_width < 0 || cp->n_width > 15)
+        return fail(c, TPC_ERR_ARG, "compress params: need q_y, q_z > 0 and n_charge, n_width in [0, 15]");
+    return TPC_OK;
+}
+
+int check_track_input(tpc_ctx_t* c, const tpc_tracks_t* t) {
+    if (!t || t->cap_tracks < 0 || t->cap_hits < 0 || !t->counts ||
+        (t->cap_tracks > 0 && (!t->hit_offset || !t->n_hits || !t->sector || !t->row_ref || !t->x_ref || !t->state)) ||
+        (t->cap_hits > 0 && !t->hit_ids))
+        return fail(c, TPC_ERR_ARG, "tracks: counts and, for cap_tracks > 0, hit_offset, n_hits, sector, row_ref, "
+                                    "x_ref, state (hit_ids for cap_hits > 0) are required");
+    return TPC_OK;
+}
+
+int check_compressed(tpc_ctx_t* c, const tpc_compressed_t* o, int64_t n, int64_t SR, int32_t cap_tracks) {
+    if (!o || !o->counts || !o->sym || !o->freq || !o->block_bytes || o->cap_sym < n + SR || o->cap_esc < 0 ||
+        o->cap_bytes < 0 || (o->cap_esc > 0 && !o->esc) || (o->cap_bytes > 0 && !o->bytes) || (n > 0 && !o->order) ||
+        (cap_tracks > 0 && !o->track_len))
+        return fail(c, TPC_ERR_ARG, "compressed output: counts, sym, freq, block_bytes, order (n > 0), track_len "
+                                    "(tracks), esc and bytes for nonzero capacities; cap_sym >= n + n_sectors * "
+                                    "n_rows");
+    return TPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpc_compress(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_cluster_props_t* props,
+                 const tpc_geometry_t* geo, double bz, const tpc_params_t* p, const tpc_compress_params_t* cp,
+                 const tpc_tracks_t* trk, tpc_compressed_t* out, void* stream, int sync_check) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p)) ||
+        (rc = check_compress_params(c, cp)) || (rc = check_track_input(c, trk)))
+        return rc;
+    if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
+    if (cl->n > 0 && (!props || !props->qtot || !props->sigma_y || !props->sigma_z))
+        return fail(c, TPC_ERR_ARG, "cluster properties (qtot, sigma_y, sigma_z) are required");
+    if ((rc = check_compressed(c, out, cl->n, (int64_t)geo->n_sectors * geo->n_rows, trk->cap_tracks))) return rc;
+    TPC_HIP(c, hipSetDevice(c->device));
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = compress_run(c, *cl, *props, pr.g, pr.kp.kq, pr.kp.s_max, *cp, *trk, *out, st))) return rc;
+    TPC_HIP(c, hipGetLastError());
+    if (!sync_check) return TPC_OK;
+    TPC_HIP(c, hipStreamSynchronize(st));
+    int64_t cnt[TPC_N_CSTREAMS * TPC_CSC_N + TPC_CST_N];
+    TPC_HIP(c, hipMemcpy(cnt, out->counts, sizeof cnt, hipMemcpyDeviceToHost));
+    if (cnt[TPC_N_CSTREAMS * TPC_CSC_N + TPC_CST_ATTACHED] + cnt[TPC_N_CSTREAMS * TPC_CSC_N + TPC_CST_UNATTACHED] >
+        cl->n)
+        return fail(c, TPC_ERR_ARG, "a cluster appears on more than one track: the streams are not valid");
+    int64_t bytes = 0;
+    for (int s = 0; s < TPC_N_CSTREAMS; ++s) {
+        bytes += cnt[s * TPC_CSC_N + TPC_CSC_BYTES];
+        if (cnt[s * TPC_CSC_N + TPC_CSC_ESCAPES] > out->cap_esc)
+            return fail(c, TPC_ERR_CAPACITY, "escape list too small: stream " + std::to_string(s) + " needs " +
+                                                 std::to_string(cnt[s * TPC_CSC_N + TPC_CSC_ESCAPES]));
+    }
+    if (bytes > out->cap_bytes)
+        return fail(c, TPC_ERR_CAPACITY, "coded output too small: needs " + std::to_string(bytes) + " bytes");
+    return TPC_OK;
+}
+
+int tpc_decompress(tpc_ctx_t* c, const tpc_compressed_t* in, const tpc_geometry_t* geo, double bz,
+                   const tpc_params_t* p, const tpc_compress_params_t* cp, const tpc_tracks_t* trk, uint16_t* syms,
+                   uint8_t* sector, uint8_t* row, int32_t* yq, int32_t* zq, uint16_t* qtot, uint8_t* sigma_y,
+                   uint8_t* sigma_z, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_geometry(c, geo)) || (rc = check_params(c, p)) || (rc = check_compress_params(c, cp)) ||
+        (rc = check_track_input(c, trk)))
+        return rc;
+    if (!std::isfinite(bz)) return fail(c, TPC_ERR_ARG, "bz must be finite");
+    if (!in || !in->counts || !in->sym || !in->freq || !in->block_bytes ||
+        in->cap_sym < (int64_t)geo->n_sectors * geo->n_rows || in->cap_sym < 1 || in->cap_esc < 0 ||
+        (in->cap_esc > 0 && !in->esc) || (in->cap_bytes > 0 && !in->bytes) || (trk->cap_tracks > 0 && !in->track_len))
+        return fail(c, TPC_ERR_ARG, "compressed input: counts, sym, freq, block_bytes, esc, bytes, track_len");
+    if (!syms || !sector || !row || !yq || !zq || !qtot || !sigma_y || !sigma_z)
+        return fail(c, TPC_ERR_ARG, "decoded outputs are NULL");
+    TPC_HIP(c, hipSetDevice(c->device));
+    tpc_clusters_t none{};
+    Prepared pr;
+    if ((rc = prepare(c, &none, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = decompress_run(c, *in, pr.g, pr.kp.kq, pr.kp.s_max, *cp, *trk, syms, sector, row, yq, zq, qtot, sigma_y,
+                             sigma_z, st)))
+        return rc;
+    TPC_HIP(c, hipGetLastError());
+    return TPC_OK;
+}
+
+int tpc_compress_sizes(tpc_ctx_t* c, const tpc_compressed_t* o, double* bits) {
+    if (!c || !o || !o->counts || !bits) return TPC_ERR_ARG;
+    c->err.clear();
+    TPC_HIP(c, hipSetDevice(c->device));
+    size_t hb = 0;
+    const uint32_t* dh = (const uint32_t*)buf_peek(c, "cq_hist", &hb);
+    if (!dh || hb < sizeof(uint32_t) * TPC_N_CSTREAMS * TPC_CS_ALPHABET)
+        return fail(c, TPC_ERR_STATE, "no tpc_compress call on this context yet");
+    TPC_HIP(c, hipDeviceSynchronize());
+    std::vector<uint32_t> h((size_t)TPC_N_CSTREAMS * TPC_CS_ALPHABET);
+    int64_t cnt[TPC_N_CSTREAMS * TPC_CSC_N];
+    TPC_HIP(c, hipMemcpy(h.data(), dh, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost));
+    TPC_HIP(c, hipMemcpy(cnt, o->counts, sizeof cnt, hipMemcpyDeviceToHost));
+    for (int s = 0; s < TPC_N_CSTREAMS; ++s) {
+        const uint32_t* hs = h.data() + (size_t)s * TPC_CS_ALPHABET;
+        double total = 0.0, ent = 0.0;
+        for (int i = 0; i < TPC_CS_ALPHABET; ++i) total += hs[i];
+        for (int i = 0; i < TPC_CS_ALPHABET; ++i)
+            if (hs[i]) ent -= hs[i] * std::log2(hs[i] / total);
+        bits[3 * s + 0] = ent;
+        bits[3 * s + 1] = (double)huffman_bits(hs, TPC_CS_ALPHABET);
+        bits[3 * s + 2] = 8.0 * (double)cnt[s * TPC_CSC_N + TPC_CSC_BYTES];
+    }
+    return TPC_OK;
+}
+
 // ------------------------------------------------------------ time frames
 }  // extern "C"
 
@@ -533,7 +694,7 @@ int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, 
              tpc_tracks_t* out, hipStream_t st) {
     static const float bins[][2] = {{8.f, 8.f}, {8.f, 16.f}, {12.f, 24.f}, {16.f, 32.f}};
     static const int chunks[] = {1, 2, 4};
-    static const int wavess[] = {2, 3, 4};
+    static const int wavess[] = {2, 3};
     Tuning best;
     best.best_ms = 1e30f;
     int n = 0, rc;
@@ -573,6 +734,54 @@ int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, 
     return TPC_OK;
 }
 
+// Tile cache file: one line per tuned shape, "<key> bin_y bin_z chunk blocks_per_cu waves best_ms
+// n_candidates", the key a 64-bit FNV-1a hash (hex) of the shape, the device and the library
+// build.  The last valid line of a key wins; unreadable files and malformed lines are ignored.
+#ifndef TPC_BUILD_ID
+#define TPC_BUILD_ID "unversioned"
+#endif
+
+std::string cache_key(const tpc_ctx_t* c, const std::string& shape) {
+    std::string s = shape + "|" + c->arch + "|" + TPC_BUILD_ID;
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char ch : s) h = (h ^ ch) * 1099511628211ull;
+    char buf[17];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return buf;
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, Tuning* t) {
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[64];
+        Tuning x;
+        if (line[0] == '#' || std::sscanf(line, "%63s %f %f %d %d %d %f %d", k, &x.bin_y, &x.bin_z, &x.chunk,
+                                          &x.blocks_per_cu, &x.waves, &x.best_ms, &x.n_candidates) != 8)
+            continue;
+        const bool ok = key == k && std::isfinite(x.bin_y) && x.bin_y > 0.f && std::isfinite(x.bin_z) &&
+                        x.bin_z > 0.f && x.chunk >= 1 && x.chunk <= 64 && x.blocks_per_cu >= 1 &&
+                        x.blocks_per_cu <= 64 && x.waves >= 2 && x.waves <= 3;
+        if (ok) {
+            *t = x;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& path, const std::string& key, const Tuning& t) {
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;  // the cache is an optimisation: a read-only location only costs the next tuning
+    if (std::ftell(f) == 0) std::fputs("# tpcca time-frame tile cache v1\n", f);
+    std::fprintf(f, "%s %.9g %.9g %d %d %d %.6g %d\n", key.c_str(), t.bin_y, t.bin_z, t.chunk, t.blocks_per_cu,
+                 t.waves, t.best_ms, t.n_candidates);
+    std::fclose(f);
+}
+
 }  // namespace
 extern "C" {
 
@@ -594,7 +803,17 @@ int tpc_track_timeframe(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geomet
                         bytes_of(&geo->z_min, sizeof(float)) + bytes_of(&geo->z_max, sizeof(float)) +
                         std::to_string(geo->n_sectors) + (p->mlp ? "|mlp" : "");
     if (!c->tune_forced && (!c->tuned || c->tuned_key != shape)) {
-        if ((rc = autotune(c, cl, geo, bz, p, out, st))) return rc;
+        auto known = c->tuned_shapes.find(shape);
+        Tuning cached;
+        if (known != c->tuned_shapes.end()) {
+            c->tuning = known->second;
+        } else if (!c->tune_cache.empty() && cache_lookup(c->tune_cache, cache_key(c, shape), &cached)) {
+            c->tuning = cached;
+        } else {
+            if ((rc = autotune(c, cl, geo, bz, p, out, st))) return rc;
+            if (!c->tune_cache.empty()) cache_store(c->tune_cache, cache_key(c, shape), c->tuning);
+        }
+        c->tuned_shapes[shape] = c->tuning;
         c->tuned = true;
         c->tuned_key = shape;
     }
@@ -668,6 +887,13 @@ int tpc_timeframe_tuning(tpc_ctx_t* c, tpc_tuning_t* o) {
     return TPC_OK;
 }
 
+int tpc_timeframe_tune_cache(tpc_ctx_t* c, const char* path) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    c->tune_cache = path ? path : "";
+    return TPC_OK;
+}
+
 int tpc_timeframe_set_tuning(tpc_ctx_t* c, const tpc_tuning_t* t) {
     if (!c) return TPC_ERR_ARG;
     if (!t) {
@@ -676,7 +902,7 @@ int tpc_timeframe_set_tuning(tpc_ctx_t* c, const tpc_tuning_t* t) {
         return TPC_OK;
     }
     if (!(t->bin_y > 0.f) || !(t->bin_z > 0.f) || t->tracklet_chunk < 1 || t->tracklet_chunk > 64 ||
-        t->blocks_per_cu < 1 || t->blocks_per_cu > 64 || t->waves_per_simd < 2 || t->waves_per_simd > 4)
+        t->blocks_per_cu < 1 || t->blocks_per_cu > 64 || t->waves_per_simd < 2 || t->waves_per_simd > 3)
         return fail(c, TPC_ERR_ARG, "bad tiles");
     c->tuning.bin_y = t->bin_y;
     c->tuning.bin_z = t->bin_z;

@@ -52,6 +52,32 @@ __device__ inline BinRange bin_range(const GridDesc& g, int s, int r, double y0,
     return bin_range(g, row_bins(g, s, r), y0, y1, z0, z1);
 }
 
+// A track's helix at x in the sector-local model, carried in one closed-form step from
+// its FP32 reference state st5 = (y, z, sin phi, dz/ds, q/pT) at x_ref: y, z and sin phi
+// there; false when |sin phi| reaches s_max on the way.  kq = -c Bz.
+__device__ inline bool helix_at_state(const float* st5, double x_ref, double x, double kq, double s_max, double& yt,
+                                      double& zt, double& st) {
+    const double y0 = st5[0], z0 = st5[1], s0 = st5[2];
+    const double t = st5[3], q = st5[4];
+    const double dx = x - x_ref;
+    const double kc = kq * q, s1 = s0 + kc * dx;
+    if (!(fabs(s1) < s_max) || !(fabs(s0) < s_max)) return false;
+    st = s1;
+    if (dx == 0.0) {
+        yt = y0;
+        zt = z0;
+        return true;
+    }
+    const double c0 = sqrt(1.0 - s0 * s0), c1 = sqrt(1.0 - s1 * s1);
+    const double dy = dx * (s0 + s1) / (c0 + c1);
+    const double L = copysign(sqrt(dx * dx + dy * dy), dx);
+    const double u = 0.5 * kc * L;
+    const double g = fabs(u) < 1e-4 ? 1.0 + u * u * (1.0 / 6.0) : asin(u) / u;  // asin(u)/u, exact to rounding
+    yt = y0 + dy;
+    zt = z0 + t * (L * g);
+    return true;
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);

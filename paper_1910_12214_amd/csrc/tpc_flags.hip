@@ -39,25 +39,7 @@ struct FlagArgs {
 // The track's helix at x (sector-local helix model): y, z, sin phi; false when
 // |sin phi| would reach s_max on the way.
 __device__ inline bool helix_at(const FlagArgs& a, int32_t k, double x, double& yt, double& zt, double& st) {
-    const double y0 = a.state[5 * k + 0], z0 = a.state[5 * k + 1], s0 = a.state[5 * k + 2];
-    const double t = a.state[5 * k + 3], q = a.state[5 * k + 4];
-    const double dx = x - (double)a.x_ref[k];
-    const double kc = a.kq * q, s1 = s0 + kc * dx;
-    if (!(fabs(s1) < a.s_max) || !(fabs(s0) < a.s_max)) return false;
-    st = s1;
-    if (dx == 0.0) {
-        yt = y0;
-        zt = z0;
-        return true;
-    }
-    const double c0 = sqrt(1.0 - s0 * s0), c1 = sqrt(1.0 - s1 * s1);
-    const double dy = dx * (s0 + s1) / (c0 + c1);
-    const double L = copysign(sqrt(dx * dx + dy * dy), dx);
-    const double u = 0.5 * kc * L;
-    const double g = fabs(u) < 1e-4 ? 1.0 + u * u * (1.0 / 6.0) : asin(u) / u;  // asin(u)/u, exact to rounding
-    yt = y0 + dy;
-    zt = z0 + t * (L * g);
-    return true;
+    return helix_at_state(a.state + 5 * k, (double)a.x_ref[k], x, a.kq, a.s_max, yt, zt, st);
 }
 
 // Key of track k for a cluster on a row where the track's protection decision is

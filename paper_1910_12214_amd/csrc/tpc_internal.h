@@ -112,6 +112,9 @@ struct tpc_ctx {
     bool tuned = false;
     std::string tuned_key;
     tpc::Tuning tuning;
+    std::map<std::string, tpc::Tuning> tuned_shapes;  // every shape tuned or read from the cache
+    std::string tune_cache;                            // tile cache file ("" = none)
+    std::string arch;                                  // device architecture and CU count (cache key)
     std::map<std::string, tpc::GraphEntry> graphs;
     hipStream_t own_stream = nullptr;
     // geometry tables already on the device (key of the last upload)
@@ -135,6 +138,7 @@ int fail(tpc_ctx_t* c, int code, const std::string& msg);
 // returns nullptr on allocation failure (error recorded)
 void* buf(tpc_ctx_t* c, const char* name, size_t bytes);
 void* buf_peek(tpc_ctx_t* c, const char* name, size_t* bytes);
+uint64_t huffman_bits(const uint32_t* count, int n_sym);
 
 // ---------------------------------------------------------------- launchers
 // scan.hip
@@ -211,6 +215,16 @@ void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s)
 void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& cl, const Hit* hits,
                    const uint32_t* bin_off, const tpc_tracks_t& trk, const tpc_flag_params_t& fp, uint64_t* key,
                    uint8_t* att, uint8_t* adj, uint8_t* flags, hipStream_t s);
+
+// compress.hip: cluster compression (Sec. 4, steps 2-4) and its decoder; the scratch
+// lives in the context (the last histogram stays in buffer "cq_hist").
+int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props_t& pr, const GridDesc& g, double kq,
+                 double s_max, const tpc_compress_params_t& cp, const tpc_tracks_t& trk, tpc_compressed_t& out,
+                 hipStream_t st);
+int decompress_run(tpc_ctx_t* c, const tpc_compressed_t& in, const GridDesc& g, double kq, double s_max,
+                   const tpc_compress_params_t& cp, const tpc_tracks_t& trk, uint16_t* syms, uint8_t* sector,
+                   uint8_t* row, int32_t* yq, int32_t* zq, uint16_t* qtot, uint8_t* sig_y, uint8_t* sig_z,
+                   hipStream_t st);
 
 // mlp.hip
 // Sizes of the training scratch: the packed BF16 weights (bytes) and one partial gradient of

@@ -56,6 +56,27 @@ class FlagParams(ctypes.Structure):
 
 FLAG_ATTACHED, FLAG_ADJACENT, FLAG_PROTECTED, FLAG_REMOVE_A, FLAG_REMOVE_B = 1, 2, 4, 8, 16
 
+# cluster compression (include/tpc_ca.h)
+CSTREAMS = ("a_drow", "a_ry", "a_rz", "u_n", "u_dz", "u_dy", "q", "sy", "sz")
+N_CSTREAMS, CS_ALPHABET, CS_BLOCK, CS_PROB_BITS = 9, 4096, 4096, 14
+CSC_N, CST_N = 4, 4  # per-stream counts (symbols, escapes, bytes, blocks); totals
+CST_ATTACHED, CST_UNATTACHED, CST_SKIPPED, CST_PRED_FAIL = 0, 1, 2, 3
+
+
+class CompressParams(ctypes.Structure):
+    _fields_ = [("q_y", ctypes.c_double), ("q_z", ctypes.c_double), ("n_charge", ctypes.c_int32),
+                ("n_width", ctypes.c_int32)]
+
+
+class ClusterProps(ctypes.Structure):
+    _fields_ = [("qtot", _vp), ("sigma_y", _vp), ("sigma_z", _vp)]
+
+
+class Compressed(ctypes.Structure):
+    _fields_ = [("cap_sym", ctypes.c_int64), ("cap_esc", ctypes.c_int64), ("cap_bytes", ctypes.c_int64),
+                ("counts", _vp), ("sym", _vp), ("esc", _vp), ("freq", _vp), ("block_bytes", _vp), ("bytes", _vp),
+                ("order", _vp), ("track_len", _vp)]
+
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("tracklet_chunk", ctypes.c_int32),
@@ -72,7 +93,8 @@ EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_de
            "tpc_track_timeframe", "tpc_timeframe_tuning", "tpc_timeframe_set_tuning", "tpc_stage_size",
            "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train",
            "tpc_profile_enable", "tpc_profile_read", "tpc_cluster_flags", "tpc_flag_params_default",
-           "tpc_mlp_train_noalloc")
+           "tpc_mlp_train_noalloc", "tpc_timeframe_tune_cache", "tpc_compress", "tpc_decompress",
+           "tpc_compress_params_default", "tpc_compress_sizes")
 MLP_NOALLOC_MAX_BATCH = 65536
 N_PROF = 5
 PROF_STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "selection")
@@ -117,6 +139,8 @@ def load():
     lib.tpc_timeframe_tuning.restype = ctypes.c_int
     lib.tpc_timeframe_set_tuning.argtypes = [_vp, P(Tuning)]
     lib.tpc_timeframe_set_tuning.restype = ctypes.c_int
+    lib.tpc_timeframe_tune_cache.argtypes = [_vp, ctypes.c_char_p]
+    lib.tpc_timeframe_tune_cache.restype = ctypes.c_int
     lib.tpc_stage_size.argtypes = [_vp, ctypes.c_int, P(ctypes.c_size_t)]
     lib.tpc_stage_size.restype = ctypes.c_int
     lib.tpc_stage_copy.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_size_t]
@@ -132,6 +156,16 @@ def load():
     lib.tpc_mlp_train.restype = ctypes.c_int
     lib.tpc_mlp_train_noalloc.argtypes = [_vp, _vp, _vp, _vp, P(TrainCfg), _vp, _vp, _vp, _vp, _vp]
     lib.tpc_mlp_train_noalloc.restype = ctypes.c_int
+    lib.tpc_compress_params_default.argtypes = [P(CompressParams)]
+    lib.tpc_compress_params_default.restype = None
+    lib.tpc_compress.argtypes = [_vp, P(Clusters), P(ClusterProps), P(Geometry), ctypes.c_double, P(Params),
+                                 P(CompressParams), P(Tracks), P(Compressed), _vp, ctypes.c_int]
+    lib.tpc_compress.restype = ctypes.c_int
+    lib.tpc_decompress.argtypes = [_vp, P(Compressed), P(Geometry), ctypes.c_double, P(Params), P(CompressParams),
+                                   P(Tracks), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.tpc_decompress.restype = ctypes.c_int
+    lib.tpc_compress_sizes.argtypes = [_vp, P(Compressed), ctypes.POINTER(ctypes.c_double)]
+    lib.tpc_compress_sizes.restype = ctypes.c_int
     lib.tpc_profile_enable.argtypes = [_vp, ctypes.c_int]
     lib.tpc_profile_enable.restype = ctypes.c_int
     lib.tpc_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -368,6 +402,101 @@ class Context:
                                                ctypes.byref(fp), ctypes.byref(t), _ptr(flags), _stream(stream)))
         return flags[:n]
 
+    # ------------------------------------------------------------- compression
+    def alloc_compressed(self, n: int, n_rows_total: int, cap_tracks: int, cap_esc: int | None = None,
+                         cap_bytes: int | None = None) -> dict:
+        """Output buffers of ``compress`` for n clusters, n_sectors * n_rows rows and cap_tracks tracks."""
+        import torch
+
+        d = torch.device("cuda", self.device)
+        cap_sym = n + n_rows_total
+        nb = cap_sym // CS_BLOCK + 1
+        cap_esc = cap_esc if cap_esc is not None else max(16, cap_sym // 4)
+        cap_bytes = cap_bytes if cap_bytes is not None else 2 * N_CSTREAMS * cap_sym + 4 * N_CSTREAMS * nb
+        return dict(cap_sym=cap_sym, cap_esc=cap_esc, cap_bytes=cap_bytes,
+                    counts=torch.zeros(N_CSTREAMS * CSC_N + CST_N, dtype=torch.int64, device=d),
+                    sym=torch.zeros(N_CSTREAMS * cap_sym, dtype=torch.int16, device=d),
+                    esc=torch.zeros(N_CSTREAMS * max(1, cap_esc), dtype=torch.int32, device=d),
+                    freq=torch.zeros(N_CSTREAMS * CS_ALPHABET, dtype=torch.int32, device=d),
+                    block_bytes=torch.zeros(N_CSTREAMS * nb, dtype=torch.int32, device=d),
+                    bytes=torch.zeros(max(1, cap_bytes), dtype=torch.uint8, device=d),
+                    order=torch.zeros(max(1, n), dtype=torch.int32, device=d),
+                    track_len=torch.zeros(max(1, cap_tracks), dtype=torch.int32, device=d))
+
+    @staticmethod
+    def _compressed_struct(c: dict) -> Compressed:
+        return Compressed(c["cap_sym"], c["cap_esc"], c["cap_bytes"], _ptr(c["counts"]), _ptr(c["sym"]),
+                          _ptr(c["esc"]), _ptr(c["freq"]), _ptr(c["block_bytes"]), _ptr(c["bytes"]), _ptr(c["order"]),
+                          _ptr(c["track_len"]))
+
+    @staticmethod
+    def _cparams(cparams: dict | None) -> CompressParams:
+        cp = CompressParams()
+        load().tpc_compress_params_default(ctypes.byref(cp))
+        for k, v in (cparams or {}).items():
+            setattr(cp, k, v)
+        return cp
+
+    def compress(self, y, z, row, sector, qtot, sigma_y, sigma_z, geom: dict, bz: float, tracks: dict,
+                 params: dict | None = None, cparams: dict | None = None, out: dict | None = None, stream=None,
+                 sync_check: bool = True) -> dict:
+        """Compress clusters given as CUDA tensors (positions as for ``track``; uint16 charge, uint8
+        widths) with their tracks (the layout ``alloc_tracks`` returns)."""
+        import torch
+
+        cl = self._clusters(y, z, row, sector)
+        n = int(cl.n)
+        need(qtot, "qtot", torch.int16 if qtot.dtype == torch.int16 else torch.uint16, numel=n)
+        need(sigma_y, "sigma_y", torch.uint8, numel=n)
+        need(sigma_z, "sigma_z", torch.uint8, numel=n)
+        check_tracks(tracks)
+        g, _keep = make_geometry(geom)
+        if out is None:
+            out = self.alloc_compressed(n, int(geom["n_sectors"]) * int(geom["n_rows"]), int(tracks["cap_tracks"]))
+        p = make_params(params)
+        cp = self._cparams(cparams)
+        pr = ClusterProps(_ptr(qtot), _ptr(sigma_y), _ptr(sigma_z))
+        t = self._tracks_struct(tracks)
+        o = self._compressed_struct(out)
+        self._check(self.lib.tpc_compress(self.h, ctypes.byref(cl), ctypes.byref(pr), ctypes.byref(g), float(bz),
+                                          ctypes.byref(p), ctypes.byref(cp), ctypes.byref(t), ctypes.byref(o),
+                                          _stream(stream), 1 if sync_check else 0))
+        return out
+
+    def decompress(self, comp: dict, geom: dict, bz: float, tracks: dict, params: dict | None = None,
+                   cparams: dict | None = None, stream=None) -> dict:
+        """Decode ``compress`` output: symbols and the clusters in stream order (device tensors)."""
+        import torch
+
+        check_tracks(tracks)
+        counts = comp["counts"].cpu().numpy()
+        n = int(counts[N_CSTREAMS * CSC_N + CST_ATTACHED] + counts[N_CSTREAMS * CSC_N + CST_UNATTACHED])
+        d = torch.device("cuda", self.device)
+        m = max(1, n)
+        res = dict(sym=torch.zeros(N_CSTREAMS * comp["cap_sym"], dtype=torch.int16, device=d),
+                   sector=torch.zeros(m, dtype=torch.uint8, device=d), row=torch.zeros(m, dtype=torch.uint8, device=d),
+                   yq=torch.zeros(m, dtype=torch.int32, device=d), zq=torch.zeros(m, dtype=torch.int32, device=d),
+                   qtot=torch.zeros(m, dtype=torch.int16, device=d),
+                   sigma_y=torch.zeros(m, dtype=torch.uint8, device=d),
+                   sigma_z=torch.zeros(m, dtype=torch.uint8, device=d))
+        g, _keep = make_geometry(geom)
+        p = make_params(params)
+        cp = self._cparams(cparams)
+        t = self._tracks_struct(tracks)
+        o = self._compressed_struct(comp)
+        self._check(self.lib.tpc_decompress(self.h, ctypes.byref(o), ctypes.byref(g), float(bz), ctypes.byref(p),
+                                            ctypes.byref(cp), ctypes.byref(t), *(_ptr(res[k]) for k in (
+                                                "sym", "sector", "row", "yq", "zq", "qtot", "sigma_y", "sigma_z")),
+                                            _stream(stream)))
+        res["n"] = n
+        return res
+
+    def compress_sizes(self, comp: dict) -> np.ndarray:
+        """[stream][entropy bits, Huffman bits, range-ANS bits] of the last ``compress`` call."""
+        b = (ctypes.c_double * (3 * N_CSTREAMS))()
+        self._check(self.lib.tpc_compress_sizes(self.h, ctypes.byref(self._compressed_struct(comp)), b))
+        return np.array(b[:], dtype=np.float64).reshape(N_CSTREAMS, 3)
+
     def stage(self, stage: int, dtype) -> np.ndarray:
         nb = ctypes.c_size_t(0)
         self._check(self.lib.tpc_stage_size(self.h, stage, ctypes.byref(nb)))
@@ -389,6 +518,10 @@ class Context:
         t = Tuning()
         self._check(self.lib.tpc_timeframe_tuning(self.h, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    def set_tune_cache(self, path: str | None):
+        """Persist time-frame tiles in a text file (None: no cache); see tpc_timeframe_tune_cache."""
+        self._check(self.lib.tpc_timeframe_tune_cache(self.h, os.fsencode(path) if path else None))
 
     def set_tuning(self, tiles: dict | None):
         if tiles is None:

@@ -69,7 +69,7 @@ def test_timeframe_equals_sector_path(ctx, small_tf):
 
 
 @pytest.mark.parametrize("tiles", [dict(bin_y=8.0, bin_z=16.0, tracklet_chunk=1, blocks_per_cu=4),
-                                   dict(bin_y=16.0, bin_z=32.0, tracklet_chunk=4, blocks_per_cu=8, waves_per_simd=4),
+                                   dict(bin_y=16.0, bin_z=32.0, tracklet_chunk=4, blocks_per_cu=8, waves_per_simd=2),
                                    dict(bin_y=5.0, bin_z=11.0, tracklet_chunk=2, blocks_per_cu=1, waves_per_simd=3)])
 def test_every_tile_choice_gives_identical_tracks(ctx, small_tf, tiles):
     from paper_1910_12214_amd import tpcca
@@ -82,6 +82,39 @@ def test_every_tile_choice_gives_identical_tracks(ctx, small_tf, tiles):
     got = tpcca.tracks_to_host(ctx.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))
     ctx.set_tuning(None)
     same(ref, got)
+
+
+def test_tile_cache_persists_across_contexts(small_tf, tmp_path):
+    """A second context with the same cache file takes the first one's tiles without tuning, and
+    tracks identically; a malformed line in the file is ignored."""
+    import time
+
+    from paper_1910_12214_amd import tpcca
+
+    w, ev = small_tf
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    path = tmp_path / "tiles.txt"
+    path.write_text("garbage line\n0123 1 2 3\n")
+    a = tpcca.Context(0)
+    a.set_tune_cache(str(path))
+    ta = tpcca.tracks_to_host(a.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))
+    tun_a = a.tuning()
+    entries = [ln for ln in path.read_text().splitlines() if ln and not ln.startswith("#")]
+    assert len(entries) == 3 and tun_a["n_candidates"] >= 4, entries
+    a.close()
+    b = tpcca.Context(0)
+    b.set_tune_cache(str(path))
+    t0 = time.perf_counter()
+    tb = tpcca.tracks_to_host(b.track(*ten, geom, synth.BZ, synth.TRACKER_PARAMS, timeframe=True))
+    dt = time.perf_counter() - t0
+    tun_b = b.tuning()
+    say(f"[tf] cached tiles {tun_b} in {dt * 1e3:.1f} ms (tuned {tun_a['best_ms']:.2f} ms per candidate run)")
+    for k in ("bin_y", "bin_z", "tracklet_chunk", "blocks_per_cu", "waves_per_simd", "n_candidates"):
+        assert tun_b[k] == pytest.approx(tun_a[k]), k
+    assert [ln for ln in path.read_text().splitlines() if ln and not ln.startswith("#")] == entries
+    same(ta, tb)
+    b.close()
 
 
 def test_graph_replay_sees_new_data_in_the_same_buffers(ctx):
