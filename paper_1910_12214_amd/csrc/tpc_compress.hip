@@ -5,9 +5,9 @@
 // the track's helix (one wave per track, one lane per hit: every hit's prediction is
 // a closed-form step from the track's reference state, so hits are independent);
 // the other clusters are counted per (sector, row), scattered into their row's
-// segment and ordered there by (zq, yq, id) -- one workgroup per row ranks its
-// clusters by counting the smaller keys, from LDS when the row fits -- then stored
-// as differences.  Step 4: range ANS per stream in blocks of 4096 symbols: a
+// segment and ordered there by (zq, yq, id) -- one workgroup per row sorts its keys
+// in LDS (bitonic); a row too long for LDS is ranked by counting smaller keys --
+// then stored as differences.  Step 4: range ANS per stream in blocks of 4096 symbols: a
 // histogram, the frequency table (one workgroup per stream), one lane per block
 // encoding backwards, and one wave per block copying the block's bytes into the
 // output in decoding order.  The decoder runs the same steps backwards.
@@ -23,7 +23,7 @@ constexpr int kAlpha = TPC_CS_ALPHABET, kEsc = TPC_CS_ALPHABET - 1;
 constexpr int kBlk = TPC_CS_BLOCK, kP = TPC_CS_PROB_BITS;
 constexpr uint32_t kAnsLow = 1u << 23;  // state interval [2^23, 2^31)
 constexpr int64_t kQLimit = int64_t(1) << 29;  // |yq|, |zq| below this: differences fit 31 bits
-constexpr int kRankLds = 4096;                   // row segments ranked from LDS up to this size
+constexpr int kSortLds = 4096;                   // row segments sorted in LDS up to this size
 
 __device__ inline uint32_t zigzag(int64_t v) { return v >= 0 ? (uint32_t)(2 * v) : (uint32_t)(-2 * v - 1); }
 __device__ inline int64_t unzigzag(uint32_t u) { return (u & 1u) ? -(int64_t)((u + 1u) >> 1) : (int64_t)(u >> 1); }
@@ -165,20 +165,43 @@ __global__ __launch_bounds__(kBlock) void k_cq_tracks(CmpArgs a, const uint32_t*
 }
 
 // ---------------------------------------------------------------- step 3, other clusters
+// Adds one to c[key] for every lane with ok, with one atomic per distinct key in the
+// wave (clusters usually arrive grouped by row); returns each such lane's slot:
+// the counter's old value plus its rank among the wave's lanes with the same key.
+// Every lane of the wave must call it.
+__device__ inline uint32_t wave_inc(uint32_t* __restrict__ c, uint32_t key, bool ok) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pend = __ballot(ok);
+    uint32_t slot = 0;
+    while (pend) {
+        const int l = __builtin_ctzll(pend);
+        const uint32_t kl = __shfl(key, l, 64);
+        const uint64_t same = __ballot(ok && key == kl) & pend;
+        uint32_t base = 0;
+        if (lane == l) base = atomicAdd(&c[kl], (uint32_t)__popcll(same));
+        base = __shfl(base, l, 64);
+        if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        pend &= ~same;
+    }
+    return slot;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cq_u_count(CmpArgs a, const uint8_t* __restrict__ fl,
                                                        uint32_t* __restrict__ ucnt) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n && fl[i] == 1) atomicAdd(&ucnt[(uint32_t)a.sector[i] * a.R + a.row[i]], 1u);
+    const bool ok = i < a.n && fl[i] == 1;
+    const uint32_t rs = ok ? (uint32_t)a.sector[i] * a.R + a.row[i] : 0u;
+    wave_inc(ucnt, rs, ok);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cq_u_scatter(CmpArgs a, const uint8_t* __restrict__ fl,
                                                          const uint32_t* __restrict__ uoff,
                                                          uint32_t* __restrict__ ucur, uint32_t* __restrict__ seg) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n && fl[i] == 1) {
-        const uint32_t rs = (uint32_t)a.sector[i] * a.R + a.row[i];
-        seg[uoff[rs] + atomicAdd(&ucur[rs], 1u)] = (uint32_t)i;
-    }
+    const bool ok = i < a.n && fl[i] == 1;
+    const uint32_t rs = ok ? (uint32_t)a.sector[i] * a.R + a.row[i] : 0u;
+    const uint32_t slot = wave_inc(ucur, rs, ok);
+    if (ok) seg[uoff[rs] + slot] = (uint32_t)i;
 }
 
 struct UKey {
@@ -189,46 +212,68 @@ __device__ inline bool key_less(const UKey& p, const UKey& q) {
     return p.z < q.z || (p.z == q.z && (p.y < q.y || (p.y == q.y && p.id < q.id)));
 }
 
-// One workgroup per (sector, row): the rank of each cluster is the number of smaller
-// (zq, yq, id) keys of its row; keys are distinct (ids), so the ranks place every
-// cluster once.
+// One workgroup per (sector, row) of at most kSortLds clusters: bitonic sort of the
+// (zq, yq, id) keys in LDS, padded to a power of two with keys above every real one
+// (|zq| < 2^29).  Keys are distinct (ids), so the sorted order is unique.
+__global__ __launch_bounds__(kBlock) void k_cq_u_sort(const uint32_t* __restrict__ ucnt, const uint32_t* __restrict__ uoff,
+                                                      const uint32_t* __restrict__ seg, const int32_t* __restrict__ yq,
+                                                      const int32_t* __restrict__ zq, const uint32_t* __restrict__ n_att,
+                                                      int64_t n, int32_t* __restrict__ order) {
+    __shared__ UKey keys[kSortLds];
+    const uint32_t rs = blockIdx.x;
+    const uint32_t m = ucnt[rs], b = uoff[rs];
+    if (m == 0 || m > (uint32_t)kSortLds) return;
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+        if (i < m) {
+            const uint32_t id = seg[b + i];
+            keys[i] = UKey{zq[id], yq[id], id};
+        } else {
+            keys[i] = UKey{INT32_MAX, INT32_MAX, UINT32_MAX};
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+                const uint32_t o = i ^ j;
+                if (o > i) {
+                    const UKey u = keys[i], v = keys[o];
+                    if ((i & k) == 0 ? key_less(v, u) : key_less(u, v)) {
+                        keys[i] = v;
+                        keys[o] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t first = (int64_t)*n_att + b;
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock)
+        if (first + i < n) order[first + i] = (int32_t)keys[i].id;
+}
+
+// Rows longer than kSortLds: the rank of each cluster is the number of smaller keys
+// of its row, read from global memory (quadratic; such rows do not occur in
+// realistic data).
 __global__ __launch_bounds__(kBlock) void k_cq_u_rank(const uint32_t* __restrict__ ucnt, const uint32_t* __restrict__ uoff,
                                                       const uint32_t* __restrict__ seg, const int32_t* __restrict__ yq,
                                                       const int32_t* __restrict__ zq, const uint32_t* __restrict__ n_att,
                                                       int64_t n, int32_t* __restrict__ order) {
-    __shared__ UKey keys[kRankLds];
     const uint32_t rs = blockIdx.x;
     const uint32_t m = ucnt[rs], b = uoff[rs];
-    if (m == 0) return;
-    const bool lds = m <= (uint32_t)kRankLds;
-    if (lds)
-        for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
-            const uint32_t id = seg[b + i];
-            keys[i] = UKey{zq[id], yq[id], id};
-        }
-    __syncthreads();
+    if (m <= (uint32_t)kSortLds) return;
     const int64_t first = (int64_t)*n_att + b;
-    int32_t* out = order + first;
     for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
-        UKey me;
-        if (lds) {
-            me = keys[i];
-        } else {
-            const uint32_t id = seg[b + i];
-            me = UKey{zq[id], yq[id], id};
-        }
+        const uint32_t id = seg[b + i];
+        const UKey me{zq[id], yq[id], id};
         uint32_t rank = 0;
         for (uint32_t j = 0; j < m; ++j) {
-            UKey o;
-            if (lds) {
-                o = keys[j];
-            } else {
-                const uint32_t id = seg[b + j];
-                o = UKey{zq[id], yq[id], id};
-            }
-            rank += key_less(o, me) ? 1u : 0u;
+            const uint32_t oid = seg[b + j];
+            rank += key_less(UKey{zq[oid], yq[oid], oid}, me) ? 1u : 0u;
         }
-        if (first + rank < n) out[rank] = (int32_t)me.id;
+        if (first + rank < n) order[first + rank] = (int32_t)me.id;
     }
 }
 
@@ -528,52 +573,90 @@ struct DecOut {
     uint8_t *sig_y, *sig_z;
 };
 
-// One lane per track: hits in order (a failed prediction takes the previous decoded hit).
+__device__ inline int64_t wave_scan(int64_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// One wave per track, one lane per hit, in chunks of 64 hits: the row is the running
+// sum of the row steps; a hit's position is its prediction plus its residuals, or,
+// where the prediction fails, the previous decoded hit plus them (the first hit's
+// predecessor is (0, 0)) -- a sum over the run of failed predictions before it,
+// taken by a segmented scan whose segments start at the hits with a prediction.
 __global__ __launch_bounds__(kBlock) void k_dq_tracks(CmpArgs a, const uint32_t* __restrict__ tlen,
                                                       const uint32_t* __restrict__ toff, const uint32_t* __restrict__ val,
                                                       const uint32_t* __restrict__ len, DecOut d) {
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
     if (k >= a.cap_tracks || !tlen[k]) return;
+    const int lane = threadIdx.x & 63;
     const uint32_t m = tlen[k], base = toff[k];
-    int r = a.rref[k];
-    int64_t y = 0, z = 0;
-    for (uint32_t j = 0; j < m; ++j) {
-        const uint32_t p = base + j;
-        if (p >= len[TPC_CS_A_DROW] || p >= len[kS]) return;
-        r += (int)unzigzag(val[(size_t)TPC_CS_A_DROW * a.cap_sym + p]);
-        const int rc = r < 0 ? 0 : (r >= a.R ? a.R - 1 : r);
-        int64_t py, pz;
-        if (!predict_q(a, k, (double)a.row_x[rc], py, pz)) {
-            py = y;
-            pz = z;
+    const uint32_t lim = len[TPC_CS_A_DROW] < len[kS] ? len[TPC_CS_A_DROW] : len[kS];
+    const uint8_t sec = (uint8_t)a.tsec[k];
+    int64_t r_in = a.rref[k], y_in = 0, z_in = 0;  // carried from the previous chunk
+    for (uint32_t j0 = 0; j0 < m; j0 += 64) {
+        const uint32_t p = base + j0 + (uint32_t)lane;
+        const bool in = j0 + (uint32_t)lane < m && p < lim;
+        const int64_t r = r_in + wave_scan(in ? unzigzag(val[(size_t)TPC_CS_A_DROW * a.cap_sym + p]) : 0, lane);
+        const int rc = r < 0 ? 0 : (r >= a.R ? a.R - 1 : (int)r);
+        int64_t py = 0, pz = 0;
+        bool head = in && predict_q(a, k, (double)a.row_x[rc], py, pz);
+        int64_t y = in ? py + unzigzag(val[(size_t)TPC_CS_A_RY * a.cap_sym + p]) : 0;
+        int64_t z = in ? pz + unzigzag(val[(size_t)TPC_CS_A_RZ * a.cap_sym + p]) : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t ty = __shfl_up(y, o, 64), tz = __shfl_up(z, o, 64);
+            const bool th = __shfl_up((int)head, o, 64) != 0;
+            if (lane >= o && !head) {
+                y += ty;
+                z += tz;
+                head = th;
+            }
         }
-        y = py + unzigzag(val[(size_t)TPC_CS_A_RY * a.cap_sym + p]);
-        z = pz + unzigzag(val[(size_t)TPC_CS_A_RZ * a.cap_sym + p]);
-        d.sector[p] = (uint8_t)a.tsec[k];
-        d.row[p] = (uint8_t)r;
-        d.yq[p] = (int32_t)y;
-        d.zq[p] = (int32_t)z;
+        if (!head) {
+            y += y_in;
+            z += z_in;
+        }
+        if (in) {
+            d.sector[p] = sec;
+            d.row[p] = (uint8_t)r;
+            d.yq[p] = (int32_t)y;
+            d.zq[p] = (int32_t)z;
+        }
+        r_in = __shfl(r, 63, 64);
+        y_in = __shfl(y, 63, 64);
+        z_in = __shfl(z, 63, 64);
     }
 }
 
-// One lane per (sector, row): the row's clusters from the differences.
+// One wave per (sector, row), one lane per cluster in chunks of 64: z and y are
+// running sums of the differences (the first z stored as itself).
 __global__ __launch_bounds__(kBlock) void k_dq_rows(CmpArgs a, const uint32_t* __restrict__ uoff,
                                                     const uint32_t* __restrict__ n_att, const uint32_t* __restrict__ val,
                                                     const uint32_t* __restrict__ len, DecOut d) {
-    const int32_t rs = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t rs = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
     if (rs >= a.S * a.R) return;
+    const int lane = threadIdx.x & 63;
     const uint32_t m = val[(size_t)TPC_CS_U_N * a.cap_sym + rs], b = uoff[rs], na = *n_att;
-    int64_t y = 0, z = 0;
-    for (uint32_t j = 0; j < m; ++j) {
-        const uint32_t p = b + j;
-        if (p >= len[TPC_CS_U_DZ] || (uint64_t)na + p >= len[kS]) return;
-        const uint32_t vz = val[(size_t)TPC_CS_U_DZ * a.cap_sym + p];
-        z = j ? z + (int64_t)vz : unzigzag(vz);
-        y += unzigzag(val[(size_t)TPC_CS_U_DY * a.cap_sym + p]);
-        d.sector[na + p] = (uint8_t)(rs / a.R);
-        d.row[na + p] = (uint8_t)(rs % a.R);
-        d.yq[na + p] = (int32_t)y;
-        d.zq[na + p] = (int32_t)z;
+    const uint8_t sec = (uint8_t)(rs / a.R), row = (uint8_t)(rs % a.R);
+    int64_t y_in = 0, z_in = 0;
+    for (uint32_t j0 = 0; j0 < m; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane, p = b + j;
+        const bool in = j < m && p < len[TPC_CS_U_DZ] && (uint64_t)na + p < len[kS];
+        const uint32_t vz = in ? val[(size_t)TPC_CS_U_DZ * a.cap_sym + p] : 0u;
+        const int64_t z = z_in + wave_scan(j == 0 ? unzigzag(vz) : (int64_t)vz, lane);
+        const int64_t y = y_in + wave_scan(in ? unzigzag(val[(size_t)TPC_CS_U_DY * a.cap_sym + p]) : 0, lane);
+        if (in) {
+            d.sector[na + p] = sec;
+            d.row[na + p] = row;
+            d.yq[na + p] = (int32_t)y;
+            d.zq[na + p] = (int32_t)z;
+        }
+        y_in = __shfl(y, 63, 64);
+        z_in = __shfl(z, 63, 64);
     }
 }
 
@@ -766,6 +849,7 @@ int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props
     k_cq_u_count<<<nblk(cl.n), kBlock, 0, st>>>(a, fl, ucnt);
     scan_u32(ucnt, uoff, SR, nullptr, n_un, scan, st);
     k_cq_u_scatter<<<nblk(cl.n), kBlock, 0, st>>>(a, fl, uoff, ucur, seg);
+    k_cq_u_sort<<<(unsigned)SR, kBlock, 0, st>>>(ucnt, uoff, seg, yq, zq, n_att, cl.n, out.order);
     k_cq_u_rank<<<(unsigned)SR, kBlock, 0, st>>>(ucnt, uoff, seg, yq, zq, n_att, cl.n, out.order);
     k_cq_u_delta<<<nblk(cl.n), kBlock, 0, st>>>(a, uoff, n_att, n_un, out.order, yq, zq, val);
     k_cq_u_n<<<nblk(SR), kBlock, 0, st>>>(a, ucnt, val);
@@ -845,10 +929,10 @@ int decompress_run(tpc_ctx_t* c, const tpc_compressed_t& in, const GridDesc& g, 
     // step 3 backwards
     if (trk.cap_tracks > 0) k_dq_track_len<<<nblk(T), kBlock, 0, st>>>(in.track_len, trk.cap_tracks, tlen);
     scan_u32(tlen, toff, T, nullptr, n_att, scan, st);
-    k_dq_tracks<<<nblk(T), kBlock, 0, st>>>(a, tlen, toff, val, len, d);
+    k_dq_tracks<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, tlen, toff, val, len, d);
     k_dq_u_n<<<nblk(SR), kBlock, 0, st>>>(a, val, ucnt);
     scan_u32(ucnt, uoff, SR, nullptr, nullptr, scan, st);
-    k_dq_rows<<<nblk(SR), kBlock, 0, st>>>(a, uoff, n_att, val, len, d);
+    k_dq_rows<<<nblk(SR, kBlock / 64), kBlock, 0, st>>>(a, uoff, n_att, val, len, d);
     k_dq_props<<<nblk(cap), kBlock, 0, st>>>(a, len, val, d);
     return TPC_OK;
 }

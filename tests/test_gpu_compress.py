@@ -69,12 +69,13 @@ def gpu_streams(c, comp):
     return out, tot
 
 
-def check_against_oracle(ctx, ev, geom, host_trk, dev_trk, props):
+def check_against_oracle(ctx, ev, geom, host_trk, dev_trk, props, cap_esc=None):
     from paper_1910_12214_amd import tpcca as T
 
     q, sy, sz = props
     ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
-    comp = ctx.compress(*ten, dev(q.view(np.int16)), dev(sy), dev(sz), geom, synth.BZ, dev_trk, P)
+    out = ctx.alloc_compressed(ev.n, geom["n_sectors"] * geom["n_rows"], int(dev_trk["cap_tracks"]), cap_esc=cap_esc)
+    comp = ctx.compress(*ten, dev(q.view(np.int16)), dev(sy), dev(sz), geom, synth.BZ, dev_trk, P, out=out)
     g, tot = gpu_streams(ctx, comp)
     o = oc.compress(ev.y, ev.z, ev.row, ev.sector, q, sy, sz, geom, synth.BZ, host_trk)
     assert int(tot[T.CST_ATTACHED]) == o["n_attached"] and int(tot[T.CST_UNATTACHED]) == o["n_unattached"]
@@ -196,3 +197,33 @@ def test_no_clusters(ctx):
     assert cnt[tpcca.CSTREAMS.index("u_n") * tpcca.CSC_N] == geom["n_rows"] * geom["n_sectors"]
     d = ctx.decompress(comp, geom, synth.BZ, trk, P)
     assert d["n"] == 0
+
+
+def test_row_longer_than_the_lds_sort(ctx):
+    """Without tracks every cluster is stored as an other cluster; one row gets 6000 extra
+    clusters, more than one workgroup sorts in LDS, so that row is ordered by the ranking
+    fallback.  Streams and decoding equal the oracle's."""
+    import dataclasses
+
+    w = synth.SECTOR_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    rng = np.random.default_rng(77)
+    k = 6000
+    r0 = 40
+    half = float(geom["row_x"][r0]) * float(geom["tan_half"])
+    ev = dataclasses.replace(
+        ev,
+        y=np.concatenate([ev.y, rng.uniform(-half, half, k).astype(np.float32)]),
+        z=np.concatenate([ev.z, rng.uniform(0.0, float(geom["z_max"]), k).astype(np.float32)]),
+        row=np.concatenate([ev.row, np.full(k, r0, ev.row.dtype)]),
+        sector=np.concatenate([ev.sector, np.full(k, ev.sector[0], ev.sector.dtype)]),
+        particle=np.concatenate([ev.particle, np.full(k, -1, ev.particle.dtype)]))
+    host = {"hit_offset": np.zeros(0, np.int32), "n_hits": np.zeros(0, np.int32), "hit_ids": np.zeros(0, np.int32),
+            "sector": np.zeros(0, np.int32), "row_ref": np.zeros(0, np.int32), "x_ref": np.zeros(0, np.float32),
+            "state": np.zeros((0, 5), np.float32)}
+    trk = ctx.alloc_tracks(16, 16)
+    # random y along the long row: most of its y differences exceed the alphabet (escapes)
+    _, o, _, _ = check_against_oracle(ctx, ev, geom, host, trk, synth.cluster_properties(ev), cap_esc=2 * ev.n)
+    assert o["n_attached"] == 0 and o["n_unattached"] == ev.n
+    say(f"[cmp] no tracks, one long row: {ev.n} clusters stored as others")
