@@ -229,6 +229,7 @@ struct Scratch {
     uint32_t *sort_cnt, *sel_order;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
     Hit* hits;
+    TlHit* tl_hits;
     int32_t *up, *dn, *upc, *dnc;
     uint8_t* start_flag;
     uint64_t* hit_key;
@@ -253,6 +254,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
     B(sorted_id, "sorted_id", 4 * n);
     B(slot_of, "slot_of", 4 * n);
     B(hits, "hits", sizeof(Hit) * n);
+    B(tl_hits, "tl_hits_rec", sizeof(TlHit) * n);
     B(up, "up", 4 * n);
     B(dn, "dn", 4 * n);
     B(upc, "upc", 4 * n);
@@ -342,13 +344,14 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     else
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
-    clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.start_flag, s.counters, st);
+    clean_and_flag(pr.kp, s.hits, n, s.counters, s.up, s.dn, s.upc, s.dnc, s.tl_hits, s.start_flag, s.counters,
+                   st);
     compact_starts(s.start_flag, s.pos_of, n, s.starts, s.block_cnt, s.scan, s.counters + C_N_STARTS, st);
     order_starts(g, s.hits, s.starts, T, s.counters, pr.slab_bins, s.slab_cnt, s.tl_slot, s.proc, s.scan, st);
     mk.mark();
     // a6 tracklets
-    build_tracklets(g, pr.kp, s.hits, s.bin_off, s.upc, s.starts, s.proc, s.seeds, s.counters, s.tl, T, tl_blocks,
-                    chunk, waves, st);
+    build_tracklets(g, pr.kp, s.hits, s.tl_hits, s.bin_off, s.row_off, s.upc, s.starts, s.proc, s.seeds, s.counters,
+                    s.tl, T, tl_blocks, chunk, waves, st);
     mk.mark();
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);

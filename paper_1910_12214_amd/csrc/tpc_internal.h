@@ -22,6 +22,14 @@ struct alignas(16) Hit {
     uint32_t rs;  // sector * n_rows + row
 };
 
+// Hit record of the tracklet kernel: position, cluster id and cleaned upward link in
+// one 16-byte line segment, so following a link chain reads one line per row.
+struct alignas(16) TlHit {
+    float y, z;
+    uint32_t id;
+    int32_t upc;
+};
+
 // Grid description handed to kernels by value.
 struct GridDesc {
     int R, S, nz;
@@ -165,7 +173,7 @@ void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, cons
                      const uint32_t* row_off, int64_t n_max, const uint32_t* counters, int32_t* up, int32_t* dn,
                      const float* mlp_q, uint32_t* cnt, hipStream_t s);
 void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uint32_t* counters, const int32_t* up,
-                    const int32_t* dn, int32_t* upc, int32_t* dnc, uint8_t* start_flag, uint32_t* cnt,
+                    const int32_t* dn, int32_t* upc, int32_t* dnc, TlHit* tl_hits, uint8_t* start_flag, uint32_t* cnt,
                     hipStream_t s);
 void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,
                     uint32_t* block_cnt, void* scan_scratch, uint32_t* n_starts_dev, hipStream_t s);
@@ -191,8 +199,9 @@ struct TrackletOut {
 };
 size_t seed_bytes();  // bytes of one precomputed tracklet start record
 // seeds: [t_max] start records in processing order (written here, then consumed)
-void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, void* seeds,
+void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const TlHit* tl_hits,
+                     const uint32_t* bin_off, const uint32_t* row_off, const int32_t* upc, const uint32_t* starts,
+                     const uint32_t* proc, void* seeds,
                      uint32_t* counters, const TrackletOut& o, int64_t t_max, int grid_blocks, int chunk, int waves,
                      hipStream_t s);
 

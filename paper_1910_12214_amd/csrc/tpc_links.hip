@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_clean_flag(KParams kp, const Hit* __
                                                        const uint32_t* __restrict__ counters,
                                                        const int32_t* __restrict__ up, const int32_t* __restrict__ dn,
                                                        int32_t* __restrict__ upc, int32_t* __restrict__ dnc,
-                                                       uint8_t* __restrict__ start_flag, uint32_t* __restrict__ cnt) {
+                                                       TlHit* __restrict__ tl_hits, uint8_t* __restrict__ start_flag,
+                                                       uint32_t* __restrict__ cnt) {
     const uint32_t n = counters[C_N_VALID_CLU];
     const int32_t p = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t clean = 0;
@@ -143,8 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_clean_flag(KParams kp, const Hit* __
         const int32_t u = clean_up(up, dn, p);
         const int32_t d0 = dn[p];
         const int32_t d = (d0 >= 0 && up[d0] == p) ? d0 : -1;
+        const Hit h = hits[p];
         upc[p] = u;
         dnc[p] = d;
+        tl_hits[p] = TlHit{h.y, h.z, h.id, u};
         clean = u >= 0;
         uint8_t flag = 0;
         if (d < 0) {
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_clean_flag(KParams kp, const Hit* __
         }
         // the flags start zeroed (cleared with the grid): only starts are written, a
         // scattered byte write for 7% of the hits instead of all of them
-        if (flag) start_flag[hits[p].id] = 1;
+        if (flag) start_flag[h.id] = 1;
     }
     block_tally2(clean, 0, C_N_LINKS_CLEAN, -1, cnt);
 }
@@ -247,9 +250,10 @@ void find_neighbours(const GridDesc& g, const KParams& kp, const Hit* hits, cons
 }
 
 void clean_and_flag(const KParams& kp, const Hit* hits, int64_t n_max, const uint32_t* counters, const int32_t* up,
-                    const int32_t* dn, int32_t* upc, int32_t* dnc, uint8_t* start_flag, uint32_t* cnt,
+                    const int32_t* dn, int32_t* upc, int32_t* dnc, TlHit* tl_hits, uint8_t* start_flag, uint32_t* cnt,
                     hipStream_t s) {
-    k_clean_flag<<<blocks(n_max), kBlock, 0, s>>>(kp, hits, counters, up, dn, upc, dnc, start_flag, cnt);
+    k_clean_flag<<<blocks(n_max), kBlock, 0, s>>>(kp, hits, counters, up, dn, upc, dnc, tl_hits, start_flag,
+                                                  cnt);
 }
 
 void compact_starts(const uint8_t* start_flag, const uint32_t* pos_of, int64_t n, uint32_t* starts,

@@ -210,7 +210,7 @@ struct Best {
     float y, z;
 };
 
-__device__ inline void consider(Best& b, const Hit& h, uint32_t k, bool valid, const double p[5], double bx,
+__device__ inline void consider(Best& b, const TlHit& h, uint32_t k, bool valid, const double p[5], double bx,
                                 double bz, double i00, double i01, double i11, double cut) {
     const double ry = (double)h.y - p[0], rz = (double)h.z - p[1];
     const double c2 = ry * (i00 * ry + i01 * rz) + rz * (i01 * ry + i11 * rz);
@@ -224,7 +224,7 @@ __device__ inline void consider(Best& b, const Hit& h, uint32_t k, bool valid, c
     b.z = take ? h.z : b.z;
 }
 
-__device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const Hit* __restrict__ hits,
+__device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const TlHit* __restrict__ hits,
                                      const uint32_t* __restrict__ bin_off, const RowBins& rb, const double p[5],
                                      const double C[15], float& hy, float& hz) {
     const double syy = C[0] + kp.vy, syz = C[1], szz = C[2] + kp.vz;
@@ -248,10 +248,10 @@ __device__ inline int32_t search_row(const GridDesc& g, const KParams& kp, const
         }
         if (kb < ke) {
             const uint32_t last = ke - 1;
-            const Hit h0 = hits[kb];
-            const Hit h1 = hits[kb + 1 < last ? kb + 1 : last];
-            const Hit h2 = hits[kb + 2 < last ? kb + 2 : last];
-            const Hit h3 = hits[kb + 3 < last ? kb + 3 : last];
+            const TlHit h0 = hits[kb];
+            const TlHit h1 = hits[kb + 1 < last ? kb + 1 : last];
+            const TlHit h2 = hits[kb + 2 < last ? kb + 2 : last];
+            const TlHit h3 = hits[kb + 3 < last ? kb + 3 : last];
             consider(b, h0, kb, true, p, bx, bz, i00, i01, i11, cut);
             consider(b, h1, kb + 1, kb + 1 < ke, p, bx, bz, i00, i01, i11, cut);
             consider(b, h2, kb + 2, kb + 2 < ke, p, bx, bz, i00, i01, i11, cut);
@@ -451,8 +451,8 @@ __device__ inline uint32_t finish(Lane& L, int R, const KParams& kp, const Track
 //   pass B: rows at or above the start row re-use pass A's hit on that row (if any),
 //           rows below it are searched.
 __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const KParams& kp,
-                            const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
-                            const int32_t* __restrict__ upc, const TrackletOut& o) {
+                            const TlHit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+                            const uint32_t* __restrict__ row_off, const TrackletOut& o) {
     // Straight-line: every lane runs the same instructions and results are blended
     // with selects; only the row search and the filter update are branches.  Values
     // a lane computes after its pass has ended are discarded by the caller.
@@ -470,15 +470,20 @@ __device__ inline bool step(Lane& L, const GridDesc& g, const RowTab& rt, const 
     const RowBins rb = row_bins_lds(rt, L.s, rc);
     const int32_t cand = A ? (L.on ? L.link : -1) : ((r >= L.r0 && L.ia >= 0) ? L.link : -1);
     const int32_t cc = cand < 0 ? 0 : cand;
-    const Hit hc = hits[cc];
-    const int32_t cand_up = upc[cc];
+    const TlHit hc = hits[cc];
+    const int32_t cand_up = hc.upc;
+    // pass B: is pass A's hit on this row (its position inside the row's range)?  In
+    // pass A the candidate is the upward link of the previous row's hit, always on this
+    // row (links join adjacent rows), while the chain lasts.
+    const uint32_t* ro = row_off + (size_t)L.s * R + rc;
+    const uint32_t rlo = A ? 0u : ro[0], rhi = A ? 0u : ro[1];
     const int ia1 = L.ia < 1 ? 0 : (L.ia > R ? R - 1 : L.ia - 1);
     const int32_t pf_next = A ? -1 : slot[ia1];  // pass A lanes load nothing (no slot lines into L2)
     // x of the row the state is at: the row before this one in the pass's direction
     const double x0 = rt.x[A ? r - 1 : r + 1];
     end = end || !propagate(L.p, L.C, x0, xr, kp);
     end = end || fabs(L.p[0]) > xr * kp.tan_half + kp.edge;
-    const bool on_row = (cand >= 0) & ((int)(hc.rs % (uint32_t)R) == r);
+    const bool on_row = (cand >= 0) & (A | (((uint32_t)cand >= rlo) & ((uint32_t)cand < rhi)));
     const bool link = A & L.on & on_row & (chi2_of(L.p, L.C, hc.y, hc.z, kp) <= kp.fol_cut);
     const bool reused = !A & on_row;
     L.on = A ? link : L.on;
@@ -556,9 +561,9 @@ __global__ __launch_bounds__(kBlock) void k_seeds(GridDesc g, const Hit* __restr
 // SIMD without spills, and three waves hide the load behind each other's work.
 template <int WAVES>
 __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES))) void k_tracklets(
-    GridDesc g, KParams kp, const Hit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
-    const int32_t* __restrict__ upc, const Seed* __restrict__ seeds, uint32_t* __restrict__ counters, TrackletOut o,
-    int chunk) {
+    GridDesc g, KParams kp, const TlHit* __restrict__ hits, const uint32_t* __restrict__ bin_off,
+    const uint32_t* __restrict__ row_off, const Seed* __restrict__ seeds, uint32_t* __restrict__ counters,
+    TrackletOut o, int chunk) {
     const uint32_t n = counters[C_N_STARTS];
     const int lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -619,7 +624,7 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
         if (!__ballot(L.phase == 1 || L.phase == 2 || L.phase == 4)) break;
         Seed sd;
         if (WAVES == 2 && L.phase == 4) sd = seeds[my_j];  // two waves: the load hides behind the step
-        if ((L.phase == 1 || L.phase == 2) && step(L, g, rt, kp, hits, bin_off, upc, o)) {
+        if ((L.phase == 1 || L.phase == 2) && step(L, g, rt, kp, hits, bin_off, row_off, o)) {
             if (L.phase == 1 && !L.fail) {
                 start_pass_b(L, g, rt, kp, o);
             } else {
@@ -655,8 +660,9 @@ __global__ __launch_bounds__(kTlBlock) __attribute__((amdgpu_waves_per_eu(WAVES,
 
 size_t seed_bytes() { return sizeof(Seed); }
 
-void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off,
-                     const int32_t* upc, const uint32_t* starts, const uint32_t* proc, void* seeds,
+void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, const TlHit* tl_hits,
+                     const uint32_t* bin_off, const uint32_t* row_off, const int32_t* upc, const uint32_t* starts,
+                     const uint32_t* proc, void* seeds,
                      uint32_t* counters, const TrackletOut& o, int64_t t_max, int grid_blocks, int chunk, int waves,
                      hipStream_t s) {
     Seed* sd = (Seed*)seeds;
@@ -666,9 +672,9 @@ void build_tracklets(const GridDesc& g, const KParams& kp, const Hit* hits, cons
     // occupancy variants: 3 waves per SIMD (168 registers, no spills) or 2 (more registers for the
     // compiler's schedule)
     if (waves >= 3)
-        k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
+        k_tracklets<3><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, tl_hits, bin_off, row_off, sd, counters, o, chunk);
     else
-        k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, hits, bin_off, upc, sd, counters, o, chunk);
+        k_tracklets<2><<<grid_blocks, kTlBlock, 0, s>>>(g, kp, tl_hits, bin_off, row_off, sd, counters, o, chunk);
 }
 
 }  // namespace tpc
