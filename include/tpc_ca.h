@@ -373,6 +373,82 @@ int tpc_decompress(tpc_ctx_t* ctx, const tpc_compressed_t* in, const tpc_geometr
                    uint16_t* syms, uint8_t* sector, uint8_t* row, int32_t* yq, int32_t* zq, uint16_t* qtot,
                    uint8_t* sigma_y, uint8_t* sigma_z, void* stream);
 
+/* ---- track merging and the merged refit (Sec. 4) ----
+ * The tracker finds each leg of a looping track, and each sector's piece of a track
+ * crossing sectors, as a track of its own (about three instances per low-pT looper).
+ * tpc_merge joins the tracks that are pieces of one helix and fits each merged track
+ * once.  Per track (FP64): its global helix h = (Xc, Yc, k, w, z0) -- circle centre in
+ * the global frame (cm), curvature k = |q/pT c Bz| > 0 (1/cm), pitch w = dz/dpsi (cm
+ * per radian around the centre) and phase z0 = z - w psi at the reference point (psi =
+ * the point's angle around the centre) -- with its covariance carried from the state
+ * covariance.  Sector s covers azimuth [360/sps * (s mod sps), 360/sps * (s mod sps + 1))
+ * degrees, sps = sectors_per_side, local x along the sector's centre line; sectors
+ * s >= sps are the other side, whose local z is mirrored (global Z = -z).
+ * Two tracks are pieces of one helix when both radii are at most rho_max, their
+ * centres differ by at most centre_window in X and in Y, chi2 of (Xc, Yc, k, w) with
+ * the sum of both covariances is at most chi2_max, and their phases agree modulo
+ * m = round(dz0 / (pi (wA + wB))) turns, |m| <= max_turns, within phase_sigmas
+ * standard deviations (z0 and m turns of pitch errors, plus phase_floor in
+ * quadrature).  Merged tracks are the connected components of that relation, each
+ * labelled by its lowest track index.  Each component is then refit by weighted least
+ * squares (Gauss-Newton, steps halved until chi2 does not grow, at most max_iter
+ * steps) to one helix theta = (Xc, Yc, rho, z0, w) through all its members' hits:
+ * transverse residual = distance of the hit from the circle (params->sigma_y),
+ * longitudinal residual = Z - z0 - w psi (params->sigma_z), each hit's psi unwrapped to
+ * the turn its own track's helix predicts, shifted by the whole turns between its
+ * track's phase and the lowest member's.
+ * tpc_merge_params_default: 600 cm, 16 cm, 60, 5, 0.1 cm, 5 turns, 18, 50. */
+typedef struct {
+    double rho_max;          /* only helices this tight merge (cm), > 0 */
+    double centre_window;    /* |dXc|, |dYc| at most this (cm), > 0 */
+    double chi2_max;         /* chi2 of (Xc, Yc, k, w), 4 dof, > 0 */
+    double phase_sigmas;     /* phase agreement in standard deviations, > 0 */
+    double phase_floor;      /* added in quadrature to the phase error (cm), >= 0 */
+    int32_t max_turns;       /* phases at most this many turns apart, 0 .. 1000 */
+    int32_t sectors_per_side;/* 1 .. 128, n_sectors <= 2 * sectors_per_side */
+    int32_t max_iter;        /* refit steps, 1 .. 1000 */
+} tpc_merge_params_t;
+
+enum {
+    TPC_MG_COMPONENTS = 0,   /* merged tracks (connected components, singletons included) */
+    TPC_MG_MERGED,           /* components of two or more tracks */
+    TPC_MG_PAIRS_TESTED,     /* candidate pairs that reached the full same-helix test */
+    TPC_MG_PAIRS_PASSED,     /* of those, pairs that passed */
+    TPC_MG_MAX_CELL,         /* most tracks in one centre cell */
+    TPC_MG_BIG_CELLS,        /* cells too long for the LDS sort (ranked instead; slower) */
+    TPC_MG_REFIT_FAILED,     /* refits whose normal matrix was singular (theta NaN) */
+    TPC_MG_N
+};
+
+/* Output of tpc_merge (device).  Entries of track k for k < number of tracks; the fit
+ * entries only at component roots (label[k] == k) whose track entries are usable and
+ * whose helix is finite, NaN (ndf 0) elsewhere. */
+typedef struct {
+    int32_t cap_tracks;      /* >= tracks->cap_tracks */
+    int32_t* label;          /* [cap] lowest track index of k's component; -1 beyond the tracks */
+    int32_t* n_members;      /* [cap] members of the component rooted at k, 0 if k is no root */
+    double* helix;           /* [cap * 5] (Xc, Yc, k, w, z0) of track k; NaN if unusable */
+    double* helix_cov;       /* [cap * 15] lower triangle, row-major */
+    double* theta;           /* [cap * 5] refit (Xc, Yc, rho, z0, w) */
+    double* theta_cov;       /* [cap * 15] lower triangle, row-major: inverse normal matrix */
+    double* chi2;            /* [cap] */
+    int32_t* ndf;            /* [cap] 2 * hits - 5 */
+    int64_t* counts;         /* [TPC_MG_N] */
+} tpc_merged_t;
+
+void tpc_merge_params_default(tpc_merge_params_t* p);
+
+/* Merge and refit the tracks of `tracks` (the tracker's output or any track set in
+ * its layout: counts[TPC_CNT_TRACKS] tracks, clamped to cap_tracks, with hit lists,
+ * sector, x_ref, state and cov) over the clusters they index.  A track whose entries
+ * are unusable (sector out of range, hits beyond cap_hits, ids out of range or of a
+ * cluster with row or sector out of range) is a component of its own without a fit.
+ * Enqueued on `stream`; no host synchronisation.  Returns TPC_ERR_ARG for bad
+ * arguments (message in tpc_last_error). */
+int tpc_merge(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom, double bz_tesla,
+              const tpc_params_t* params, const tpc_merge_params_t* mparams, const tpc_tracks_t* tracks,
+              tpc_merged_t* out, void* stream);
+
 /* ---- allocation-free variant ----
  * For callers that cannot allocate device memory while they run: code under HIP
  * graph capture, tight training loops, harnesses that forbid hipMalloc.

@@ -521,6 +521,19 @@ void tpc_compress_params_default(tpc_compress_params_t* p) {
     p->n_width = 3;
 }
 
+void tpc_merge_params_default(tpc_merge_params_t* p) {
+    if (!p) return;
+    p->rho_max = 600.0;
+    p->centre_window = 16.0;
+    p->chi2_max = 60.0;
+    p->phase_sigmas = 5.0;
+    p->phase_floor = 0.1;
+    p->max_turns = 5;
+    p->sectors_per_side = 18;
+    p->max_iter = 50;
+}
+
+
 }  // extern "C"
 
 namespace {
@@ -645,6 +658,38 @@ int tpc_compress_sizes(tpc_ctx_t* c, const tpc_compressed_t* o, double* bits) {
         bits[3 * s + 1] = (double)huffman_bits(hs, TPC_CS_ALPHABET);
         bits[3 * s + 2] = 8.0 * (double)cnt[s * TPC_CSC_N + TPC_CSC_BYTES];
     }
+    return TPC_OK;
+}
+
+int tpc_merge(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
+              const tpc_merge_params_t* mp, const tpc_tracks_t* trk, tpc_merged_t* out, void* stream) {
+    if (!c) return TPC_ERR_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_clusters(c, cl)) || (rc = check_geometry(c, geo)) || (rc = check_params(c, p)) ||
+        (rc = check_track_input(c, trk)))
+        return rc;
+    if (!std::isfinite(bz) || bz == 0.0) return fail(c, TPC_ERR_ARG, "bz must be finite and nonzero");
+    if (trk->cap_tracks > 0 && !trk->cov) return fail(c, TPC_ERR_ARG, "tracks: cov is required");
+    if (!mp || !finite_pos(mp->rho_max) || !finite_pos(mp->centre_window) || !finite_pos(mp->chi2_max) ||
+        !finite_pos(mp->phase_sigmas) || !std::isfinite(mp->phase_floor) || mp->phase_floor < 0.0 ||
+        mp->max_turns < 0 || mp->max_turns > 1000 || mp->sectors_per_side < 1 || mp->sectors_per_side > 128 ||
+        geo->n_sectors > 2 * mp->sectors_per_side || mp->max_iter < 1 || mp->max_iter > 1000)
+        return fail(c, TPC_ERR_ARG, "merge params: need rho_max, centre_window, chi2_max, phase_sigmas > 0, "
+                                    "phase_floor >= 0, max_turns in [0, 1000], sectors_per_side in [1, 128] with "
+                                    "n_sectors <= 2 * sectors_per_side, max_iter in [1, 1000]");
+    if (!out || out->cap_tracks < trk->cap_tracks || !out->counts ||
+        (trk->cap_tracks > 0 && (!out->label || !out->n_members || !out->helix || !out->helix_cov || !out->theta ||
+                                 !out->theta_cov || !out->chi2 || !out->ndf)))
+        return fail(c, TPC_ERR_ARG, "merge output: every array for cap_tracks >= tracks->cap_tracks, and counts");
+    TPC_HIP(c, hipSetDevice(c->device));
+    Prepared pr;
+    if ((rc = prepare(c, cl, geo, bz, p, p->bin_y, p->bin_z, &pr))) return rc;
+    double xmax = 0.0;
+    for (int r = 0; r < geo->n_rows; ++r) xmax = std::max(xmax, (double)geo->row_x[r]);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = merge_run(c, *cl, pr.g, pr.kp.kq, p->sigma_y, p->sigma_z, xmax, *mp, *trk, *out, st))) return rc;
+    TPC_HIP(c, hipGetLastError());
     return TPC_OK;
 }
 

@@ -230,6 +230,11 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
 int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props_t& pr, const GridDesc& g, double kq,
                  double s_max, const tpc_compress_params_t& cp, const tpc_tracks_t& trk, tpc_compressed_t& out,
                  hipStream_t st);
+// merge.hip: track merging and the merged refit (Sec. 4); scratch in the context.
+// max_row_x: the largest pad-row radius (sizes the grid of helix centres).
+int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double kq, double sigma_y, double sigma_z,
+              double max_row_x, const tpc_merge_params_t& mp, const tpc_tracks_t& trk, tpc_merged_t& out,
+              hipStream_t st);
 int decompress_run(tpc_ctx_t* c, const tpc_compressed_t& in, const GridDesc& g, double kq, double s_max,
                    const tpc_compress_params_t& cp, const tpc_tracks_t& trk, uint16_t* syms, uint8_t* sector,
                    uint8_t* row, int32_t* yq, int32_t* zq, uint16_t* qtot, uint8_t* sig_y, uint8_t* sig_z,

@@ -1,0 +1,815 @@
+// Track merging and the merged refit (Sec. 4: the legs of a looping track, and the
+// pieces of one track in neighbouring sectors, are found as separate tracks; they are
+// merged into one track, which is then fitted once).  FP64 throughout.
+//
+//  1. helix: one lane per track.  Its global helix h = (Xc, Yc, k, w, z0) -- circle
+//     centre, curvature k > 0, pitch w = dz/dpsi (z advance per radian around the
+//     centre) and phase z0 = z - w psi at the reference point -- and the covariance of
+//     h carried from the track's state covariance by the Jacobian.  A track takes part
+//     when its hit entries are usable, h is finite and its radius 1/k is at most
+//     rho_max.
+//  2. cells: centres closer than the window in X and Y lie in neighbouring cells of a
+//     grid of window-sized cells.  Each track also gets a phase interval
+//     [z0 - reach, z0 + reach] such that two tracks can pass the phase test only when
+//     their intervals overlap (bound below).  Tracks are counted per cell, scattered,
+//     and each cell is sorted by interval start (bitonic in LDS; rank counting for a
+//     cell too long for LDS).
+//  3. pairs: one lane per track A walks the nine cells around its own and tests the
+//     tracks B whose interval starts inside A's, so every overlapping pair is reached
+//     from the track that starts first (from both on equal starts).  The same-helix
+//     test decides, always evaluated with the lower track index first.
+//  4. labels: passing pairs join a union-find forest whose links always point to a
+//     smaller index (a root is linked under the smaller root by compare-and-swap), so
+//     each root is the lowest index of its component whatever the order in which the
+//     pairs are found.
+//  5. refit: members are grouped by label in ascending index and one wave fits the
+//     component's hits: Gauss-Newton on (Xc, Yc, rho, z0, w), lanes over hits, normal
+//     equations summed across the wave in a fixed order, each step halved until chi2
+//     does not grow.
+//
+// Phase bound.  The test takes m = round(dz0 / p) turns, p = pi (wA + wB), rejects
+// |m| > M, and passes when (dz0 - m p)^2 <= n^2 var with var = CA_z0 + CB_z0 +
+// (pi m)^2 (CA_w + CB_w) + f^2.  Then |dz0| <= M pi (|wA| + |wB|) + n sqrt(var), and
+// sqrt(var) <= sA + sB with s = sqrt(max(C_z0, 0) + (pi M)^2 max(C_w, 0) + f^2 / 2), so
+// |dz0| <= reach_A + reach_B with reach = M pi |w| + n s (the same for p = 0, where
+// the test is |dz0| <= n sqrt(CA_z0 + CB_z0 + f^2)).  A reach that is not a number
+// becomes infinite: such a track is tested against every track of its cells.
+#include "tpc_device.h"
+#include "tpc_internal.h"
+
+namespace tpc {
+
+namespace {
+
+constexpr int kCellSortLds = 4096;  // cells sorted in LDS up to this many tracks
+
+struct MgArgs {
+    // tracks
+    const int32_t* tcounts;
+    int32_t cap_tracks, cap_hits;
+    const int32_t *off, *nh, *ids, *tsec;
+    const float *xref, *state, *cov;
+    // clusters
+    int64_t n;
+    const float *y, *z;
+    const uint8_t *row, *sector;
+    const float* row_x;
+    int R, S;
+    int sps;      // sectors per side
+    double dphi;  // azimuth width of a sector
+    double kq;    // -c Bz
+    // merging
+    double rho_max, win, chi2_max, n_sig, floor2;
+    int max_turns;
+    double cell_w, cell_lo;
+    int nc;
+    // refit
+    double wy, wz;  // hit weights 1 / sigma^2
+    int max_iter;
+};
+
+enum MgTally { T_PAIRS = 0, T_PASSED, T_BIG_CELLS, T_FAILED, T_MERGED, T_COMPONENTS, T_MAX_CELL, T_N };
+
+__device__ inline int32_t n_tracks(const MgArgs& a) {
+    const int32_t c = a.tcounts[TPC_CNT_TRACKS];
+    return c < 0 ? 0 : (c < a.cap_tracks ? c : a.cap_tracks);
+}
+
+__device__ inline int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Adds one to c[key] for every lane with ok, one atomic per distinct key of the wave;
+// returns each such lane's slot (the old count plus its rank among equal keys).  Every
+// lane of the wave must call it.
+__device__ inline uint32_t wave_inc(uint32_t* __restrict__ c, uint32_t key, bool ok) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pend = __ballot(ok);
+    uint32_t slot = 0;
+    while (pend) {
+        const int l = __builtin_ctzll(pend);
+        const uint32_t kl = __shfl(key, l, 64);
+        const uint64_t same = __ballot(ok && key == kl) & pend;
+        uint32_t base = 0;
+        if (lane == l) base = atomicAdd(&c[kl], (uint32_t)__popcll(same));
+        base = __shfl(base, l, 64);
+        if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        pend &= ~same;
+    }
+    return slot;
+}
+
+// Wave total of v added to tally[t] by lane 0.  Every lane of the wave must call it.
+__device__ inline void wave_tally(unsigned long long* tally, int t, uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&tally[t], (unsigned long long)v);
+}
+
+// Solves A x = b (n x n, row-major, overwritten) by elimination with partial pivoting
+// (the first row of largest magnitude); false when a pivot is exactly zero.
+template <int N>
+__device__ inline bool solve(double A[N][N], double b[N], double x[N]) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        int p = c;
+        double best = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < N; ++r)
+            if (fabs(A[r][c]) > best) {
+                best = fabs(A[r][c]);
+                p = r;
+            }
+        // row swap by selects (constant indices keep the matrix in registers)
+#pragma unroll
+        for (int r = c + 1; r < N; ++r) {
+            const bool sw = r == p;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const double t = A[c][k];
+                A[c][k] = sw ? A[r][k] : t;
+                A[r][k] = sw ? t : A[r][k];
+            }
+            const double t = b[c];
+            b[c] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+        if (A[c][c] == 0.0) return false;
+#pragma unroll
+        for (int r = c + 1; r < N; ++r) {
+            const double f = A[r][c] / A[c][c];
+#pragma unroll
+            for (int k = c; k < N; ++k) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+#pragma unroll
+    for (int r = N - 1; r >= 0; --r) {
+        double s = b[r];
+#pragma unroll
+        for (int k = r + 1; k < N; ++k) s -= A[r][k] * x[k];
+        x[r] = s / A[r][r];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------- 1. helix per track
+// use[k]: bit0 the track is refit (its entries are usable -- sector in range, hits inside
+// cap_hits, ids of clusters with row and sector in range -- and its helix is finite),
+// bit1 it also takes part in merging.
+__global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restrict__ H, double* __restrict__ CH,
+                                                     uint8_t* __restrict__ use, uint32_t* __restrict__ cell,
+                                                     double* __restrict__ lo, double* __restrict__ hi,
+                                                     uint32_t* __restrict__ ccnt) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const bool in = k < a.cap_tracks;
+    uint8_t u = 0;
+    uint32_t ck = 0;
+    if (in) {
+        double h[5], ch[15];
+        for (int i = 0; i < 5; ++i) h[i] = NAN;
+        for (int i = 0; i < 15; ++i) ch[i] = NAN;
+        bool valid = false;
+        if (k < n_tracks(a)) {
+            const int32_t o = a.off[k], m = a.nh[k], s = a.tsec[k];
+            valid = s >= 0 && s < a.S && o >= 0 && m > 0 && (int64_t)o + m <= (int64_t)a.cap_hits;
+            for (int32_t j = 0; valid && j < m; ++j) {
+                const int32_t id = a.ids[o + j];
+                valid = id >= 0 && (int64_t)id < a.n && a.row[id] < a.R && a.sector[id] < a.S;
+            }
+        }
+        if (valid) {
+            const int s = a.tsec[k];
+            const double side = s >= a.sps ? -1.0 : 1.0;
+            const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
+            const float* st = a.state + 5 * (size_t)k;
+            const double x = a.xref[k], y = st[0], z = st[1], sn = st[2], t = st[3], q = st[4];
+            const double kq = a.kq, kap = kq * q;
+            const double c = sqrt(fmax(1.0 - sn * sn, 0.0));
+            const double phi = asin(sn) + al;
+            const double ca = cos(al), sa = sin(al), sp = sin(phi), cp = cos(phi);
+            const double X = x * ca - y * sa, Y = x * sa + y * ca;
+            const double Xc = X - sp / kap, Yc = Y + cp / kap;
+            const double tg = side * t, w = tg / kap;
+            const double psi = atan2(Y - Yc, X - Xc);
+            h[0] = Xc;
+            h[1] = Yc;
+            h[2] = fabs(kap);
+            h[3] = w;
+            h[4] = side * z - w * psi;
+            // Jacobian d(Xc, Yc, k, w, z0) / d(y, z, sin phi, dz/ds, q/pT); psi moves with
+            // phi, so d psi / d sin phi = 1 / cos phi
+            double J[5][5] = {};
+            const double k2 = kap * kap;
+            J[0][0] = -sa;
+            J[0][2] = -cp / (kap * c);
+            J[0][4] = sp * kq / k2;
+            J[1][0] = ca;
+            J[1][2] = -sp / (kap * c);
+            J[1][4] = -cp * kq / k2;
+            J[2][4] = (double)((kap > 0.0) - (kap < 0.0)) * kq;
+            J[3][3] = side / kap;
+            J[3][4] = -tg * kq / k2;
+            J[4][1] = side;
+            J[4][2] = -w / c;
+            J[4][3] = -psi * J[3][3];
+            J[4][4] = -psi * J[3][4];
+            const float* cv = a.cov + 15 * (size_t)k;
+            double JC[5][5];
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j) {
+                    double v = 0.0;
+                    for (int l = 0; l < 5; ++l) v += J[i][l] * (double)cv[tri(l, j)];
+                    JC[i][j] = v;
+                }
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    double v = 0.0;
+                    for (int l = 0; l < 5; ++l) v += JC[i][l] * J[j][l];
+                    ch[tri(i, j)] = v;
+                }
+            bool fin = true;
+            for (int i = 0; i < 5; ++i) fin = fin && isfinite(h[i]);
+            u = fin ? 1 : 0;
+            if (fin && 1.0 / h[2] <= a.rho_max) {
+                u = 3;
+                const double M = (double)a.max_turns, pm = M_PI * M;
+                const double v = fmax(ch[14], 0.0) + pm * pm * fmax(ch[9], 0.0) + 0.5 * a.floor2;
+                double reach = pm * fabs(w) + a.n_sig * sqrt(v);
+                reach = reach >= 0.0 ? reach * (1.0 + 1e-9) + 1e-9 * (fabs(h[4]) + 1.0) : INFINITY;
+                lo[k] = h[4] - reach;
+                hi[k] = h[4] + reach;
+                const double top = (double)(a.nc - 1);
+                double fx = floor((Xc - a.cell_lo) / a.cell_w), fy = floor((Yc - a.cell_lo) / a.cell_w);
+                fx = fx < 0.0 ? 0.0 : (fx > top ? top : fx);
+                fy = fy < 0.0 ? 0.0 : (fy > top ? top : fy);
+                ck = (uint32_t)fy * (uint32_t)a.nc + (uint32_t)fx;
+                cell[k] = ck;
+            }
+        }
+        for (int i = 0; i < 5; ++i) H[5 * (size_t)k + i] = h[i];
+        for (int i = 0; i < 15; ++i) CH[15 * (size_t)k + i] = ch[i];
+        use[k] = u;
+    }
+    wave_inc(ccnt, ck, u == 3);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_scatter(MgArgs a, const uint8_t* __restrict__ use,
+                                                       const uint32_t* __restrict__ cell,
+                                                       const uint32_t* __restrict__ coff, uint32_t* __restrict__ ccur,
+                                                       uint32_t* __restrict__ seg) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const bool ok = k < a.cap_tracks && use[k] == 3;
+    const uint32_t ck = ok ? cell[k] : 0u;
+    const uint32_t slot = wave_inc(ccur, ck, ok);
+    if (ok) seg[coff[ck] + slot] = (uint32_t)k;
+}
+
+// ---------------------------------------------------------------- 2. cells sorted by interval start
+struct CKey {
+    double lo;
+    uint32_t k;
+};
+__device__ inline bool ckey_less(const CKey& p, const CKey& q) { return p.lo < q.lo || (p.lo == q.lo && p.k < q.k); }
+
+// One workgroup per cell of at most kCellSortLds tracks: bitonic sort of (start, index)
+// in LDS, padded with keys above every real one; writes the sorted indices and starts.
+__global__ __launch_bounds__(kBlock) void k_mg_cell_sort(const uint32_t* __restrict__ ccnt,
+                                                         const uint32_t* __restrict__ coff,
+                                                         const double* __restrict__ lo, uint32_t* __restrict__ seg,
+                                                         double* __restrict__ slo,
+                                                         unsigned long long* __restrict__ tally) {
+    __shared__ CKey keys[kCellSortLds];
+    const uint32_t cc = blockIdx.x;
+    const uint32_t m = ccnt[cc], b = coff[cc];
+    if (m == 0) return;
+    if (threadIdx.x == 0) atomicMax(&tally[T_MAX_CELL], (unsigned long long)m);
+    if (m > (uint32_t)kCellSortLds) {
+        if (threadIdx.x == 0) atomicAdd(&tally[T_BIG_CELLS], 1ull);
+        return;
+    }
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+        if (i < m) {
+            const uint32_t k = seg[b + i];
+            keys[i] = CKey{lo[k], k};
+        } else {
+            keys[i] = CKey{INFINITY, UINT32_MAX};
+        }
+    }
+    __syncthreads();
+    for (uint32_t s = 2; s <= P; s <<= 1) {
+        for (uint32_t j = s >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+                const uint32_t o = i ^ j;
+                if (o > i) {
+                    const CKey u = keys[i], v = keys[o];
+                    if ((i & s) == 0 ? ckey_less(v, u) : ckey_less(u, v)) {
+                        keys[i] = v;
+                        keys[o] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+        seg[b + i] = keys[i].k;
+        slo[b + i] = keys[i].lo;
+    }
+}
+
+// Cells longer than kCellSortLds: each track's place is the number of smaller keys of
+// its cell (quadratic).  Reads the unsorted segment, writes the sorted copy.
+__global__ __launch_bounds__(kBlock) void k_mg_cell_rank(const uint32_t* __restrict__ ccnt,
+                                                         const uint32_t* __restrict__ coff,
+                                                         const double* __restrict__ lo, const uint32_t* __restrict__ seg,
+                                                         uint32_t* __restrict__ seg_out, double* __restrict__ slo) {
+    const uint32_t cc = blockIdx.x;
+    const uint32_t m = ccnt[cc], b = coff[cc];
+    if (m <= (uint32_t)kCellSortLds) return;
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+        const uint32_t k = seg[b + i];
+        const CKey me{lo[k], k};
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint32_t o = seg[b + j];
+            rank += ckey_less(CKey{lo[o], o}, me) ? 1u : 0u;
+        }
+        seg_out[b + rank] = k;
+        slo[b + rank] = me.lo;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_cell_copy(const uint32_t* __restrict__ ccnt,
+                                                         const uint32_t* __restrict__ coff,
+                                                         const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    const uint32_t cc = blockIdx.x;
+    const uint32_t m = ccnt[cc], b = coff[cc];
+    if (m <= (uint32_t)kCellSortLds) return;
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) dst[b + i] = src[b + i];
+}
+
+// ---------------------------------------------------------------- 3. same-helix test
+__device__ bool same_helix(const MgArgs& a, const double* hA, const double* cA, const double* hB, const double* cB) {
+    if (fabs(hA[0] - hB[0]) > a.win || fabs(hA[1] - hB[1]) > a.win) return false;
+    double S[4][4], d[4], x[4], dd[4];
+    for (int i = 0; i < 4; ++i) {
+        d[i] = hA[i] - hB[i];
+        dd[i] = d[i];
+        for (int j = 0; j < 4; ++j) S[i][j] = cA[tri(i, j)] + cB[tri(i, j)];
+    }
+    if (!solve<4>(S, dd, x)) return false;
+    const double chi2 = d[0] * x[0] + d[1] * x[1] + d[2] * x[2] + d[3] * x[3];
+    if (!(chi2 <= a.chi2_max)) return false;
+    const double pitch = 2.0 * M_PI * 0.5 * (hA[3] + hB[3]);
+    const double dz0 = hA[4] - hB[4];
+    if (!(fabs(pitch) > 0.0)) return fabs(dz0) <= a.n_sig * sqrt(cA[14] + cB[14] + a.floor2);
+    const double m = rint(dz0 / pitch);
+    if (fabs(m) > (double)a.max_turns) return false;
+    const double dz = dz0 - m * pitch;
+    const double pm = M_PI * m;
+    const double var = cA[14] + cB[14] + pm * pm * (cA[9] + cB[9]) + a.floor2;
+    return dz * dz <= a.n_sig * a.n_sig * var;
+}
+
+// ---------------------------------------------------------------- 4. union-find
+__device__ inline int32_t uf_ld(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void uf_st(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Root of x, halving the path on the way (every link keeps pointing to a smaller index
+// of the same tree, whatever other lanes do meanwhile).
+__device__ inline int32_t uf_find(int32_t* par, int32_t x) {
+    int32_t cur = uf_ld(par + x);
+    if (cur != x) {
+        int32_t prev = x, next;
+        while (cur > (next = uf_ld(par + cur))) {
+            uf_st(par + prev, next);
+            prev = cur;
+            cur = next;
+        }
+    }
+    return cur;
+}
+
+__device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
+    int32_t ra = uf_find(par, a), rb = uf_find(par, b);
+    while (ra != rb) {
+        if (ra < rb) {
+            const int32_t t = ra;
+            ra = rb;
+            rb = t;
+        }
+        const int32_t old = atomicCAS(par + ra, ra, rb);  // the larger root under the smaller
+        if (old == ra) return;
+        ra = uf_find(par, old);
+        rb = uf_find(par, rb);
+    }
+}
+
+// One lane per track in cell order.
+__global__ __launch_bounds__(kBlock) void k_mg_pairs(MgArgs a, const uint32_t* __restrict__ n_elig,
+                                                     const uint32_t* __restrict__ seg, const double* __restrict__ slo,
+                                                     const uint32_t* __restrict__ coff, const uint32_t* __restrict__ cell,
+                                                     const double* __restrict__ lo, const double* __restrict__ hi,
+                                                     const double* __restrict__ H, const double* __restrict__ CH,
+                                                     int32_t* __restrict__ par, unsigned long long* __restrict__ tally) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    uint64_t tested = 0, passed = 0;
+    if (i < *n_elig) {
+        const uint32_t A = seg[i], ca = cell[A];
+        const double loA = lo[A], hiA = hi[A];
+        const int cx = (int)(ca % (uint32_t)a.nc), cy = (int)(ca / (uint32_t)a.nc);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = cy + dy;
+            if (y < 0 || y >= a.nc) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = cx + dx;
+                if (x < 0 || x >= a.nc) continue;
+                const uint32_t cc = (uint32_t)y * (uint32_t)a.nc + (uint32_t)x;
+                uint32_t b = coff[cc], e = coff[cc + 1];
+                // first start >= loA
+                while (b < e) {
+                    const uint32_t mid = b + (e - b) / 2;
+                    if (slo[mid] < loA)
+                        b = mid + 1;
+                    else
+                        e = mid;
+                }
+                e = coff[cc + 1];
+                for (uint32_t j = b; j < e && slo[j] <= hiA; ++j) {
+                    const uint32_t B = seg[j];
+                    if (B == A) continue;
+                    ++tested;
+                    const uint32_t p = A < B ? A : B, q = A < B ? B : A;
+                    if (same_helix(a, H + 5 * (size_t)p, CH + 15 * (size_t)p, H + 5 * (size_t)q,
+                                   CH + 15 * (size_t)q)) {
+                        ++passed;
+                        uf_unite(par, (int32_t)A, (int32_t)B);
+                    }
+                }
+            }
+        }
+    }
+    wave_tally(tally, T_PAIRS, tested);
+    wave_tally(tally, T_PASSED, passed);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_init(int32_t cap, int32_t* __restrict__ par) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k < cap) par[k] = k;
+}
+
+// Labels (the root of every track) and member counts per root.
+__global__ __launch_bounds__(kBlock) void k_mg_label(MgArgs a, const uint8_t* __restrict__ use,
+                                                     const int32_t* __restrict__ par, int32_t* __restrict__ label,
+                                                     uint32_t* __restrict__ gcnt) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.cap_tracks) return;
+    if (k >= n_tracks(a)) {
+        label[k] = -1;
+        return;
+    }
+    int32_t r = k;
+    while (par[r] != r) r = par[r];
+    label[k] = r;
+    atomicAdd(&gcnt[r], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_group(MgArgs a, const int32_t* __restrict__ label,
+                                                     const uint32_t* __restrict__ goff, uint32_t* __restrict__ gcur,
+                                                     int32_t* __restrict__ mem) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= n_tracks(a)) return;
+    const int32_t r = label[k];
+    mem[goff[r] + atomicAdd(&gcur[r], 1u)] = k;
+}
+
+// Members of each component in ascending index (insertion sort; components are small).
+__global__ __launch_bounds__(kBlock) void k_mg_sort_members(MgArgs a, const int32_t* __restrict__ label,
+                                                            const uint32_t* __restrict__ gcnt,
+                                                            const uint32_t* __restrict__ goff, int32_t* __restrict__ mem,
+                                                            int32_t* __restrict__ n_members,
+                                                            unsigned long long* __restrict__ tally) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const bool root = k < n_tracks(a) && label[k] == k;
+    uint32_t m = 0;
+    if (root) {
+        m = gcnt[k];
+        int32_t* p = mem + goff[k];
+        for (uint32_t i = 1; i < m; ++i) {
+            const int32_t v = p[i];
+            uint32_t j = i;
+            while (j > 0 && p[j - 1] > v) {
+                p[j] = p[j - 1];
+                --j;
+            }
+            p[j] = v;
+        }
+    }
+    if (k < a.cap_tracks) n_members[k] = root ? (int32_t)m : 0;
+    wave_tally(tally, T_COMPONENTS, root ? 1u : 0u);
+    wave_tally(tally, T_MERGED, m >= 2 ? 1u : 0u);
+}
+
+// ---------------------------------------------------------------- 5. refit
+// Per hit of a component being fitted, stored at the hit's own place in the track set's
+// hit list (inside cap_hits for every usable track, so no separate offsets are needed).
+struct alignas(32) FitHit {
+    double X, Y, Z, ps0;  // global position and the angle unwrapped at the start
+};
+
+// Members of one component (ascending index) and where their hits are.
+struct Comp {
+    const int32_t* mem;
+    uint32_t m;
+    const int32_t *off, *nh;
+};
+
+// Sums over the component's hits at th (every lane ends with the same totals): chi2,
+// and with `normal` also the normal matrix (lower triangle) and gradient.  Hit f of
+// the component (members' hits concatenated) belongs to lane f mod 64.
+__device__ inline void fit_sums(const FitHit* __restrict__ fh, const Comp& cp, const double th[5], double wy,
+                                double wz, bool normal, double& chi2, double N[15], double g[5]) {
+    const int lane = threadIdx.x & 63;
+    chi2 = 0.0;
+    for (int i = 0; i < 15; ++i) N[i] = 0.0;
+    for (int i = 0; i < 5; ++i) g[i] = 0.0;
+    const double tau = 2.0 * M_PI;
+    uint32_t base = 0;
+    for (uint32_t mi = 0; mi < cp.m; ++mi) {
+        const int32_t t = cp.mem[mi];
+        const int32_t o = cp.off[t], nt = cp.nh[t];
+        const int32_t j0 = (int32_t)(((uint32_t)lane + 64u - (base & 63u)) & 63u);
+        base += (uint32_t)nt;
+        for (int32_t j = j0; j < nt; j += 64) {
+            const FitHit h = fh[o + j];
+            const double dx = h.X - th[0], dy = h.Y - th[1];
+            const double r = hypot(dx, dy);
+            const double d = atan2(dy, dx) - h.ps0;
+            const double ps = h.ps0 + (d - tau * rint(d / tau));
+            const double rt = r - th[2], rz = h.Z - th[3] - th[4] * ps;
+            chi2 += wy * rt * rt + wz * rz * rz;
+            if (normal) {
+                const double jt[5] = {-dx / r, -dy / r, -1.0, 0.0, 0.0};
+                const double r2 = r * r;
+                const double jz[5] = {-th[4] * dy / r2, th[4] * dx / r2, 0.0, -1.0, -ps};
+#pragma unroll
+                for (int p = 0; p < 5; ++p) {
+                    g[p] += wy * jt[p] * rt + wz * jz[p] * rz;
+#pragma unroll
+                    for (int q = 0; q <= p; ++q) N[tri(p, q)] += wy * jt[p] * jt[q] + wz * jz[p] * jz[q];
+                }
+            }
+        }
+    }
+    chi2 = wave_sum_d(chi2);
+    if (normal) {
+        for (int i = 0; i < 15; ++i) N[i] = wave_sum_d(N[i]);
+        for (int i = 0; i < 5; ++i) g[i] = wave_sum_d(g[i]);
+    }
+}
+
+// One wave per component root: place its hits (members in ascending index, each
+// member's hits in its list order) with their starting turn, then Gauss-Newton.
+// Usable tracks with overlapping hit lists (never produced by the tracker) would share
+// FitHit entries; their fits are then unspecified, but every access stays inside the
+// hit list.
+__global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __restrict__ use,
+                                                     const int32_t* __restrict__ label,
+                                                     const uint32_t* __restrict__ gcnt,
+                                                     const uint32_t* __restrict__ goff, const int32_t* __restrict__ mem,
+                                                     const double* __restrict__ H, FitHit* __restrict__ fh,
+                                                     double* __restrict__ theta, double* __restrict__ theta_cov,
+                                                     double* __restrict__ chi2_out, int32_t* __restrict__ ndf_out,
+                                                     unsigned long long* __restrict__ tally) {
+    const int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    if (k >= a.cap_tracks) return;
+    const int lane = threadIdx.x & 63;
+    if (k >= n_tracks(a) || label[k] != k || !(use[k] & 1)) {  // no fit at this index
+        if (lane < 5) theta[5 * (size_t)k + lane] = NAN;
+        if (lane < 15) theta_cov[15 * (size_t)k + lane] = NAN;
+        if (lane == 0) {
+            chi2_out[k] = NAN;
+            ndf_out[k] = 0;
+        }
+        return;
+    }
+    const double tau = 2.0 * M_PI;
+    const double* h0 = H + 5 * (size_t)k;
+    double th[5] = {h0[0], h0[1], 1.0 / h0[2], h0[4], h0[3]};
+    const Comp cp{mem + goff[k], gcnt[k], a.off, a.nh};
+    int64_t nhit = 0;
+    for (uint32_t mi = 0; mi < cp.m; ++mi) {
+        const int32_t t = cp.mem[mi];
+        const int32_t o = a.off[t], nt = a.nh[t];
+        const double* hh = H + 5 * (size_t)t;
+        const int32_t j0 = (int32_t)(((uint32_t)lane + 64u - ((uint32_t)nhit & 63u)) & 63u);
+        for (int32_t j = j0; j < nt; j += 64) {
+            const int32_t id = a.ids[o + j];
+            const int s = a.sector[id];
+            const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
+            const double x = (double)a.row_x[a.row[id]], y = (double)a.y[id];
+            FitHit f;
+            f.X = x * cos(al) - y * sin(al);
+            f.Y = x * sin(al) + y * cos(al);
+            f.Z = (s >= a.sps ? -1.0 : 1.0) * (double)a.z[id];
+            const double psi = atan2(f.Y - th[1], f.X - th[0]);
+            double turns = 0.0;
+            if (th[4] != 0.0) {
+                const double own =
+                    rint((f.Z - hh[4] - hh[3] * atan2(f.Y - hh[1], f.X - hh[0])) / (tau * hh[3]));
+                const double shift = rint((hh[4] - th[3]) / (tau * th[4]));
+                const double base = own + shift;
+                const double z_of = th[3] + th[4] * (psi + tau * base);
+                turns = base + rint((f.Z - z_of) / (tau * th[4]));
+            }
+            f.ps0 = psi + tau * turns;
+            fh[o + j] = f;
+        }
+        nhit += nt;
+    }
+    double chi2, N[15], g[5];
+    fit_sums(fh, cp, th, a.wy, a.wz, false, chi2, N, g);
+    bool failed = false;
+    for (int it = 0; it < a.max_iter; ++it) {
+        double c2;
+        fit_sums(fh, cp, th, a.wy, a.wz, true, c2, N, g);
+        double A[5][5], b[5], step[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            b[p] = -g[p];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) A[p][q] = N[tri(p, q)];
+        }
+        if (!solve<5>(A, b, step)) {
+            failed = true;
+            break;
+        }
+        bool accepted = false;
+        double cand[5];
+        for (int h = 0; h < 30; ++h) {
+            for (int p = 0; p < 5; ++p) cand[p] = th[p] + step[p];
+            fit_sums(fh, cp, cand, a.wy, a.wz, false, c2, N, g);
+            if (c2 <= chi2) {
+                accepted = true;
+                break;
+            }
+            for (int p = 0; p < 5; ++p) step[p] = 0.5 * step[p];
+        }
+        if (!accepted) break;
+        const bool done = chi2 - c2 <= 1e-12 * chi2;
+        for (int p = 0; p < 5; ++p) th[p] = cand[p];
+        chi2 = c2;
+        if (done) break;
+    }
+    // covariance: the inverse of the normal matrix at the result
+    double c2;
+    fit_sums(fh, cp, th, a.wy, a.wz, true, c2, N, g);
+    double cov[15];
+    for (int i = 0; i < 15; ++i) cov[i] = NAN;
+#pragma unroll
+    for (int col = 0; col < 5; ++col) {
+        double A[5][5], b[5], x[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            b[p] = p == col ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) A[p][q] = N[tri(p, q)];
+        }
+        failed = failed || !solve<5>(A, b, x);
+#pragma unroll
+        for (int p = col; p < 5; ++p) cov[tri(p, col)] = x[p];
+    }
+    if (lane == 0) {
+        for (int p = 0; p < 5; ++p) theta[5 * (size_t)k + p] = failed ? NAN : th[p];
+        for (int i = 0; i < 15; ++i) theta_cov[15 * (size_t)k + i] = failed ? NAN : cov[i];
+        chi2_out[k] = failed ? NAN : chi2;
+        ndf_out[k] = (int32_t)(2 * nhit - 5 < INT32_MAX ? 2 * nhit - 5 : INT32_MAX);
+        if (failed) atomicAdd(&tally[T_FAILED], 1ull);
+    }
+}
+
+__global__ void k_mg_counts(const unsigned long long* __restrict__ tally, int64_t* __restrict__ counts) {
+    if (threadIdx.x != 0) return;
+    counts[TPC_MG_COMPONENTS] = (int64_t)tally[T_COMPONENTS];
+    counts[TPC_MG_MERGED] = (int64_t)tally[T_MERGED];
+    counts[TPC_MG_PAIRS_TESTED] = (int64_t)tally[T_PAIRS];
+    counts[TPC_MG_PAIRS_PASSED] = (int64_t)tally[T_PASSED];
+    counts[TPC_MG_MAX_CELL] = (int64_t)tally[T_MAX_CELL];
+    counts[TPC_MG_BIG_CELLS] = (int64_t)tally[T_BIG_CELLS];
+    counts[TPC_MG_REFIT_FAILED] = (int64_t)tally[T_FAILED];
+}
+
+inline unsigned nblk(int64_t n, int per = kBlock) { return (unsigned)(n > 0 ? (n + per - 1) / per : 1); }
+
+#define MB(field, name, bytes)                              \
+    field = (decltype(field))buf(c, name, (size_t)(bytes)); \
+    if (!field) return TPC_ERR_HIP;
+
+}  // namespace
+
+int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double kq, double sigma_y, double sigma_z,
+              double max_row_x, const tpc_merge_params_t& mp, const tpc_tracks_t& trk, tpc_merged_t& out,
+              hipStream_t st) {
+    const int64_t T = trk.cap_tracks > 0 ? trk.cap_tracks : 1;
+    const int64_t NH = trk.cap_hits > 0 ? trk.cap_hits : 1;
+    MgArgs a{};
+    a.tcounts = trk.counts;
+    a.cap_tracks = trk.cap_tracks;
+    a.cap_hits = trk.cap_hits;
+    a.off = trk.hit_offset;
+    a.nh = trk.n_hits;
+    a.ids = trk.hit_ids;
+    a.tsec = trk.sector;
+    a.xref = trk.x_ref;
+    a.state = trk.state;
+    a.cov = trk.cov;
+    a.n = cl.n;
+    a.y = cl.y;
+    a.z = cl.z;
+    a.row = cl.row;
+    a.sector = cl.sector;
+    a.row_x = g.row_x;
+    a.R = g.R;
+    a.S = g.S;
+    a.sps = mp.sectors_per_side;
+    a.dphi = 2.0 * M_PI / (double)mp.sectors_per_side;
+    a.kq = kq;
+    a.rho_max = mp.rho_max;
+    a.win = mp.centre_window;
+    a.chi2_max = mp.chi2_max;
+    a.n_sig = mp.phase_sigmas;
+    a.floor2 = mp.phase_floor * mp.phase_floor;
+    a.max_turns = mp.max_turns;
+    // cells a little wider than the window, so centres within the window always fall in
+    // neighbouring cells despite rounding; centres beyond the grid go to its edge cells
+    a.cell_w = mp.centre_window * (1.0 + 1e-9);
+    const double reach = max_row_x * std::sqrt(2.0) + mp.rho_max + mp.centre_window;
+    int64_t nc = (int64_t)std::ceil(2.0 * reach / a.cell_w);
+    nc = nc < 1 ? 1 : (nc > 4096 ? 4096 : nc);
+    a.nc = (int)nc;
+    a.cell_lo = -0.5 * (double)nc * a.cell_w;
+    a.wy = 1.0 / (sigma_y * sigma_y);
+    a.wz = 1.0 / (sigma_z * sigma_z);
+    a.max_iter = mp.max_iter;
+    const int64_t NC = nc * nc;
+    uint8_t* use;
+    uint32_t *cell, *ccnt, *coff, *ccur, *seg, *seg2, *gcnt, *goff, *gcur, *n_elig;
+    int32_t *par, *mem;
+    double *lo, *hi, *slo;
+    FitHit* fh;
+    unsigned long long* tally;
+    void* scan;
+    MB(use, "mg_use", T);
+    MB(cell, "mg_cell", 4 * T);
+    MB(ccnt, "mg_ccnt", 4 * (NC + 1));
+    MB(coff, "mg_coff", 4 * (NC + 1));
+    MB(ccur, "mg_ccur", 4 * (NC + 1));
+    MB(seg, "mg_seg", 4 * T);
+    MB(seg2, "mg_seg2", 4 * T);
+    MB(lo, "mg_lo", 8 * T);
+    MB(hi, "mg_hi", 8 * T);
+    MB(slo, "mg_slo", 8 * T);
+    MB(par, "mg_par", 4 * T);
+    MB(gcnt, "mg_gcnt", 4 * (T + 1));
+    MB(goff, "mg_goff", 4 * (T + 1));
+    MB(gcur, "mg_gcur", 4 * (T + 1));
+    MB(mem, "mg_mem", 4 * T);
+    MB(n_elig, "mg_nelig", 16);
+    MB(fh, "mg_fithits", sizeof(FitHit) * NH);
+    MB(tally, "mg_tally", 8 * T_N);
+    int64_t sn = NC + 1 > T + 1 ? NC + 1 : T + 1;
+    MB(scan, "mg_scan", scan_scratch_bytes(sn));
+    fill_u32(ccnt, 0u, NC + 1, st);
+    fill_u32(ccur, 0u, NC + 1, st);
+    fill_u32(gcnt, 0u, T + 1, st);
+    fill_u32(gcur, 0u, T + 1, st);
+    fill_u64((uint64_t*)tally, 0ull, T_N, st);
+    const unsigned nb = nblk(T);
+    k_mg_helix<<<nb, kBlock, 0, st>>>(a, out.helix, out.helix_cov, use, cell, lo, hi, ccnt);
+    scan_u32(ccnt, coff, NC + 1, nullptr, n_elig, scan, st);
+    k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, seg);
+    k_mg_cell_sort<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, lo, seg, slo, tally);
+    k_mg_cell_rank<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, lo, seg, seg2, slo);
+    k_mg_cell_copy<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, seg2, seg);
+    k_mg_init<<<nb, kBlock, 0, st>>>(trk.cap_tracks, par);
+    k_mg_pairs<<<nb, kBlock, 0, st>>>(a, n_elig, seg, slo, coff, cell, lo, hi, out.helix, out.helix_cov, par, tally);
+    k_mg_label<<<nb, kBlock, 0, st>>>(a, use, par, out.label, gcnt);
+    scan_u32(gcnt, goff, T, nullptr, nullptr, scan, st);
+    k_mg_group<<<nb, kBlock, 0, st>>>(a, out.label, goff, gcur, mem);
+    k_mg_sort_members<<<nb, kBlock, 0, st>>>(a, out.label, gcnt, goff, mem, out.n_members, tally);
+    k_mg_refit<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, use, out.label, gcnt, goff, mem, out.helix, fh,
+                                                         out.theta, out.theta_cov, out.chi2, out.ndf, tally);
+    k_mg_counts<<<1, 64, 0, st>>>(tally, out.counts);
+    return TPC_OK;
+}
+
+#undef MB
+
+}  // namespace tpc

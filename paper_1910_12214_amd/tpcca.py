@@ -78,6 +78,21 @@ class Compressed(ctypes.Structure):
                 ("order", _vp), ("track_len", _vp)]
 
 
+class MergeParams(ctypes.Structure):
+    _fields_ = [("rho_max", ctypes.c_double), ("centre_window", ctypes.c_double), ("chi2_max", ctypes.c_double),
+                ("phase_sigmas", ctypes.c_double), ("phase_floor", ctypes.c_double), ("max_turns", ctypes.c_int32),
+                ("sectors_per_side", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
+class Merged(ctypes.Structure):
+    _fields_ = [("cap_tracks", ctypes.c_int32), ("label", _vp), ("n_members", _vp), ("helix", _vp),
+                ("helix_cov", _vp), ("theta", _vp), ("theta_cov", _vp), ("chi2", _vp), ("ndf", _vp),
+                ("counts", _vp)]
+
+
+MG_COUNTS = ("components", "merged", "pairs_tested", "pairs_passed", "max_cell", "big_cells", "refit_failed")
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("bin_z", ctypes.c_float), ("tracklet_chunk", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("best_ms", ctypes.c_float),
@@ -94,7 +109,7 @@ EXPORTS = ("tpc_ctx_create", "tpc_ctx_destroy", "tpc_last_error", "tpc_params_de
            "tpc_stage_copy", "tpc_mlp_infer", "tpc_triplets", "tpc_mlp_grad", "tpc_mlp_train",
            "tpc_profile_enable", "tpc_profile_read", "tpc_cluster_flags", "tpc_flag_params_default",
            "tpc_mlp_train_noalloc", "tpc_timeframe_tune_cache", "tpc_compress", "tpc_decompress",
-           "tpc_compress_params_default", "tpc_compress_sizes")
+           "tpc_compress_params_default", "tpc_compress_sizes", "tpc_merge", "tpc_merge_params_default")
 MLP_NOALLOC_MAX_BATCH = 65536
 N_PROF = 5
 PROF_STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "selection")
@@ -166,6 +181,11 @@ def load():
     lib.tpc_decompress.restype = ctypes.c_int
     lib.tpc_compress_sizes.argtypes = [_vp, P(Compressed), ctypes.POINTER(ctypes.c_double)]
     lib.tpc_compress_sizes.restype = ctypes.c_int
+    lib.tpc_merge_params_default.argtypes = [P(MergeParams)]
+    lib.tpc_merge_params_default.restype = None
+    lib.tpc_merge.argtypes = [_vp, P(Clusters), P(Geometry), ctypes.c_double, P(Params), P(MergeParams), P(Tracks),
+                              P(Merged), _vp]
+    lib.tpc_merge.restype = ctypes.c_int
     lib.tpc_profile_enable.argtypes = [_vp, ctypes.c_int]
     lib.tpc_profile_enable.restype = ctypes.c_int
     lib.tpc_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -496,6 +516,58 @@ class Context:
         b = (ctypes.c_double * (3 * N_CSTREAMS))()
         self._check(self.lib.tpc_compress_sizes(self.h, ctypes.byref(self._compressed_struct(comp)), b))
         return np.array(b[:], dtype=np.float64).reshape(N_CSTREAMS, 3)
+
+    # ------------------------------------------------------------------ merging
+    def alloc_merged(self, cap_tracks: int) -> dict:
+        """Output buffers of ``merge`` for a track set of capacity cap_tracks."""
+        import torch
+
+        d = torch.device("cuda", self.device)
+        c = max(1, cap_tracks)
+        f64 = dict(dtype=torch.float64, device=d)
+        return dict(cap_tracks=cap_tracks, label=torch.empty(c, dtype=torch.int32, device=d),
+                    n_members=torch.empty(c, dtype=torch.int32, device=d), helix=torch.empty(c, 5, **f64),
+                    helix_cov=torch.empty(c, 15, **f64), theta=torch.empty(c, 5, **f64),
+                    theta_cov=torch.empty(c, 15, **f64), chi2=torch.empty(c, **f64),
+                    ndf=torch.empty(c, dtype=torch.int32, device=d),
+                    counts=torch.zeros(len(MG_COUNTS), dtype=torch.int64, device=d))
+
+    @staticmethod
+    def merge_params(mparams: dict | None = None) -> MergeParams:
+        mp = MergeParams()
+        load().tpc_merge_params_default(ctypes.byref(mp))
+        for k, v in (mparams or {}).items():
+            setattr(mp, k, v)
+        return mp
+
+    def merge(self, y, z, row, sector, geom: dict, bz: float, tracks: dict, params: dict | None = None,
+              mparams: dict | None = None, out: dict | None = None, stream=None) -> dict:
+        """Merge the pieces of one helix among ``tracks`` (the layout ``alloc_tracks`` returns) and
+        refit every merged track over its hits (clusters as CUDA tensors, as for ``track``)."""
+        import torch
+
+        cl = self._clusters(y, z, row, sector)
+        check_tracks(tracks)
+        if out is None:
+            out = self.alloc_merged(int(tracks["cap_tracks"]))
+        c = max(1, int(tracks["cap_tracks"]))
+        if int(out["cap_tracks"]) < int(tracks["cap_tracks"]):
+            raise TpcError(TPC_ERR_ARG, "merge output: cap_tracks below the track set's")
+        for k, dt, per in (("label", torch.int32, 1), ("n_members", torch.int32, 1), ("helix", torch.float64, 5),
+                           ("helix_cov", torch.float64, 15), ("theta", torch.float64, 5),
+                           ("theta_cov", torch.float64, 15), ("chi2", torch.float64, 1), ("ndf", torch.int32, 1)):
+            need(out[k], k, dt, min_numel=per * c)
+        need(out["counts"], "counts", torch.int64, min_numel=len(MG_COUNTS))
+        g, _keep = make_geometry(geom)
+        p = make_params(params)
+        mp = self.merge_params(mparams)
+        t = self._tracks_struct(tracks)
+        o = Merged(int(out["cap_tracks"]), *(_ptr(out[k]) for k in ("label", "n_members", "helix", "helix_cov",
+                                                                     "theta", "theta_cov", "chi2", "ndf",
+                                                                     "counts")))
+        self._check(self.lib.tpc_merge(self.h, ctypes.byref(cl), ctypes.byref(g), float(bz), ctypes.byref(p),
+                                       ctypes.byref(mp), ctypes.byref(t), ctypes.byref(o), _stream(stream)))
+        return out
 
     def stage(self, stage: int, dtype) -> np.ndarray:
         nb = ctypes.c_size_t(0)

@@ -1,0 +1,225 @@
+"""Track merging and the merged refit on the GPU (Sec. 4) against the oracle: every track's helix and
+its covariance, the merge labels (identical), and each merged track's refit (parameters within the
+fit's convergence tolerance, chi2, covariance, ndf), on looper events, a Pb-Pb event with the GPU's
+own tracks (sampled), malformed and empty track sets."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import merge as om
+from tests.test_gpu_flags import tracks_to_device
+
+pytestmark = pytest.mark.gpu
+P = synth.TRACKER_PARAMS
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1910_12214_amd import tpcca
+
+    c = tpcca.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def looper_event(seed, sigma=0.0, n=60):
+    w = dataclasses.replace(synth.sector_event(seed), only_sector=-1, phi_mode=1, pt_lo=0.06, pt_hi=0.4,
+                            sigma_y=sigma, sigma_z=sigma, eff=1.0, noise_frac=0.0, mult_fixed=n)
+    return w, synth.generate(w)
+
+
+def oracle_track_set(ev, geom):
+    """The oracle's tracks with their covariances rounded to FP32 (as the tracker stores them)."""
+    o = oracle.track(ev.y, ev.z, ev.row, ev.sector, geom, P, synth.BZ)
+    t = oracle.tracks_for_flags(o, geom, ev.sector)
+    nt = int(o["n_tracks"])
+    t["cov"] = np.asarray(o["tl_cov"][o["trk_tl"][:nt]], dtype=np.float32).reshape(-1, 15)
+    d = tracks_to_device(t)
+    ct = max(1, nt)
+    cov = np.zeros((ct, 15), np.float32)
+    cov[:nt] = t["cov"]
+    d["cov"] = dev(cov)
+    return t, d
+
+
+def host(out, nt):
+    return {k: out[k][:nt].cpu().numpy() for k in ("label", "n_members", "helix", "helix_cov", "theta", "theta_cov",
+                                                   "chi2", "ndf")}
+
+
+def check_refit(g, ids, hh, X, Y, Z, H, m, sy, sz):
+    """GPU refit of component g against the oracle's: within the convergence tolerance.
+
+    Both fits stop when a step lowers chi2 by at most 1e-12 of it, so each lies within about
+    sqrt(2e-12 chi2) standard deviations of the minimum; 1e-4 sigma covers both."""
+    th, cov, chi2, ndf, _ = om.refit(X[ids], Y[ids], Z[ids], H[g], sy, sz, hh)
+    sig = np.sqrt(np.abs(np.diag(cov)))
+    d = np.abs(m["theta"][g] - th)
+    assert np.all(d <= 1e-4 * sig + 1e-9 * np.abs(th) + 1e-12), (g, d / sig)
+    assert m["chi2"][g] == pytest.approx(chi2, rel=1e-6, abs=1e-9)
+    assert int(m["ndf"][g]) == ndf
+    ii, jj = np.tril_indices(5)
+    assert np.allclose(m["theta_cov"][g], cov[ii, jj], rtol=1e-5, atol=1e-12 * np.abs(cov).max())
+
+
+def full_check(ctx, ev, geom, t, d, sy, sz):
+    nt = len(t["nh"])
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    out = ctx.merge(*ten, geom, synth.BZ, d, params=P)
+    m = host(out, nt)
+    H, CH = om.helix_params(t["state"], t["x_ref"], t["sector"], t["cov"].astype(np.float64), synth.BZ)
+    scale = np.abs(H).max(axis=0)
+    assert np.allclose(m["helix"], H, rtol=1e-10, atol=1e-11 * scale), np.abs(m["helix"] - H).max(axis=0)
+    ii = np.tril_indices(5)
+    ch = CH[:, ii[0], ii[1]]
+    assert np.allclose(m["helix_cov"], ch, rtol=1e-8, atol=1e-12 * np.abs(ch).max())
+    lab = om.merge_labels(H, CH)
+    assert np.array_equal(m["label"], lab)
+    roots, cnt = np.unique(lab, return_counts=True)
+    assert np.array_equal(m["n_members"][roots], cnt)
+    assert np.all(m["n_members"][np.setdiff1d(np.arange(nt), roots)] == 0)
+    X, Y, Z = om.hit_points(ev.y, ev.z, ev.row, ev.sector, geom["row_x"])
+    for g in roots:
+        mem = np.nonzero(lab == g)[0]
+        ids = np.concatenate([t["hits"][t["off"][k]:t["off"][k] + t["nh"][k]] for k in mem])
+        hh = np.concatenate([np.repeat(H[k:k + 1], t["nh"][k], axis=0) for k in mem])
+        check_refit(g, ids, hh, X, Y, Z, H, m, sy, sz)
+    c = out["counts"].cpu().numpy()
+    assert c[0] == len(roots) and c[1] == int((cnt >= 2).sum()) and c[6] == 0
+    return m, lab, c
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_noise_free_loopers_equal_oracle(ctx, seed):
+    w, ev = looper_event(seed)
+    geom = synth.geometry(w)
+    t, d = oracle_track_set(ev, geom)
+    m, lab, c = full_check(ctx, ev, geom, t, d, P["sigma_y"], P["sigma_z"])
+    say(f"[merge] loopers seed {seed}: {len(lab)} tracks -> {c[0]} merged tracks ({c[1]} of several pieces); "
+        f"{c[2]} pairs tested, {c[3]} passed, largest cell {c[4]}")
+
+
+def test_smeared_loopers_equal_oracle(ctx):
+    w, _ = looper_event(14, sigma=0.06, n=40)
+    w = dataclasses.replace(w, sigma_z=0.1)
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    t, d = oracle_track_set(ev, geom)
+    m, lab, c = full_check(ctx, ev, geom, t, d, 0.06, 0.1)
+    say(f"[merge] smeared loopers: {len(lab)} tracks -> {c[0]}; chi2/ndf "
+        f"{np.nansum(m['chi2']) / m['ndf'][m['ndf'] > 0].sum():.3f}")
+
+
+def test_pbpb_event_gpu_tracks_sampled(ctx):
+    """The full Pb-Pb event with the GPU's own tracks: helices of every track; for sampled tracks,
+    every track the oracle's same-helix test joins to it (searched by brute force) carries its label;
+    sampled merged tracks are connected by the oracle's relation and labelled by their lowest
+    member; their refits equal the oracle's."""
+    from paper_1910_12214_amd import tpcca
+
+    w = synth.PBPB_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    trk = ctx.track(*ten, geom, synth.BZ, P)
+    h = tpcca.tracks_to_host(trk)
+    nt = len(h["n_hits"])
+    out = ctx.merge(*ten, geom, synth.BZ, trk, params=P)
+    m = host(out, nt)
+    cov = trk["cov"][:nt].cpu().numpy().astype(np.float64)
+    H, CH = om.helix_params(h["state"], h["x_ref"], h["sector"], cov, synth.BZ)
+    scale = np.abs(H).max(axis=0)
+    assert np.allclose(m["helix"], H, rtol=1e-10, atol=1e-11 * scale)
+    rng = np.random.default_rng(5)
+    ok = np.all(np.isfinite(H), axis=1) & (1.0 / H[:, 2] <= om.RHO_MAX)
+    lab = m["label"]
+    for i in rng.choice(nt, 200, replace=False):
+        if not ok[i]:
+            assert lab[i] == i
+            continue
+        near = np.nonzero(ok & (np.abs(H[:, 0] - H[i, 0]) <= om.CENTRE_WINDOW) &
+                          (np.abs(H[:, 1] - H[i, 1]) <= om.CENTRE_WINDOW))[0]
+        for j in near:
+            if j != i:
+                a, b = min(i, j), max(i, j)
+                if om.compatible(H[a], CH[a], H[b], CH[b]):
+                    assert lab[j] == lab[i], (i, j)
+    roots = np.unique(lab)
+    multi = [g for g in roots if m["n_members"][g] >= 2]
+    X, Y, Z = om.hit_points(ev.y, ev.z, ev.row, ev.sector, geom["row_x"])
+    for g in rng.choice(multi, min(40, len(multi)), replace=False):
+        mem = np.nonzero(lab == g)[0]
+        assert mem.min() == g
+        # connected through the oracle's relation
+        seen, todo = {mem[0]}, [mem[0]]
+        while todo:
+            a = todo.pop()
+            for b in mem:
+                if b not in seen and om.compatible(H[min(a, b)], CH[min(a, b)], H[max(a, b)], CH[max(a, b)]):
+                    seen.add(b)
+                    todo.append(b)
+        assert len(seen) == len(mem), g
+        ids = np.concatenate([h["hit_ids"][h["hit_offset"][k]:h["hit_offset"][k] + h["n_hits"][k]] for k in mem])
+        hh = np.concatenate([np.repeat(H[k:k + 1], h["n_hits"][k], axis=0) for k in mem])
+        check_refit(g, ids, hh, X, Y, Z, H, m, P["sigma_y"], P["sigma_z"])
+    c = out["counts"].cpu().numpy()
+    say(f"[merge] Pb-Pb event: {nt} tracks -> {c[0]} ({c[1]} of several pieces), {c[2]} pairs tested, "
+        f"{c[3]} passed, largest cell {c[4]}, refits failed {c[6]}")
+
+
+def test_malformed_and_empty_track_sets(ctx):
+    import torch
+
+    from paper_1910_12214_amd import tpcca
+
+    w, ev = looper_event(13)
+    geom = synth.geometry(w)
+    t, d = oracle_track_set(ev, geom)
+    nt = len(t["nh"])
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    ref = host(ctx.merge(*ten, geom, synth.BZ, d, params=P), nt)
+    # a track with a cluster id out of range and one with a NaN state: singletons without a fit
+    hits = t["hits"].copy()
+    hits[t["off"][2] + 1] = ev.n + 7
+    state = np.asarray(t["state"], np.float32).copy()
+    state[5, 2] = np.nan
+    t2 = dict(t, hits=hits, state=state)
+    d2 = tracks_to_device(t2)
+    d2["cov"] = d["cov"]
+    m = host(ctx.merge(*ten, geom, synth.BZ, d2, params=P), nt)
+    for k in (2, 5):
+        assert m["label"][k] == k and m["n_members"][k] == 1 and np.isnan(m["theta"][k]).all() and m["ndf"][k] == 0
+    # the others: the oracle's labels with tracks 2 and 5 left out
+    H, CH = om.helix_params(t["state"], t["x_ref"], t["sector"], t["cov"].astype(np.float64), synth.BZ)
+    H[[2, 5]] = np.nan
+    assert np.array_equal(m["label"], om.merge_labels(H, CH))
+    assert np.isfinite(ref["theta"][2]).all()
+    # no tracks
+    trk = ctx.alloc_tracks(16, 16)
+    out = ctx.merge(*ten, geom, synth.BZ, trk, params=P)
+    assert out["counts"].cpu().numpy()[0] == 0
+    # argument errors
+    small = ctx.alloc_merged(8)
+    with pytest.raises(tpcca.TpcError):
+        ctx.merge(*ten, geom, synth.BZ, d, params=P, out=small)
+    with pytest.raises(tpcca.TpcError):
+        ctx.merge(*ten, geom, synth.BZ, d, params=P, mparams={"sectors_per_side": 9})
+    torch.cuda.synchronize()
