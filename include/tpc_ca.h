@@ -390,8 +390,8 @@ int tpc_decompress(tpc_ctx_t* ctx, const tpc_compressed_t* in, const tpc_geometr
  * m = round(dz0 / (pi (wA + wB))) turns, |m| <= max_turns, within phase_sigmas
  * standard deviations (z0 and m turns of pitch errors, plus phase_floor in
  * quadrature).  Merged tracks are the connected components of that relation, each
- * labelled by its lowest track index.  Each component is then refit by weighted least
- * squares (Gauss-Newton, steps halved until chi2 does not grow, at most max_iter
+ * labelled by its lowest track index.  Each merged track (two or more members) is then
+ * refit by weighted least squares (Gauss-Newton, steps halved until chi2 does not grow, at most max_iter
  * steps) to one helix theta = (Xc, Yc, rho, z0, w) through all its members' hits:
  * transverse residual = distance of the hit from the circle (params->sigma_y),
  * longitudinal residual = Z - z0 - w psi (params->sigma_z), each hit's psi unwrapped to
@@ -415,14 +415,14 @@ enum {
     TPC_MG_PAIRS_TESTED,     /* candidate pairs that reached the full same-helix test */
     TPC_MG_PAIRS_PASSED,     /* of those, pairs that passed */
     TPC_MG_MAX_CELL,         /* most tracks in one centre cell */
-    TPC_MG_BIG_CELLS,        /* cells too long for the LDS sort (ranked instead; slower) */
+    TPC_MG_BIG_CELLS,        /* cells too long for the LDS sort (sorted in global memory) */
     TPC_MG_REFIT_FAILED,     /* refits whose normal matrix was singular (theta NaN) */
     TPC_MG_N
 };
 
 /* Output of tpc_merge (device).  Entries of track k for k < number of tracks; the fit
- * entries only at component roots (label[k] == k) whose track entries are usable and
- * whose helix is finite, NaN (ndf 0) elsewhere. */
+ * entries only at the roots (label[k] == k) of merged tracks of two or more members,
+ * NaN (ndf 0) elsewhere: a track that merged with nothing keeps the tracker's fit. */
 typedef struct {
     int32_t cap_tracks;      /* >= tracks->cap_tracks */
     int32_t* label;          /* [cap] lowest track index of k's component; -1 beyond the tracks */

@@ -6,8 +6,8 @@
 // a closed-form step from the track's reference state, so hits are independent);
 // the other clusters are counted per (sector, row), scattered into their row's
 // segment and ordered there by (zq, yq, id) -- one workgroup per row sorts its keys
-// in LDS (bitonic); a row too long for LDS is ranked by counting smaller keys --
-// then stored as differences.  Step 4: range ANS per stream in blocks of 4096 symbols: a
+// with a bitonic sort, in LDS, or in global memory for a row too long for LDS -- then
+// stored as differences.  Step 4: range ANS per stream in blocks of 4096 symbols: a
 // histogram, the frequency table (one workgroup per stream), one lane per block
 // encoding backwards, and one wave per block copying the block's bytes into the
 // output in decoding order.  The decoder runs the same steps backwards.
@@ -254,27 +254,31 @@ __global__ __launch_bounds__(kBlock) void k_cq_u_sort(const uint32_t* __restrict
         if (first + i < n) order[first + i] = (int32_t)keys[i].id;
 }
 
-// Rows longer than kSortLds: the rank of each cluster is the number of smaller keys
-// of its row, read from global memory (quadratic; such rows do not occur in
-// realistic data).
-__global__ __launch_bounds__(kBlock) void k_cq_u_rank(const uint32_t* __restrict__ ucnt, const uint32_t* __restrict__ uoff,
-                                                      const uint32_t* __restrict__ seg, const int32_t* __restrict__ yq,
-                                                      const int32_t* __restrict__ zq, const uint32_t* __restrict__ n_att,
-                                                      int64_t n, int32_t* __restrict__ order) {
+struct UKeyLess {
+    __device__ bool operator()(const UKey& p, const UKey& q) const { return key_less(p, q); }
+};
+
+// Rows longer than kSortLds: the same order by a bitonic sort of the row's keys in
+// global memory, one workgroup of 1024 lanes per row.
+__global__ __launch_bounds__(1024) void k_cq_u_sort_big(const uint32_t* __restrict__ ucnt,
+                                                        const uint32_t* __restrict__ uoff,
+                                                        const uint32_t* __restrict__ seg,
+                                                        const int32_t* __restrict__ yq, const int32_t* __restrict__ zq,
+                                                        const uint32_t* __restrict__ n_att, int64_t n,
+                                                        UKey* __restrict__ ukeys, int32_t* __restrict__ order) {
     const uint32_t rs = blockIdx.x;
     const uint32_t m = ucnt[rs], b = uoff[rs];
     if (m <= (uint32_t)kSortLds) return;
-    const int64_t first = (int64_t)*n_att + b;
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+    UKey* k = ukeys + b;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
         const uint32_t id = seg[b + i];
-        const UKey me{zq[id], yq[id], id};
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < m; ++j) {
-            const uint32_t oid = seg[b + j];
-            rank += key_less(UKey{zq[oid], yq[oid], oid}, me) ? 1u : 0u;
-        }
-        if (first + rank < n) order[first + rank] = (int32_t)me.id;
+        k[i] = UKey{zq[id], yq[id], id};
     }
+    __syncthreads();
+    flip_bitonic_sort(k, m, UKeyLess{});
+    const int64_t first = (int64_t)*n_att + b;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
+        if (first + i < n) order[first + i] = (int32_t)k[i].id;
 }
 
 // Differences of the other clusters (position p of their part of the order) and the
@@ -795,6 +799,7 @@ int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props
     const int64_t T = trk.cap_tracks > 0 ? trk.cap_tracks : 1;
     const int64_t nb_max = (cap + kBlk - 1) / kBlk, bb_stride = cap / kBlk + 1;
     int32_t *yq, *zq;
+    UKey* ukeys;
     uint8_t *fl, *tmp;
     uint32_t *tlen, *toff, *ucnt, *uoff, *ucur, *seg, *val, *eflag, *eidx, *hist, *cum, *tst, *n_emit, *boff, *len,
         *esc_tot, *byte_tot, *n_att, *n_un, *tally, *b_tot;
@@ -808,6 +813,7 @@ int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props
     CB(uoff, "cq_uoff", 4 * (SR + 1));
     CB(ucur, "cq_ucur", 4 * (SR + 1));
     CB(seg, "cq_seg", 4 * n);
+    CB(ukeys, "cq_ukeys", sizeof(UKey) * n);
     CB(val, "cq_val", 4 * kS * cap);
     CB(eflag, "cq_eflag", 4 * kS * cap);
     CB(eidx, "cq_eidx", 4 * kS * cap);
@@ -850,7 +856,7 @@ int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props
     scan_u32(ucnt, uoff, SR, nullptr, n_un, scan, st);
     k_cq_u_scatter<<<nblk(cl.n), kBlock, 0, st>>>(a, fl, uoff, ucur, seg);
     k_cq_u_sort<<<(unsigned)SR, kBlock, 0, st>>>(ucnt, uoff, seg, yq, zq, n_att, cl.n, out.order);
-    k_cq_u_rank<<<(unsigned)SR, kBlock, 0, st>>>(ucnt, uoff, seg, yq, zq, n_att, cl.n, out.order);
+    k_cq_u_sort_big<<<(unsigned)SR, 1024, 0, st>>>(ucnt, uoff, seg, yq, zq, n_att, cl.n, ukeys, out.order);
     k_cq_u_delta<<<nblk(cl.n), kBlock, 0, st>>>(a, uoff, n_att, n_un, out.order, yq, zq, val);
     k_cq_u_n<<<nblk(SR), kBlock, 0, st>>>(a, ucnt, val);
     k_cq_props<<<nblk(cl.n), kBlock, 0, st>>>(a, n_att, n_un, out.order, val);

@@ -78,6 +78,45 @@ __device__ inline bool helix_at_state(const float* st5, double x_ref, double x, 
     return true;
 }
 
+// Ascending sort of a[0, m) in global memory by one workgroup: the bitonic network in
+// its flip form, where every compare-exchange puts the smaller key at the lower index,
+// over the next power of two P >= m.  Positions [m, P) hold virtual keys above every
+// real key; such a key never has to move below a real one, so nothing is stored beyond
+// m.  Every thread of the workgroup must call it; the workgroup's barriers order the
+// global accesses (all its waves share one CU's caches).
+template <class K, class Less>
+__device__ void flip_bitonic_sort(K* a, uint32_t m, Less less) {
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        const uint32_t h = k >> 1;
+        for (uint32_t t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+            const uint32_t i = (t / h) * k + (t % h), o = (t / h) * k + (k - 1 - (t % h));
+            if (o < m) {
+                const K x = a[i], y = a[o];
+                if (less(y, x)) {
+                    a[i] = y;
+                    a[o] = x;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+                const uint32_t i = (t / j) * 2 * j + (t % j), o = i + j;
+                if (o < m) {
+                    const K x = a[i], y = a[o];
+                    if (less(y, x)) {
+                        a[i] = y;
+                        a[o] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);

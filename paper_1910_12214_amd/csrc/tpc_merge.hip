@@ -12,20 +12,23 @@
 //     grid of window-sized cells.  Each track also gets a phase interval
 //     [z0 - reach, z0 + reach] such that two tracks can pass the phase test only when
 //     their intervals overlap (bound below).  Tracks are counted per cell, scattered,
-//     and each cell is sorted by interval start (bitonic in LDS; rank counting for a
-//     cell too long for LDS).
-//  3. pairs: one lane per track A walks the nine cells around its own and tests the
-//     tracks B whose interval starts inside A's, so every overlapping pair is reached
-//     from the track that starts first (from both on equal starts).  The same-helix
+//     and each cell is sorted by interval start (bitonic in LDS; in global memory for a
+//     cell too long for LDS), then laid out as 64-byte candidate records.
+//  3. pairs: one lane per track A walks the nine cells around its own and reads the
+//     records of the tracks B whose interval starts inside A's, so every overlapping
+//     pair is reached from the track that starts first (from both on equal starts).  A
+//     prefilter drops pairs that cannot pass: the centre window, and |d_i| <=
+//     sqrt(chi2_max) (sigma_A,i + sigma_B,i) for each of Xc, Yc, k, w (implied by the chi2
+//     cut when both tracks' covariance blocks are positive definite).  The same-helix
 //     test decides, always evaluated with the lower track index first.
 //  4. labels: passing pairs join a union-find forest whose links always point to a
 //     smaller index (a root is linked under the smaller root by compare-and-swap), so
 //     each root is the lowest index of its component whatever the order in which the
 //     pairs are found.
-//  5. refit: members are grouped by label in ascending index and one wave fits the
-//     component's hits: Gauss-Newton on (Xc, Yc, rho, z0, w), lanes over hits, normal
-//     equations summed across the wave in a fixed order, each step halved until chi2
-//     does not grow.
+//  5. refit: members are grouped by label in ascending index and one wave fits the hits
+//     of each merged track (two or more members): Gauss-Newton on (Xc, Yc, rho, z0, w),
+//     lanes over hits, normal equations summed across the wave in a fixed order, each
+//     step halved until chi2 does not grow.
 //
 // Phase bound.  The test takes m = round(dz0 / p) turns, p = pi (wA + wB), rejects
 // |m| > M, and passes when (dz0 - m p)^2 <= n^2 var with var = CA_z0 + CB_z0 +
@@ -164,7 +167,7 @@ __device__ inline bool solve(double A[N][N], double b[N], double x[N]) {
 __global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restrict__ H, double* __restrict__ CH,
                                                      uint8_t* __restrict__ use, uint32_t* __restrict__ cell,
                                                      double* __restrict__ lo, double* __restrict__ hi,
-                                                     uint32_t* __restrict__ ccnt) {
+                                                     float* __restrict__ rad, uint32_t* __restrict__ ccnt) {
     const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     const bool in = k < a.cap_tracks;
     uint8_t u = 0;
@@ -243,6 +246,33 @@ __global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restric
                 reach = reach >= 0.0 ? reach * (1.0 + 1e-9) + 1e-9 * (fabs(h[4]) + 1.0) : INFINITY;
                 lo[k] = h[4] - reach;
                 hi[k] = h[4] + reach;
+                // Prefilter radii: for a positive definite S = CA + CB, chi2 = d' S^-1 d >=
+                // d_i^2 / S_ii, so a passing pair has |d_i| <= sqrt(chi2_max) (sA_i + sB_i).  Only
+                // a track whose (Xc, Yc, k, w) block is positive definite (Cholesky) gets finite
+                // radii: the sum of two such blocks is positive definite.
+                bool pd = true;
+                double L[4][4] = {};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j <= i; ++j) {
+                        double v = ch[tri(i, j)];
+#pragma unroll
+                        for (int l = 0; l < j; ++l) v -= L[i][l] * L[j][l];
+                        if (i == j) {
+                            pd = pd && v > 0.0;
+                            L[i][i] = v > 0.0 ? sqrt(v) : 1.0;
+                        } else {
+                            L[i][j] = v / L[j][j];
+                        }
+                    }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double r = sqrt(a.chi2_max * ch[tri(i, i)]) * (1.0 + 1e-9);
+                    float f = (float)r;
+                    if ((double)f < r) f = nextafterf(f, INFINITY);
+                    rad[4 * (size_t)k + i] = pd && r >= 0.0 ? f : INFINITY;
+                }
                 const double top = (double)(a.nc - 1);
                 double fx = floor((Xc - a.cell_lo) / a.cell_w), fy = floor((Yc - a.cell_lo) / a.cell_w);
                 fx = fx < 0.0 ? 0.0 : (fx > top ? top : fx);
@@ -258,30 +288,31 @@ __global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restric
     wave_inc(ccnt, ck, u == 3);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_scatter(MgArgs a, const uint8_t* __restrict__ use,
-                                                       const uint32_t* __restrict__ cell,
-                                                       const uint32_t* __restrict__ coff, uint32_t* __restrict__ ccur,
-                                                       uint32_t* __restrict__ seg) {
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    const bool ok = k < a.cap_tracks && use[k] == 3;
-    const uint32_t ck = ok ? cell[k] : 0u;
-    const uint32_t slot = wave_inc(ccur, ck, ok);
-    if (ok) seg[coff[ck] + slot] = (uint32_t)k;
-}
-
-// ---------------------------------------------------------------- 2. cells sorted by interval start
 struct CKey {
     double lo;
     uint32_t k;
 };
 __device__ inline bool ckey_less(const CKey& p, const CKey& q) { return p.lo < q.lo || (p.lo == q.lo && p.k < q.k); }
+struct CKeyLess {
+    __device__ bool operator()(const CKey& p, const CKey& q) const { return ckey_less(p, q); }
+};
 
+__global__ __launch_bounds__(kBlock) void k_mg_scatter(MgArgs a, const uint8_t* __restrict__ use,
+                                                       const uint32_t* __restrict__ cell,
+                                                       const uint32_t* __restrict__ coff, uint32_t* __restrict__ ccur,
+                                                       const double* __restrict__ lo, CKey* __restrict__ keys) {
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const bool ok = k < a.cap_tracks && use[k] == 3;
+    const uint32_t ck = ok ? cell[k] : 0u;
+    const uint32_t slot = wave_inc(ccur, ck, ok);
+    if (ok) keys[coff[ck] + slot] = CKey{lo[k], (uint32_t)k};
+}
+
+// ---------------------------------------------------------------- 2. cells sorted by interval start
 // One workgroup per cell of at most kCellSortLds tracks: bitonic sort of (start, index)
-// in LDS, padded with keys above every real one; writes the sorted indices and starts.
+// in LDS, padded with keys above every real one.
 __global__ __launch_bounds__(kBlock) void k_mg_cell_sort(const uint32_t* __restrict__ ccnt,
-                                                         const uint32_t* __restrict__ coff,
-                                                         const double* __restrict__ lo, uint32_t* __restrict__ seg,
-                                                         double* __restrict__ slo,
+                                                         const uint32_t* __restrict__ coff, CKey* __restrict__ gkeys,
                                                          unsigned long long* __restrict__ tally) {
     __shared__ CKey keys[kCellSortLds];
     const uint32_t cc = blockIdx.x;
@@ -294,14 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_cell_sort(const uint32_t* __restr
     }
     uint32_t P = 1;
     while (P < m) P <<= 1;
-    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
-        if (i < m) {
-            const uint32_t k = seg[b + i];
-            keys[i] = CKey{lo[k], k};
-        } else {
-            keys[i] = CKey{INFINITY, UINT32_MAX};
-        }
-    }
+    for (uint32_t i = threadIdx.x; i < P; i += kBlock) keys[i] = i < m ? gkeys[b + i] : CKey{INFINITY, UINT32_MAX};
     __syncthreads();
     for (uint32_t s = 2; s <= P; s <<= 1) {
         for (uint32_t j = s >> 1; j > 0; j >>= 1) {
@@ -318,41 +342,46 @@ __global__ __launch_bounds__(kBlock) void k_mg_cell_sort(const uint32_t* __restr
             __syncthreads();
         }
     }
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
-        seg[b + i] = keys[i].k;
-        slo[b + i] = keys[i].lo;
-    }
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) gkeys[b + i] = keys[i];
 }
 
-// Cells longer than kCellSortLds: each track's place is the number of smaller keys of
-// its cell (quadratic).  Reads the unsorted segment, writes the sorted copy.
-__global__ __launch_bounds__(kBlock) void k_mg_cell_rank(const uint32_t* __restrict__ ccnt,
-                                                         const uint32_t* __restrict__ coff,
-                                                         const double* __restrict__ lo, const uint32_t* __restrict__ seg,
-                                                         uint32_t* __restrict__ seg_out, double* __restrict__ slo) {
+// Cells longer than kCellSortLds (dense cells of low-momentum loopers in a time frame):
+// the same network in global memory, one workgroup of 1024 lanes per cell.
+__global__ __launch_bounds__(1024) void k_mg_cell_sort_big(const uint32_t* __restrict__ ccnt,
+                                                           const uint32_t* __restrict__ coff, CKey* __restrict__ gkeys) {
     const uint32_t cc = blockIdx.x;
-    const uint32_t m = ccnt[cc], b = coff[cc];
+    const uint32_t m = ccnt[cc];
     if (m <= (uint32_t)kCellSortLds) return;
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
-        const uint32_t k = seg[b + i];
-        const CKey me{lo[k], k};
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < m; ++j) {
-            const uint32_t o = seg[b + j];
-            rank += ckey_less(CKey{lo[o], o}, me) ? 1u : 0u;
-        }
-        seg_out[b + rank] = k;
-        slo[b + rank] = me.lo;
-    }
+    flip_bitonic_sort(gkeys + coff[cc], m, CKeyLess{});
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_cell_copy(const uint32_t* __restrict__ ccnt,
-                                                         const uint32_t* __restrict__ coff,
-                                                         const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
-    const uint32_t cc = blockIdx.x;
-    const uint32_t m = ccnt[cc], b = coff[cc];
-    if (m <= (uint32_t)kCellSortLds) return;
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) dst[b + i] = src[b + i];
+// Candidate record of a cell position (64 bytes, read in sequence by the pair search):
+// the interval start, the helix values the prefilter compares, the prefilter radii of
+// (Xc, Yc, k, w) (rounded up to FP32) and the track index.
+struct alignas(64) CRec {
+    double lo, Xc, Yc, k, w;
+    float r[4];
+    uint32_t idx, pad;
+};
+
+__global__ __launch_bounds__(kBlock) void k_mg_records(const uint32_t* __restrict__ n_elig,
+                                                       const CKey* __restrict__ keys, const double* __restrict__ H,
+                                                       const float* __restrict__ rad, CRec* __restrict__ rec) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= *n_elig) return;
+    const CKey key = keys[i];
+    const double* h = H + 5 * (size_t)key.k;
+    const float* r = rad + 4 * (size_t)key.k;
+    CRec c;
+    c.lo = key.lo;
+    c.Xc = h[0];
+    c.Yc = h[1];
+    c.k = h[2];
+    c.w = h[3];
+    for (int j = 0; j < 4; ++j) c.r[j] = r[j];
+    c.idx = key.k;
+    c.pad = 0;
+    rec[i] = c;
 }
 
 // ---------------------------------------------------------------- 3. same-helix test
@@ -412,18 +441,22 @@ __device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
     }
 }
 
-// One lane per track in cell order.
+// One lane per track in cell order.  The candidates of a neighbouring cell are the
+// records whose interval starts inside the lane's own interval; a candidate passing the
+// prefilter (centre window, and the marginal chi2 bounds on Xc, Yc, k and w) gets the
+// full test.
 __global__ __launch_bounds__(kBlock) void k_mg_pairs(MgArgs a, const uint32_t* __restrict__ n_elig,
-                                                     const uint32_t* __restrict__ seg, const double* __restrict__ slo,
-                                                     const uint32_t* __restrict__ coff, const uint32_t* __restrict__ cell,
-                                                     const double* __restrict__ lo, const double* __restrict__ hi,
+                                                     const CRec* __restrict__ rec, const uint32_t* __restrict__ coff,
+                                                     const uint32_t* __restrict__ cell, const double* __restrict__ hi,
                                                      const double* __restrict__ H, const double* __restrict__ CH,
                                                      int32_t* __restrict__ par, unsigned long long* __restrict__ tally) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     uint64_t tested = 0, passed = 0;
     if (i < *n_elig) {
-        const uint32_t A = seg[i], ca = cell[A];
-        const double loA = lo[A], hiA = hi[A];
+        const CRec ra = rec[i];
+        const uint32_t A = ra.idx, ca = cell[A];
+        const double loA = ra.lo, hiA = hi[A];
+        const double win = a.win;
         const int cx = (int)(ca % (uint32_t)a.nc), cy = (int)(ca / (uint32_t)a.nc);
         for (int dy = -1; dy <= 1; ++dy) {
             const int y = cy + dy;
@@ -436,16 +469,24 @@ __global__ __launch_bounds__(kBlock) void k_mg_pairs(MgArgs a, const uint32_t* _
                 // first start >= loA
                 while (b < e) {
                     const uint32_t mid = b + (e - b) / 2;
-                    if (slo[mid] < loA)
+                    if (rec[mid].lo < loA)
                         b = mid + 1;
                     else
                         e = mid;
                 }
                 e = coff[cc + 1];
-                for (uint32_t j = b; j < e && slo[j] <= hiA; ++j) {
-                    const uint32_t B = seg[j];
-                    if (B == A) continue;
+                for (uint32_t j = b; j < e; ++j) {
+                    const CRec rb = rec[j];
+                    if (!(rb.lo <= hiA)) break;
+                    const double ex = fabs(ra.Xc - rb.Xc), ey = fabs(ra.Yc - rb.Yc);
+                    const bool pre = rb.idx != A && ex <= win && ey <= win &&
+                                     ex <= (double)ra.r[0] + (double)rb.r[0] &&
+                                     ey <= (double)ra.r[1] + (double)rb.r[1] &&
+                                     fabs(ra.k - rb.k) <= (double)ra.r[2] + (double)rb.r[2] &&
+                                     fabs(ra.w - rb.w) <= (double)ra.r[3] + (double)rb.r[3];
+                    if (!pre) continue;
                     ++tested;
+                    const uint32_t B = rb.idx;
                     const uint32_t p = A < B ? A : B, q = A < B ? B : A;
                     if (same_helix(a, H + 5 * (size_t)p, CH + 15 * (size_t)p, H + 5 * (size_t)q,
                                    CH + 15 * (size_t)q)) {
@@ -534,13 +575,16 @@ struct Comp {
 // Sums over the component's hits at th (every lane ends with the same totals): chi2,
 // and with `normal` also the normal matrix (lower triangle) and gradient.  Hit f of
 // the component (members' hits concatenated) belongs to lane f mod 64.
+// The residual derivatives are jt = (-dx/r, -dy/r, -1, 0, 0) (transverse) and
+// jz = (-w dy/r^2, w dx/r^2, 0, -1, -psi) (longitudinal), so N22 = wy n, N33 = wz n and
+// N32 = N42 = 0 need no sums; the other eleven entries, the gradient and chi2 are summed.
 __device__ inline void fit_sums(const FitHit* __restrict__ fh, const Comp& cp, const double th[5], double wy,
                                 double wz, bool normal, double& chi2, double N[15], double g[5]) {
     const int lane = threadIdx.x & 63;
-    chi2 = 0.0;
-    for (int i = 0; i < 15; ++i) N[i] = 0.0;
-    for (int i = 0; i < 5; ++i) g[i] = 0.0;
-    const double tau = 2.0 * M_PI;
+    double s[17];
+#pragma unroll
+    for (int i = 0; i < 17; ++i) s[i] = 0.0;
+    const double tau = 2.0 * M_PI, itau = 1.0 / tau;
     uint32_t base = 0;
     for (uint32_t mi = 0; mi < cp.m; ++mi) {
         const int32_t t = cp.mem[mi];
@@ -552,26 +596,55 @@ __device__ inline void fit_sums(const FitHit* __restrict__ fh, const Comp& cp, c
             const double dx = h.X - th[0], dy = h.Y - th[1];
             const double r = hypot(dx, dy);
             const double d = atan2(dy, dx) - h.ps0;
-            const double ps = h.ps0 + (d - tau * rint(d / tau));
+            const double ps = h.ps0 + (d - tau * rint(d * itau));
             const double rt = r - th[2], rz = h.Z - th[3] - th[4] * ps;
-            chi2 += wy * rt * rt + wz * rz * rz;
+            s[0] += wy * rt * rt + wz * rz * rz;
             if (normal) {
-                const double jt[5] = {-dx / r, -dy / r, -1.0, 0.0, 0.0};
-                const double r2 = r * r;
-                const double jz[5] = {-th[4] * dy / r2, th[4] * dx / r2, 0.0, -1.0, -ps};
-#pragma unroll
-                for (int p = 0; p < 5; ++p) {
-                    g[p] += wy * jt[p] * rt + wz * jz[p] * rz;
-#pragma unroll
-                    for (int q = 0; q <= p; ++q) N[tri(p, q)] += wy * jt[p] * jt[q] + wz * jz[p] * jz[q];
-                }
+                const double ir = 1.0 / r;
+                const double ja = -dx * ir, jb = -dy * ir;
+                const double jc = -th[4] * dy * ir * ir, jd = th[4] * dx * ir * ir;
+                const double wzps = wz * ps;
+                s[1] += wy * ja * ja + wz * jc * jc;  // N00
+                s[2] += wy * ja * jb + wz * jc * jd;  // N10
+                s[3] += wy * jb * jb + wz * jd * jd;  // N11
+                s[4] -= wy * ja;                      // N20
+                s[5] -= wy * jb;                      // N21
+                s[6] -= wz * jc;                      // N30
+                s[7] -= wz * jd;                      // N31
+                s[8] -= wzps * jc;                    // N40
+                s[9] -= wzps * jd;                    // N41
+                s[10] += wzps;                        // N43
+                s[11] += wzps * ps;                   // N44
+                s[12] += wy * ja * rt + wz * jc * rz; // g0
+                s[13] += wy * jb * rt + wz * jd * rz; // g1
+                s[14] -= wy * rt;                     // g2
+                s[15] -= wz * rz;                     // g3
+                s[16] -= wzps * rz;                   // g4
             }
         }
     }
-    chi2 = wave_sum_d(chi2);
+    chi2 = wave_sum_d(s[0]);
     if (normal) {
-        for (int i = 0; i < 15; ++i) N[i] = wave_sum_d(N[i]);
-        for (int i = 0; i < 5; ++i) g[i] = wave_sum_d(g[i]);
+#pragma unroll
+        for (int i = 1; i < 17; ++i) s[i] = wave_sum_d(s[i]);
+        const double n = (double)base;
+        N[tri(0, 0)] = s[1];
+        N[tri(1, 0)] = s[2];
+        N[tri(1, 1)] = s[3];
+        N[tri(2, 0)] = s[4];
+        N[tri(2, 1)] = s[5];
+        N[tri(2, 2)] = wy * n;
+        N[tri(3, 0)] = s[6];
+        N[tri(3, 1)] = s[7];
+        N[tri(3, 2)] = 0.0;
+        N[tri(3, 3)] = wz * n;
+        N[tri(4, 0)] = s[8];
+        N[tri(4, 1)] = s[9];
+        N[tri(4, 2)] = 0.0;
+        N[tri(4, 3)] = s[10];
+        N[tri(4, 4)] = s[11];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = s[12 + i];
     }
 }
 
@@ -588,10 +661,18 @@ __global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __
                                                      double* __restrict__ theta, double* __restrict__ theta_cov,
                                                      double* __restrict__ chi2_out, int32_t* __restrict__ ndf_out,
                                                      unsigned long long* __restrict__ tally) {
+    // cos and sin of every sector's azimuth (the same expressions as the helix kernel's)
+    __shared__ double sec_cs[2 * 256];
+    for (int s = threadIdx.x; s < a.S; s += kBlock) {
+        const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
+        sec_cs[2 * s] = cos(al);
+        sec_cs[2 * s + 1] = sin(al);
+    }
+    __syncthreads();
     const int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
     if (k >= a.cap_tracks) return;
     const int lane = threadIdx.x & 63;
-    if (k >= n_tracks(a) || label[k] != k || !(use[k] & 1)) {  // no fit at this index
+    if (k >= n_tracks(a) || label[k] != k || gcnt[k] < 2 || !(use[k] & 1)) {  // no fit at this index
         if (lane < 5) theta[5 * (size_t)k + lane] = NAN;
         if (lane < 15) theta_cov[15 * (size_t)k + lane] = NAN;
         if (lane == 0) {
@@ -613,11 +694,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __
         for (int32_t j = j0; j < nt; j += 64) {
             const int32_t id = a.ids[o + j];
             const int s = a.sector[id];
-            const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
             const double x = (double)a.row_x[a.row[id]], y = (double)a.y[id];
+            const double ca = sec_cs[2 * s], sa = sec_cs[2 * s + 1];
             FitHit f;
-            f.X = x * cos(al) - y * sin(al);
-            f.Y = x * sin(al) + y * cos(al);
+            f.X = x * ca - y * sa;
+            f.Y = x * sa + y * ca;
             f.Z = (s >= a.sps ? -1.0 : 1.0) * (double)a.z[id];
             const double psi = atan2(f.Y - th[1], f.X - th[0]);
             double turns = 0.0;
@@ -760,9 +841,12 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     a.max_iter = mp.max_iter;
     const int64_t NC = nc * nc;
     uint8_t* use;
-    uint32_t *cell, *ccnt, *coff, *ccur, *seg, *seg2, *gcnt, *goff, *gcur, *n_elig;
+    uint32_t *cell, *ccnt, *coff, *ccur, *gcnt, *goff, *gcur, *n_elig;
     int32_t *par, *mem;
-    double *lo, *hi, *slo;
+    double *lo, *hi;
+    float* rad;
+    CKey* keys;
+    CRec* rec;
     FitHit* fh;
     unsigned long long* tally;
     void* scan;
@@ -771,11 +855,11 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     MB(ccnt, "mg_ccnt", 4 * (NC + 1));
     MB(coff, "mg_coff", 4 * (NC + 1));
     MB(ccur, "mg_ccur", 4 * (NC + 1));
-    MB(seg, "mg_seg", 4 * T);
-    MB(seg2, "mg_seg2", 4 * T);
+    MB(keys, "mg_keys", sizeof(CKey) * T);
+    MB(rec, "mg_rec", sizeof(CRec) * T);
+    MB(rad, "mg_rad", 16 * T);
     MB(lo, "mg_lo", 8 * T);
     MB(hi, "mg_hi", 8 * T);
-    MB(slo, "mg_slo", 8 * T);
     MB(par, "mg_par", 4 * T);
     MB(gcnt, "mg_gcnt", 4 * (T + 1));
     MB(goff, "mg_goff", 4 * (T + 1));
@@ -792,14 +876,14 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     fill_u32(gcur, 0u, T + 1, st);
     fill_u64((uint64_t*)tally, 0ull, T_N, st);
     const unsigned nb = nblk(T);
-    k_mg_helix<<<nb, kBlock, 0, st>>>(a, out.helix, out.helix_cov, use, cell, lo, hi, ccnt);
+    k_mg_helix<<<nb, kBlock, 0, st>>>(a, out.helix, out.helix_cov, use, cell, lo, hi, rad, ccnt);
     scan_u32(ccnt, coff, NC + 1, nullptr, n_elig, scan, st);
-    k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, seg);
-    k_mg_cell_sort<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, lo, seg, slo, tally);
-    k_mg_cell_rank<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, lo, seg, seg2, slo);
-    k_mg_cell_copy<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, seg2, seg);
+    k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, lo, keys);
+    k_mg_cell_sort<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, keys, tally);
+    k_mg_cell_sort_big<<<(unsigned)NC, 1024, 0, st>>>(ccnt, coff, keys);
+    k_mg_records<<<nb, kBlock, 0, st>>>(n_elig, keys, out.helix, rad, rec);
     k_mg_init<<<nb, kBlock, 0, st>>>(trk.cap_tracks, par);
-    k_mg_pairs<<<nb, kBlock, 0, st>>>(a, n_elig, seg, slo, coff, cell, lo, hi, out.helix, out.helix_cov, par, tally);
+    k_mg_pairs<<<nb, kBlock, 0, st>>>(a, n_elig, rec, coff, cell, hi, out.helix, out.helix_cov, par, tally);
     k_mg_label<<<nb, kBlock, 0, st>>>(a, use, par, out.label, gcnt);
     scan_u32(gcnt, goff, T, nullptr, nullptr, scan, st);
     k_mg_group<<<nb, kBlock, 0, st>>>(a, out.label, goff, gcur, mem);
