@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-pruning leg")
     ap.add_argument("--no-flags", action="store_true", help="skip the cluster-flag measurement")
     ap.add_argument("--no-compress", action="store_true", help="skip the cluster-compression measurement")
+    ap.add_argument("--no-merge", action="store_true", help="skip the track-merging measurement")
     ap.add_argument("--sector-path", action="store_true", help="time frames through tpc_track_sectors")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     return ap.parse_args()
@@ -226,6 +227,71 @@ def measure_compression(ctx, ev, ten, geom, params, trk, stream, steps: int) -> 
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_cluster": CMP_BYTES_PER_CLUSTER}}
 
 
+def particle_instances(ev, h) -> tuple[np.ndarray, np.ndarray]:
+    """Per track the majority particle of its hits (-1 for noise) and its hit count."""
+    import numpy as np
+
+    nt = len(h["n_hits"])
+    tid = np.repeat(np.arange(nt), h["n_hits"])
+    part = ev.particle[h["hit_ids"][:len(tid)]].astype(np.int64)
+    key = tid * (int(part.max()) + 2) + (part + 1)
+    u, cnt = np.unique(key, return_counts=True)
+    t_of, p_of = u // (int(part.max()) + 2), u % (int(part.max()) + 2) - 1
+    best = np.full(nt, -1, np.int64)
+    bc = np.zeros(nt, np.int64)
+    order = np.lexsort((-cnt, t_of))  # per track, most hits first
+    first = np.ones(len(order), bool)
+    first[1:] = t_of[order][1:] != t_of[order][:-1]
+    best[t_of[order][first]] = p_of[order][first]
+    bc[t_of[order][first]] = cnt[order][first]
+    return best, bc
+
+
+def measure_merge(ctx, ev, ten, geom, params, trk, stream, steps: int) -> dict:
+    """Merging and refit of the tracks just found (Sec. 4): time per call, how many tracks
+    become one, and the tracks per particle before and after for particles with a looping or
+    sector-crossing track (several instances)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1910_12214_amd import tpcca
+
+    out = ctx.merge(*ten, geom, synth.BZ, trk, params=params, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.merge(*ten, geom, synth.BZ, trk, params=params, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    c = out["counts"].cpu().numpy()
+    h = tpcca.tracks_to_host(trk)
+    nt = len(h["n_hits"])
+    lab = out["label"][:nt].cpu().numpy()
+    best, _ = particle_instances(ev, h)
+    sig = best >= 0
+    multi = np.bincount(best[sig])
+    many = np.nonzero(multi >= 2)[0]
+    before = float(multi[many].mean()) if len(many) else 0.0
+    # components per such particle after merging
+    pairs = np.unique(np.stack([best[sig], lab[sig]], 1), axis=0)
+    after_cnt = np.bincount(pairs[:, 0], minlength=len(multi))
+    after = float(after_cnt[many].mean()) if len(many) else 0.0
+    lp = np.unique(np.stack([lab[sig], best[sig]], 1), axis=0)
+    mixed = int((np.bincount(lp[:, 0]) > 1).sum()) if len(lp) else 0
+    chi2 = out["chi2"][:nt].cpu().numpy()
+    ndf = out["ndf"][:nt].cpu().numpy()
+    fit = np.isfinite(chi2) & (ndf > 0)
+    return {"value": nt / (ms * 1e-3), "unit": "tracks/s", "ms": ms, "tracks": nt, "merged_tracks": int(c[0]),
+            "of_several_pieces": int(c[1]), "pairs_tested": int(c[2]), "pairs_passed": int(c[3]),
+            "largest_cell": int(c[4]), "refit_failed": int(c[6]),
+            "particles_with_several_tracks": int(len(many)), "tracks_per_such_particle_before": before,
+            "tracks_per_such_particle_after": after, "components_mixing_particles": mixed,
+            "refit_chi2_per_ndf_median": float(np.median(chi2[fit] / ndf[fit])) if fit.any() else None}
+
+
 def measure(w, args, primary: bool):
     """Plain and pruned throughput of one workload, its stage times and roofline, the cluster
     flags of its tracks and (for events) two events in flight."""
@@ -334,6 +400,10 @@ def measure(w, args, primary: bool):
     if not args.no_compress:
         res["compression"] = measure_compression(ctx, ev, (y, z, r, s), geom, params, out, stream, args.steps)
         log("timed compression")
+    # Merging of looper legs and sector pieces, and the merged refit (Sec. 4)
+    if not args.no_merge:
+        res["merging"] = measure_merge(ctx, ev, (y, z, r, s), geom, params, out, stream, args.steps)
+        log("timed merging")
     # learned pruning: the scorer trained on events of this workload's generator if there is
     # one, else the one-sector scorer
     if not args.no_mlp:

@@ -740,7 +740,7 @@ int timed_run(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo,
 // occupancy (two waves per block: 2 x waves per SIMD).
 int autotune(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, double bz, const tpc_params_t* p,
              tpc_tracks_t* out, hipStream_t st) {
-    static const float bins[][2] = {{8.f, 8.f}, {8.f, 16.f}, {12.f, 24.f}, {16.f, 32.f}};
+    static const float bins[][2] = {{6.f, 6.f}, {8.f, 6.f}, {6.f, 8.f}, {8.f, 8.f}, {8.f, 16.f}, {12.f, 24.f}, {16.f, 32.f}};
     static const int chunks[] = {1, 2, 4};
     static const int wavess[] = {2, 3};
     Tuning best;
