@@ -292,6 +292,25 @@ def check_tracks(o: dict):
     need_gpu(o["hit_ids"], "hit_ids")
 
 
+def check_merged(out: dict, cap_tracks: int):
+    """A merge output (as ``Context.alloc_merged`` returns) large enough for cap_tracks tracks."""
+    import torch
+
+    if int(out["cap_tracks"]) < cap_tracks:
+        raise TpcError(TPC_ERR_ARG, f"merge output: cap_tracks {int(out['cap_tracks'])} below the track set's "
+                                    f"{cap_tracks}")
+    c = max(1, cap_tracks)
+    arrays = (("label", torch.int32, 1), ("n_members", torch.int32, 1), ("helix", torch.float64, 5),
+              ("helix_cov", torch.float64, 15), ("theta", torch.float64, 5), ("theta_cov", torch.float64, 15),
+              ("chi2", torch.float64, 1), ("ndf", torch.int32, 1))
+    for k, dt, per in arrays:
+        need(out[k], k, dt, min_numel=per * c, on_gpu=False)
+    need(out["counts"], "counts", torch.int64, min_numel=len(MG_COUNTS), on_gpu=False)
+    for k, *_ in arrays:
+        need_gpu(out[k], k)
+    need_gpu(out["counts"], "counts")
+
+
 def _stream(stream) -> int:
     import torch
 
@@ -544,20 +563,11 @@ class Context:
               mparams: dict | None = None, out: dict | None = None, stream=None) -> dict:
         """Merge the pieces of one helix among ``tracks`` (the layout ``alloc_tracks`` returns) and
         refit every merged track over its hits (clusters as CUDA tensors, as for ``track``)."""
-        import torch
-
         cl = self._clusters(y, z, row, sector)
         check_tracks(tracks)
         if out is None:
             out = self.alloc_merged(int(tracks["cap_tracks"]))
-        c = max(1, int(tracks["cap_tracks"]))
-        if int(out["cap_tracks"]) < int(tracks["cap_tracks"]):
-            raise TpcError(TPC_ERR_ARG, "merge output: cap_tracks below the track set's")
-        for k, dt, per in (("label", torch.int32, 1), ("n_members", torch.int32, 1), ("helix", torch.float64, 5),
-                           ("helix_cov", torch.float64, 15), ("theta", torch.float64, 5),
-                           ("theta_cov", torch.float64, 15), ("chi2", torch.float64, 1), ("ndf", torch.int32, 1)):
-            need(out[k], k, dt, min_numel=per * c)
-        need(out["counts"], "counts", torch.int64, min_numel=len(MG_COUNTS))
+        check_merged(out, int(tracks["cap_tracks"]))
         g, _keep = make_geometry(geom)
         p = make_params(params)
         mp = self.merge_params(mparams)

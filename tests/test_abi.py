@@ -43,3 +43,15 @@ def test_binding_matches_header():
     d = tpcca.default_params()
     for k, v in synth.TRACKER_PARAMS.items():
         assert d[k] == pytest.approx(v), k
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_merge_defaults_are_the_oracle_readings():
+    """tpc_merge_params_default holds the constants of the merging oracle's reading (a host call)."""
+    from oracle import merge as om
+    from paper_1910_12214_amd import tpcca
+
+    mp = tpcca.Context.merge_params()
+    assert (mp.rho_max, mp.centre_window, mp.chi2_max, mp.phase_sigmas, mp.phase_floor, mp.max_turns) == \
+        (om.RHO_MAX, om.CENTRE_WINDOW, om.CHI2_HELIX, om.PHASE_SIGMAS, om.PHASE_FLOOR, om.MAX_TURNS)
+    assert mp.sectors_per_side == 18 and mp.max_iter == 50

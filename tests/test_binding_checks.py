@@ -69,3 +69,20 @@ def test_row_indices_are_checked():
     rejects(tpcca.check_rows, torch.tensor([0, 5, 10], dtype=torch.int32), 10, "idx", match=r"\[0, 10\)")
     rejects(tpcca.check_rows, torch.tensor([-1], dtype=torch.int32), 10, "idx")
     tpcca.check_rows(torch.tensor([0, 9], dtype=torch.int32), 10, "idx")
+
+
+def test_merge_outputs_are_checked():
+    ct = 8
+    f64, i32 = dict(dtype=torch.float64), dict(dtype=torch.int32)
+    good = dict(cap_tracks=ct, label=torch.zeros(ct, **i32), n_members=torch.zeros(ct, **i32),
+                helix=torch.zeros(ct, 5, **f64), helix_cov=torch.zeros(ct, 15, **f64),
+                theta=torch.zeros(ct, 5, **f64), theta_cov=torch.zeros(ct, 15, **f64), chi2=torch.zeros(ct, **f64),
+                ndf=torch.zeros(ct, **i32), counts=torch.zeros(len(tpcca.MG_COUNTS), dtype=torch.int64))
+    rejects(tpcca.check_merged, good, ct, match="must be on a GPU")  # complete, but host memory
+    rejects(tpcca.check_merged, good, ct + 1, match="below the track set's")
+    for k, bad, match in (("helix", torch.zeros(ct, 4, **f64), "helix: 32 elements"),
+                          ("theta_cov", torch.zeros(ct, 15, dtype=torch.float32), "theta_cov: dtype"),
+                          ("label", torch.zeros(ct, dtype=torch.int64), "label: dtype"),
+                          ("counts", torch.zeros(3, dtype=torch.int64), "counts: 3 elements"),
+                          ("chi2", torch.zeros(2 * ct, **f64)[::2], "chi2: must be contiguous")):
+        rejects(tpcca.check_merged, dict(good, **{k: bad}), ct, match=match)
