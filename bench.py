@@ -30,7 +30,10 @@ ALG_BYTES_PER_CLUSTER = {"grid": 32.0, "neighbours": 32.0, "clean_starts": 24.0,
 # row, sector, charge and widths read (14 B), its quantised position written and read (16 B), its
 # five symbols written as values and read back (40 B), written as symbols and read by the histogram
 # and the coder (30 B), and about 4 coded bytes written: 104 B.
-CMP_BYTES_PER_CLUSTER = 104.0
+CMP_BYTES_PER_CLUSTER = 104
+# Track merging and refit, minimum traffic: 96 B in and 340 B out per track, 14 B per hit of a merged track.
+MERGE_BYTES_PER_TRACK = 436
+MERGE_BYTES_PER_HIT = 14.0
 # Cluster flags (Sec. 4): the grid build (32 B per cluster) plus, per cluster, its record read by
 # the tube walk (16 B), its key written and read (16 B), two byte arrays written and read (4 B)
 # and the flag byte written: 69 B per cluster at minimum.
@@ -284,12 +287,21 @@ def measure_merge(ctx, ev, ten, geom, params, trk, stream, steps: int) -> dict:
     chi2 = out["chi2"][:nt].cpu().numpy()
     ndf = out["ndf"][:nt].cpu().numpy()
     fit = np.isfinite(chi2) & (ndf > 0)
+    # algorithmic bytes: per track its state, covariance, reference and hit-list entries in (96 B) and
+    # the label, member count, helix, refit and covariances out (340 B); per hit of a merged track its
+    # id and cluster (14 B), read once
+    n_hits_merged = int(h["n_hits"][np.isin(lab, np.nonzero(np.bincount(lab, minlength=nt) >= 2)[0])].sum())
+    alg = MERGE_BYTES_PER_TRACK * nt + MERGE_BYTES_PER_HIT * n_hits_merged
+    ach = alg / (ms * 1e-3) / 1e9
     return {"value": nt / (ms * 1e-3), "unit": "tracks/s", "ms": ms, "tracks": nt, "merged_tracks": int(c[0]),
             "of_several_pieces": int(c[1]), "pairs_tested": int(c[2]), "pairs_passed": int(c[3]),
             "largest_cell": int(c[4]), "refit_failed": int(c[6]),
             "particles_with_several_tracks": int(len(many)), "tracks_per_such_particle_before": before,
             "tracks_per_such_particle_after": after, "components_mixing_particles": mixed,
-            "refit_chi2_per_ndf_median": float(np.median(chi2[fit] / ndf[fit])) if fit.any() else None}
+            "refit_chi2_per_ndf_median": float(np.median(chi2[fit] / ndf[fit])) if fit.any() else None,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "traffic": None, "alg_bytes_per_track": MERGE_BYTES_PER_TRACK,
+                         "alg_bytes_per_merged_hit": MERGE_BYTES_PER_HIT}}
 
 
 def measure(w, args, primary: bool):
