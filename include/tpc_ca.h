@@ -443,8 +443,9 @@ void tpc_merge_params_default(tpc_merge_params_t* p);
  * sector, x_ref, state and cov) over the clusters they index.  A track whose entries
  * are unusable (sector out of range, hits beyond cap_hits, ids out of range or of a
  * cluster with row or sector out of range) is a component of its own without a fit.
- * Enqueued on `stream`; no host synchronisation.  Returns TPC_ERR_ARG for bad
- * arguments (message in tpc_last_error). */
+ * bz_tesla must be finite and nonzero (helix centres need a curvature).  Enqueued on
+ * `stream`; no host synchronisation (a first call with new geometry uploads its tables
+ * synchronously).  Returns TPC_ERR_ARG for bad arguments (message in tpc_last_error). */
 int tpc_merge(tpc_ctx_t* ctx, const tpc_clusters_t* clusters, const tpc_geometry_t* geom, double bz_tesla,
               const tpc_params_t* params, const tpc_merge_params_t* mparams, const tpc_tracks_t* tracks,
               tpc_merged_t* out, void* stream);

@@ -131,18 +131,14 @@ def test_smeared_loopers_equal_oracle(ctx):
         f"{np.nansum(m['chi2']) / m['ndf'][m['ndf'] > 0].sum():.3f}")
 
 
-def test_pbpb_event_gpu_tracks_sampled(ctx):
-    """The full Pb-Pb event with the GPU's own tracks: helices of every track; for sampled tracks,
-    every track the oracle's same-helix test joins to it (searched by brute force) carries its label;
-    sampled merged tracks are connected by the oracle's relation and labelled by their lowest
-    member; their refits equal the oracle's."""
+def sampled_merge_check(ctx, ev, geom, trk, n_samples, n_components, seed):
+    """Merge the GPU's own tracks; check every track's helix against the oracle's, that every oracle
+    partner of sampled tracks (searched by brute force over the tracks in its centre window) carries
+    its label, and that sampled merged tracks are connected by the oracle's relation, labelled by
+    their lowest member and refit as the oracle refits them."""
     from paper_1910_12214_amd import tpcca
 
-    w = synth.PBPB_EVENT
-    ev = synth.generate(w)
-    geom = synth.geometry(w)
     ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
-    trk = ctx.track(*ten, geom, synth.BZ, P)
     h = tpcca.tracks_to_host(trk)
     nt = len(h["n_hits"])
     out = ctx.merge(*ten, geom, synth.BZ, trk, params=P)
@@ -151,24 +147,27 @@ def test_pbpb_event_gpu_tracks_sampled(ctx):
     H, CH = om.helix_params(h["state"], h["x_ref"], h["sector"], cov, synth.BZ)
     scale = np.abs(H).max(axis=0)
     assert np.allclose(m["helix"], H, rtol=1e-10, atol=1e-11 * scale)
-    rng = np.random.default_rng(5)
+    rng = np.random.default_rng(seed)
     ok = np.all(np.isfinite(H), axis=1) & (1.0 / H[:, 2] <= om.RHO_MAX)
     lab = m["label"]
-    for i in rng.choice(nt, 200, replace=False):
+    order = np.argsort(H[:, 0])  # tracks by Xc, for the window search
+    xs = H[order, 0]
+    for i in rng.choice(nt, n_samples, replace=False):
         if not ok[i]:
             assert lab[i] == i
             continue
-        near = np.nonzero(ok & (np.abs(H[:, 0] - H[i, 0]) <= om.CENTRE_WINDOW) &
-                          (np.abs(H[:, 1] - H[i, 1]) <= om.CENTRE_WINDOW))[0]
+        lo, hi = np.searchsorted(xs, H[i, 0] - om.CENTRE_WINDOW, "left"), np.searchsorted(xs, H[i, 0] + om.CENTRE_WINDOW, "right")
+        near = order[lo:hi]
+        near = near[ok[near] & (np.abs(H[near, 1] - H[i, 1]) <= om.CENTRE_WINDOW)]
         for j in near:
             if j != i:
                 a, b = min(i, j), max(i, j)
                 if om.compatible(H[a], CH[a], H[b], CH[b]):
                     assert lab[j] == lab[i], (i, j)
     roots = np.unique(lab)
-    multi = [g for g in roots if m["n_members"][g] >= 2]
+    multi = roots[m["n_members"][roots] >= 2]
     X, Y, Z = om.hit_points(ev.y, ev.z, ev.row, ev.sector, geom["row_x"])
-    for g in rng.choice(multi, min(40, len(multi)), replace=False):
+    for g in rng.choice(multi, min(n_components, len(multi)), replace=False):
         mem = np.nonzero(lab == g)[0]
         assert mem.min() == g
         # connected through the oracle's relation
@@ -183,9 +182,35 @@ def test_pbpb_event_gpu_tracks_sampled(ctx):
         ids = np.concatenate([h["hit_ids"][h["hit_offset"][k]:h["hit_offset"][k] + h["n_hits"][k]] for k in mem])
         hh = np.concatenate([np.repeat(H[k:k + 1], h["n_hits"][k], axis=0) for k in mem])
         check_refit(g, ids, hh, X, Y, Z, H, m, P["sigma_y"], P["sigma_z"])
-    c = out["counts"].cpu().numpy()
+    return nt, out["counts"].cpu().numpy()
+
+
+def test_pbpb_event_gpu_tracks_sampled(ctx):
+    """The full Pb-Pb event with the GPU's own tracks (sampled checks, see sampled_merge_check)."""
+    w = synth.PBPB_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    trk = ctx.track(*[dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)], geom, synth.BZ, P)
+    nt, c = sampled_merge_check(ctx, ev, geom, trk, 200, 40, 5)
     say(f"[merge] Pb-Pb event: {nt} tracks -> {c[0]} ({c[1]} of several pieces), {c[2]} pairs tested, "
         f"{c[3]} passed, largest cell {c[4]}, refits failed {c[6]}")
+
+
+def test_pbpb_timeframe_gpu_tracks_sampled(ctx):
+    """The full 570-collision Pb-Pb frame (72.8M clusters) tracked in one launch, its 1.27M tracks
+    merged: sampled checks against the oracle, including cells too long for LDS."""
+    w = synth.PBPB_TIMEFRAME
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    trk = ctx.alloc_tracks(ev.n // 8, ev.n)
+    ctx.set_tuning(dict(bin_y=8.0, bin_z=8.0, tracklet_chunk=1, blocks_per_cu=6, waves_per_simd=3))
+    ctx.track(*ten, geom, synth.BZ, P, out=trk, timeframe=True)
+    ctx.set_tuning(None)
+    nt, c = sampled_merge_check(ctx, ev, geom, trk, 100, 20, 7)
+    assert c[5] >= 1  # some cells exceeded the LDS sort
+    say(f"[merge] Pb-Pb frame: {nt} tracks -> {c[0]} ({c[1]} of several pieces), {c[2]} pairs tested, "
+        f"{c[3]} passed, largest cell {c[4]} ({c[5]} cells sorted in global memory), refits failed {c[6]}")
 
 
 def test_malformed_and_empty_track_sets(ctx):
