@@ -531,31 +531,56 @@ __global__ __launch_bounds__(kBlock) void k_mg_group(MgArgs a, const int32_t* __
     mem[goff[r] + atomicAdd(&gcur[r], 1u)] = k;
 }
 
-// Members of each component in ascending index (insertion sort; components are small).
+// Members of each component in ascending index: insertion sort by one lane for components
+// of at most kSmallComp members (nearly all); larger ones are listed for a workgroup sort.
+constexpr uint32_t kSmallComp = 64;
+
 __global__ __launch_bounds__(kBlock) void k_mg_sort_members(MgArgs a, const int32_t* __restrict__ label,
                                                             const uint32_t* __restrict__ gcnt,
                                                             const uint32_t* __restrict__ goff, int32_t* __restrict__ mem,
-                                                            int32_t* __restrict__ n_members,
+                                                            int32_t* __restrict__ n_members, uint32_t* __restrict__ big,
+                                                            uint32_t* __restrict__ n_big,
                                                             unsigned long long* __restrict__ tally) {
     const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     const bool root = k < n_tracks(a) && label[k] == k;
     uint32_t m = 0;
     if (root) {
         m = gcnt[k];
-        int32_t* p = mem + goff[k];
-        for (uint32_t i = 1; i < m; ++i) {
-            const int32_t v = p[i];
-            uint32_t j = i;
-            while (j > 0 && p[j - 1] > v) {
-                p[j] = p[j - 1];
-                --j;
+        if (m > kSmallComp) {
+            big[atomicAdd(n_big, 1u)] = (uint32_t)k;
+        } else {
+            int32_t* p = mem + goff[k];
+            for (uint32_t i = 1; i < m; ++i) {
+                const int32_t v = p[i];
+                uint32_t j = i;
+                while (j > 0 && p[j - 1] > v) {
+                    p[j] = p[j - 1];
+                    --j;
+                }
+                p[j] = v;
             }
-            p[j] = v;
         }
     }
     if (k < a.cap_tracks) n_members[k] = root ? (int32_t)m : 0;
     wave_tally(tally, T_COMPONENTS, root ? 1u : 0u);
     wave_tally(tally, T_MERGED, m >= 2 ? 1u : 0u);
+}
+
+struct IntLess {
+    __device__ bool operator()(int32_t p, int32_t q) const { return p < q; }
+};
+
+// The listed large components, one workgroup each (bitonic sort in global memory).
+__global__ __launch_bounds__(1024) void k_mg_sort_big(const uint32_t* __restrict__ big,
+                                                      const uint32_t* __restrict__ n_big,
+                                                      const uint32_t* __restrict__ gcnt,
+                                                      const uint32_t* __restrict__ goff, int32_t* __restrict__ mem) {
+    const uint32_t nb = *n_big;
+    for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const uint32_t k = big[i];
+        flip_bitonic_sort(mem + goff[k], gcnt[k], IntLess{});
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- 5. refit
@@ -841,7 +866,7 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     a.max_iter = mp.max_iter;
     const int64_t NC = nc * nc;
     uint8_t* use;
-    uint32_t *cell, *ccnt, *coff, *ccur, *gcnt, *goff, *gcur, *n_elig;
+    uint32_t *cell, *ccnt, *coff, *ccur, *gcnt, *goff, *gcur, *n_elig, *big;
     int32_t *par, *mem;
     double *lo, *hi;
     float* rad;
@@ -865,11 +890,13 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     MB(goff, "mg_goff", 4 * (T + 1));
     MB(gcur, "mg_gcur", 4 * (T + 1));
     MB(mem, "mg_mem", 4 * T);
+    MB(big, "mg_big", 4 * T);
     MB(n_elig, "mg_nelig", 16);
     MB(fh, "mg_fithits", sizeof(FitHit) * NH);
     MB(tally, "mg_tally", 8 * T_N);
     int64_t sn = NC + 1 > T + 1 ? NC + 1 : T + 1;
     MB(scan, "mg_scan", scan_scratch_bytes(sn));
+    fill_u32(n_elig, 0u, 4, st);  // [0] eligible tracks (scan total), [1] large components
     fill_u32(ccnt, 0u, NC + 1, st);
     fill_u32(ccur, 0u, NC + 1, st);
     fill_u32(gcnt, 0u, T + 1, st);
@@ -887,7 +914,8 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     k_mg_label<<<nb, kBlock, 0, st>>>(a, use, par, out.label, gcnt);
     scan_u32(gcnt, goff, T, nullptr, nullptr, scan, st);
     k_mg_group<<<nb, kBlock, 0, st>>>(a, out.label, goff, gcur, mem);
-    k_mg_sort_members<<<nb, kBlock, 0, st>>>(a, out.label, gcnt, goff, mem, out.n_members, tally);
+    k_mg_sort_members<<<nb, kBlock, 0, st>>>(a, out.label, gcnt, goff, mem, out.n_members, big, n_elig + 1, tally);
+    k_mg_sort_big<<<256, 1024, 0, st>>>(big, n_elig + 1, gcnt, goff, mem);
     k_mg_refit<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, use, out.label, gcnt, goff, mem, out.helix, fh,
                                                          out.theta, out.theta_cov, out.chi2, out.ndf, tally);
     k_mg_counts<<<1, 64, 0, st>>>(tally, out.counts);

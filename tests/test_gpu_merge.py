@@ -283,3 +283,30 @@ def test_cell_longer_than_the_lds_sort(ctx):
             assert not om.compatible(H[i], CH[i], H[i + 2], CH[i + 2])
     torch.cuda.synchronize()
     say(f"[merge] one cell of {nt} tracks: {c[0]} merged tracks")
+
+
+def test_large_component_is_deterministic(ctx):
+    """300 copies of one track form one merged track (its members sorted by the workgroup path for
+    components beyond 64 members): labels, member count, and a refit bit-identical between runs."""
+    import torch
+
+    w = synth.SECTOR_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    nt = 300
+    state = np.tile(np.array([1.5, 40.0, 0.2, 0.3, 2.0], np.float32), (nt, 1))
+    cov = np.zeros((nt, 15), np.float32)
+    cov[:, [0, 2, 5, 9, 14]] = [0.01, 0.01, 1e-6, 1e-6, 1e-4]
+    t = {"off": (10 * np.arange(nt)).astype(np.int32), "nh": np.full(nt, 10, np.int32),
+         "hits": np.tile(np.arange(10, dtype=np.int32), nt), "sector": np.zeros(nt, np.int32),
+         "x_ref": np.full(nt, 100.0, np.float32), "state": state}
+    d = tracks_to_device(t)
+    d["cov"] = dev(cov)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    r1 = host(ctx.merge(*ten, geom, synth.BZ, d, params=P), nt)
+    r2 = host(ctx.merge(*ten, geom, synth.BZ, d, params=P), nt)
+    assert np.all(r1["label"] == 0) and r1["n_members"][0] == nt
+    for k in ("theta", "theta_cov", "chi2"):
+        assert np.array_equal(r1[k], r2[k], equal_nan=True), k
+    assert r1["ndf"][0] == 2 * 10 * nt - 5
+    torch.cuda.synchronize()
