@@ -340,7 +340,7 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     // a2 neighbours (a3: with the learned scorer fused), a4/a5 cleaning and starts
     if (mlp_q)
         neighbours_mlp(g, pr.kp, s.hits, s.bin_off, n, s.counters, mlp_q, s.up, s.dn, s.nb_ovf, s.nb_cand, s.nb_nund,
-                       s.nb_wrec, st);
+                       s.nb_wrec, st, c->aux_stream, c->ev_fork, c->ev_join);
     else
         find_neighbours(g, pr.kp, s.hits, s.bin_off, s.row_off, n, s.counters, s.up, s.dn, nullptr, s.counters, st);
     mk.mark();
@@ -420,6 +420,11 @@ int tpc_ctx_create(tpc_ctx_t** out, int device) {
         c->n_cu = prop.multiProcessorCount;
         c->arch = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
     }
+    // the auxiliary stream (default priority) and its fork/join events; without them the
+    // chain simply runs on one stream
+    if (hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess) c->aux_stream = nullptr;
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) c->ev_fork = nullptr;
+    if (hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) c->ev_join = nullptr;
     *out = c;
     return TPC_OK;
 }
@@ -435,6 +440,9 @@ void tpc_ctx_destroy(tpc_ctx_t* c) {
     for (auto& kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 

@@ -125,6 +125,10 @@ struct tpc_ctx {
     std::string arch;                                  // device architecture and CU count (cache key)
     std::map<std::string, tpc::GraphEntry> graphs;
     hipStream_t own_stream = nullptr;
+    // second stream for work that can run beside the main chain (the scorer's fallback
+    // waves), joined back through the two events; created on first use
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // geometry tables already on the device (key of the last upload)
     std::string geo_key;
     uint64_t buf_gen = 0;  // bumped whenever a scratch buffer moves (invalidates captured graphs)
@@ -253,9 +257,13 @@ void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hip
 // ovf: [nb_overflow_entries(n_max)] wave indices (counted in counters[C_NB_OVF]);
 // cand: [nb_cand_entries(n_max)] 16-byte candidate records; nund: [n_max];
 // wrec: [nb_overflow_entries(n_max)]
+// aux, ev_fork, ev_join: a second stream on which the fallback waves run beside the
+// scoring kernel (forked after the candidate kernel, joined before returning), or null
+// for one stream.
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                     uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, void* cand,
-                    uint32_t* nund, uint32_t* wrec, hipStream_t s);
+                    uint32_t* nund, uint32_t* wrec, hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                    hipEvent_t ev_join);
 size_t nb_overflow_entries(int64_t n_max);
 size_t nb_cand_entries(int64_t n_max);
 void triplet_count(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,

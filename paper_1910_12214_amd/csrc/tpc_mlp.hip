@@ -1098,16 +1098,27 @@ void mlp_infer(const float* q, const float* feats, int64_t n, float* logits, hip
 
 void neighbours_mlp(const GridDesc& g, const KParams& kp, const Hit* hits, const uint32_t* bin_off, int64_t n_max,
                     uint32_t* counters, const float* q, int32_t* up, int32_t* dn, uint32_t* ovf, void* cand,
-                    uint32_t* nund, uint32_t* wrec, hipStream_t s) {
+                    uint32_t* nund, uint32_t* wrec, hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                    hipEvent_t ev_join) {
     const int64_t waves = (n_max + 63) / 64;
     const unsigned nb = (unsigned)((waves + kPW - 1) / kPW > 0 ? (waves + kPW - 1) / kPW : 1);
     const uint32_t seg_cap = (uint32_t)(nb_cand_entries(n_max) / kTallyLines);
     k_nb_cand<<<blocks(n_max), kBlock, 0, s>>>(g, kp, hits, bin_off, counters, (Cand*)cand, seg_cap, nund, wrec, up,
                                                 dn, ovf);
+    // Waves whose candidates overflowed the list (dense noise near the inner rows of a time
+    // frame) are enumerated per lane by the fallback, grid-stride over the overflow list; it
+    // writes other hits' links than the scoring kernel, so the two run side by side when a
+    // second stream is given (a few heavy waves make the fallback a long tail).
+    const bool fork = aux && ev_fork && ev_join;
+    hipStream_t sf = s;
+    if (fork && hipEventRecord(ev_fork, s) == hipSuccess && hipStreamWaitEvent(aux, ev_fork, 0) == hipSuccess) sf = aux;
+    k_nb_mlp_fallback<<<1024, 64 * kNbWaves, 0, sf>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, ovf, up, dn);
     k_nb_score<<<nb, 64 * kPW, 0, s>>>(g, kp, hits, counters, (const uint8_t*)q, (const Cand*)cand, nund, wrec, up,
                                        dn);
-    // waves whose candidates overflowed the list (normally none): grid-stride over the overflow list
-    k_nb_mlp_fallback<<<64, 64 * kNbWaves, 0, s>>>(g, kp, hits, bin_off, counters, (const uint8_t*)q, ovf, up, dn);
+    if (sf != s) {
+        (void)hipEventRecord(ev_join, aux);
+        (void)hipStreamWaitEvent(s, ev_join, 0);
+    }
 }
 
 size_t nb_overflow_entries(int64_t n_max) { return (size_t)((n_max + 63) / 64 + 1); }
