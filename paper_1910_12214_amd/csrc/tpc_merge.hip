@@ -25,10 +25,12 @@
 //     smaller index (a root is linked under the smaller root by compare-and-swap), so
 //     each root is the lowest index of its component whatever the order in which the
 //     pairs are found.
-//  5. refit: members are grouped by label in ascending index and one wave fits the hits
-//     of each merged track (two or more members): Gauss-Newton on (Xc, Yc, rho, z0, w),
-//     lanes over hits, normal equations summed across the wave in a fixed order, each
-//     step halved until chi2 does not grow.
+//  5. refit: members are grouped by label in ascending index; the roots of merged tracks
+//     (two or more members) are listed, those with many hits first, each with a range of
+//     its own for its hits packed together.  Persistent waves take the listed components
+//     one at a time: Gauss-Newton on (Xc, Yc, rho, z0, w), lanes over hits, normal
+//     equations summed across the wave in a fixed order, each step halved until chi2 does
+//     not grow.
 //
 // Phase bound.  The test takes m = round(dz0 / p) turns, p = pi (wA + wB), rejects
 // |m| > M, and passes when (dz0 - m p)^2 <= n^2 var with var = CA_z0 + CB_z0 +
@@ -71,7 +73,7 @@ struct MgArgs {
     int max_iter;
 };
 
-enum MgTally { T_PAIRS = 0, T_PASSED, T_BIG_CELLS, T_FAILED, T_MERGED, T_COMPONENTS, T_MAX_CELL, T_N };
+enum MgTally { T_PAIRS = 0, T_PASSED, T_BIG_CELLS, T_FAILED, T_MERGED, T_COMPONENTS, T_MAX_CELL, T_FIT_HITS, T_N };
 
 __device__ inline int32_t n_tracks(const MgArgs& a) {
     const int32_t c = a.tcounts[TPC_CNT_TRACKS];
@@ -111,6 +113,20 @@ __device__ inline void wave_tally(unsigned long long* tally, int t, uint64_t v) 
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(&tally[t], (unsigned long long)v);
+}
+
+// Exclusive prefix sum of v over the wave's lanes (lane order); total gets the wave's sum.
+// Every lane of the wave must call it.
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t s = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(s, d, 64);
+        if (lane >= d) s += t;
+    }
+    total = __shfl(s, 63, 64);
+    return s - v;
 }
 
 // Solves A x = b (n x n, row-major, overwritten) by elimination with partial pivoting
@@ -531,25 +547,49 @@ __global__ __launch_bounds__(kBlock) void k_mg_group(MgArgs a, const int32_t* __
     mem[goff[r] + atomicAdd(&gcur[r], 1u)] = k;
 }
 
+// ---------------------------------------------------------------- 5. refit: the list
+// Per hit of a component being fitted: its global position and the angle unwrapped at
+// the start.  A component's hits are packed together (members in ascending index, each
+// member's hits in its list order) from its item's hb on.
+struct alignas(32) FitHit {
+    double X, Y, Z, ps0;
+};
+
+// One component to fit: its root, its hit count and where its packed hits start.
+struct FitItem {
+    int32_t k;
+    uint32_t nhit;
+    uint64_t hb;
+};
+
+// Components of at least this many hits are fitted first (listed from the front of the
+// fit list, the others from its back).
+constexpr uint32_t kLargeFit = 1024;
+
 // Members of each component in ascending index: insertion sort by one lane for components
 // of at most kSmallComp members (nearly all); larger ones are listed for a workgroup sort.
+// Roots of components of two or more usable members are listed for the refit with their
+// packed hit range; every other track below the track count gets the no-fit outputs.
 constexpr uint32_t kSmallComp = 64;
 
-__global__ __launch_bounds__(kBlock) void k_mg_sort_members(MgArgs a, const int32_t* __restrict__ label,
-                                                            const uint32_t* __restrict__ gcnt,
-                                                            const uint32_t* __restrict__ goff, int32_t* __restrict__ mem,
-                                                            int32_t* __restrict__ n_members, uint32_t* __restrict__ big,
-                                                            uint32_t* __restrict__ n_big,
-                                                            unsigned long long* __restrict__ tally) {
+__global__ __launch_bounds__(kBlock) void k_mg_sort_members(
+    MgArgs a, const uint8_t* __restrict__ use, const int32_t* __restrict__ label, const uint32_t* __restrict__ gcnt,
+    const uint32_t* __restrict__ goff, int32_t* __restrict__ mem, int32_t* __restrict__ n_members,
+    uint32_t* __restrict__ big, uint32_t* __restrict__ n_big, FitItem* __restrict__ fit, uint32_t* __restrict__ n_fit,
+    double* __restrict__ theta, double* __restrict__ theta_cov, double* __restrict__ chi2_out,
+    int32_t* __restrict__ ndf_out, unsigned long long* __restrict__ tally) {
     const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    const bool root = k < n_tracks(a) && label[k] == k;
+    const int lane = threadIdx.x & 63;
+    const bool in = k < n_tracks(a);
+    const bool root = in && label[k] == k;
     uint32_t m = 0;
+    uint64_t hits = 0;
     if (root) {
         m = gcnt[k];
+        int32_t* p = mem + goff[k];
         if (m > kSmallComp) {
             big[atomicAdd(n_big, 1u)] = (uint32_t)k;
         } else {
-            int32_t* p = mem + goff[k];
             for (uint32_t i = 1; i < m; ++i) {
                 const int32_t v = p[i];
                 uint32_t j = i;
@@ -560,6 +600,35 @@ __global__ __launch_bounds__(kBlock) void k_mg_sort_members(MgArgs a, const int3
                 p[j] = v;
             }
         }
+        if (m >= 2 && (use[k] & 1))
+            for (uint32_t i = 0; i < m; ++i) hits += (uint64_t)a.nh[p[i]];
+    }
+    // more hits than 2^31 in one component only with overlapping hit lists: no fit
+    const bool fitted = root && m >= 2 && (use[k] & 1) && hits < (1ull << 31);
+    uint32_t tot;
+    const uint32_t pre = wave_excl_scan(fitted ? (uint32_t)hits : 0u, tot);
+    const bool large = fitted && hits >= kLargeFit;
+    const uint64_t bl = __ballot(large), bs = __ballot(fitted && !large);
+    unsigned long long hb0 = 0;
+    uint32_t l0 = 0, s0 = 0;
+    if (lane == 0) {
+        if (tot) hb0 = atomicAdd(&tally[T_FIT_HITS], (unsigned long long)tot);
+        if (bl) l0 = atomicAdd(&n_fit[0], (uint32_t)__popcll(bl));
+        if (bs) s0 = atomicAdd(&n_fit[1], (uint32_t)__popcll(bs));
+    }
+    hb0 = __shfl(hb0, 0, 64);
+    l0 = __shfl(l0, 0, 64);
+    s0 = __shfl(s0, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (fitted) {
+        const uint32_t slot = large ? l0 + (uint32_t)__popcll(bl & below)
+                                    : (uint32_t)a.cap_tracks - 1u - (s0 + (uint32_t)__popcll(bs & below));
+        fit[slot] = FitItem{k, (uint32_t)hits, (uint64_t)hb0 + pre};
+    } else if (in) {  // no fit at this index
+        for (int p = 0; p < 5; ++p) theta[5 * (size_t)k + p] = NAN;
+        for (int i = 0; i < 15; ++i) theta_cov[15 * (size_t)k + i] = NAN;
+        chi2_out[k] = NAN;
+        ndf_out[k] = 0;
     }
     if (k < a.cap_tracks) n_members[k] = root ? (int32_t)m : 0;
     wave_tally(tally, T_COMPONENTS, root ? 1u : 0u);
@@ -583,86 +652,67 @@ __global__ __launch_bounds__(1024) void k_mg_sort_big(const uint32_t* __restrict
     }
 }
 
-// ---------------------------------------------------------------- 5. refit
-// Per hit of a component being fitted, stored at the hit's own place in the track set's
-// hit list (inside cap_hits for every usable track, so no separate offsets are needed).
-struct alignas(32) FitHit {
-    double X, Y, Z, ps0;  // global position and the angle unwrapped at the start
-};
-
-// Members of one component (ascending index) and where their hits are.
-struct Comp {
-    const int32_t* mem;
-    uint32_t m;
-    const int32_t *off, *nh;
-};
-
-// Sums over the component's hits at th (every lane ends with the same totals): chi2,
-// and with `normal` also the normal matrix (lower triangle) and gradient.  Hit f of
-// the component (members' hits concatenated) belongs to lane f mod 64.
+// ---------------------------------------------------------------- 5. refit: the fit
+// Sums over a component's n packed hits at th (every lane ends with the same totals):
+// chi2, and with `normal` also the normal matrix (lower triangle) and gradient.  Hit f
+// belongs to lane f mod 64, which also wrote it.
 // The residual derivatives are jt = (-dx/r, -dy/r, -1, 0, 0) (transverse) and
 // jz = (-w dy/r^2, w dx/r^2, 0, -1, -psi) (longitudinal), so N22 = wy n, N33 = wz n and
 // N32 = N42 = 0 need no sums; the other eleven entries, the gradient and chi2 are summed.
-__device__ inline void fit_sums(const FitHit* __restrict__ fh, const Comp& cp, const double th[5], double wy,
+__device__ inline void fit_sums(const FitHit* __restrict__ fh, uint32_t n, const double th[5], double wy,
                                 double wz, bool normal, double& chi2, double N[15], double g[5]) {
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63;
     double s[17];
 #pragma unroll
     for (int i = 0; i < 17; ++i) s[i] = 0.0;
     const double tau = 2.0 * M_PI, itau = 1.0 / tau;
-    uint32_t base = 0;
-    for (uint32_t mi = 0; mi < cp.m; ++mi) {
-        const int32_t t = cp.mem[mi];
-        const int32_t o = cp.off[t], nt = cp.nh[t];
-        const int32_t j0 = (int32_t)(((uint32_t)lane + 64u - (base & 63u)) & 63u);
-        base += (uint32_t)nt;
-        for (int32_t j = j0; j < nt; j += 64) {
-            const FitHit h = fh[o + j];
-            const double dx = h.X - th[0], dy = h.Y - th[1];
-            const double r = hypot(dx, dy);
-            const double d = atan2(dy, dx) - h.ps0;
-            const double ps = h.ps0 + (d - tau * rint(d * itau));
-            const double rt = r - th[2], rz = h.Z - th[3] - th[4] * ps;
-            s[0] += wy * rt * rt + wz * rz * rz;
-            if (normal) {
-                const double ir = 1.0 / r;
-                const double ja = -dx * ir, jb = -dy * ir;
-                const double jc = -th[4] * dy * ir * ir, jd = th[4] * dx * ir * ir;
-                const double wzps = wz * ps;
-                s[1] += wy * ja * ja + wz * jc * jc;  // N00
-                s[2] += wy * ja * jb + wz * jc * jd;  // N10
-                s[3] += wy * jb * jb + wz * jd * jd;  // N11
-                s[4] -= wy * ja;                      // N20
-                s[5] -= wy * jb;                      // N21
-                s[6] -= wz * jc;                      // N30
-                s[7] -= wz * jd;                      // N31
-                s[8] -= wzps * jc;                    // N40
-                s[9] -= wzps * jd;                    // N41
-                s[10] += wzps;                        // N43
-                s[11] += wzps * ps;                   // N44
-                s[12] += wy * ja * rt + wz * jc * rz; // g0
-                s[13] += wy * jb * rt + wz * jd * rz; // g1
-                s[14] -= wy * rt;                     // g2
-                s[15] -= wz * rz;                     // g3
-                s[16] -= wzps * rz;                   // g4
-            }
+#pragma unroll 1
+    for (uint32_t f = lane; f < n; f += 64) {
+        const FitHit h = fh[f];
+        const double dx = h.X - th[0], dy = h.Y - th[1];
+        const double r = hypot(dx, dy);
+        const double d = atan2(dy, dx) - h.ps0;
+        const double ps = h.ps0 + (d - tau * rint(d * itau));
+        const double rt = r - th[2], rz = h.Z - th[3] - th[4] * ps;
+        s[0] += wy * rt * rt + wz * rz * rz;
+        if (normal) {
+            const double ir = 1.0 / r;
+            const double ja = -dx * ir, jb = -dy * ir;
+            const double jc = -th[4] * dy * ir * ir, jd = th[4] * dx * ir * ir;
+            const double wzps = wz * ps;
+            s[1] += wy * ja * ja + wz * jc * jc;  // N00
+            s[2] += wy * ja * jb + wz * jc * jd;  // N10
+            s[3] += wy * jb * jb + wz * jd * jd;  // N11
+            s[4] -= wy * ja;                      // N20
+            s[5] -= wy * jb;                      // N21
+            s[6] -= wz * jc;                      // N30
+            s[7] -= wz * jd;                      // N31
+            s[8] -= wzps * jc;                    // N40
+            s[9] -= wzps * jd;                    // N41
+            s[10] += wzps;                        // N43
+            s[11] += wzps * ps;                   // N44
+            s[12] += wy * ja * rt + wz * jc * rz; // g0
+            s[13] += wy * jb * rt + wz * jd * rz; // g1
+            s[14] -= wy * rt;                     // g2
+            s[15] -= wz * rz;                     // g3
+            s[16] -= wzps * rz;                   // g4
         }
     }
     chi2 = wave_sum_d(s[0]);
     if (normal) {
 #pragma unroll
         for (int i = 1; i < 17; ++i) s[i] = wave_sum_d(s[i]);
-        const double n = (double)base;
+        const double nd = (double)n;
         N[tri(0, 0)] = s[1];
         N[tri(1, 0)] = s[2];
         N[tri(1, 1)] = s[3];
         N[tri(2, 0)] = s[4];
         N[tri(2, 1)] = s[5];
-        N[tri(2, 2)] = wy * n;
+        N[tri(2, 2)] = wy * nd;
         N[tri(3, 0)] = s[6];
         N[tri(3, 1)] = s[7];
         N[tri(3, 2)] = 0.0;
-        N[tri(3, 3)] = wz * n;
+        N[tri(3, 3)] = wz * nd;
         N[tri(4, 0)] = s[8];
         N[tri(4, 1)] = s[9];
         N[tri(4, 2)] = 0.0;
@@ -673,49 +723,28 @@ __device__ inline void fit_sums(const FitHit* __restrict__ fh, const Comp& cp, c
     }
 }
 
-// One wave per component root: place its hits (members in ascending index, each
-// member's hits in its list order) with their starting turn, then Gauss-Newton.
-// Usable tracks with overlapping hit lists (never produced by the tracker) would share
-// FitHit entries; their fits are then unspecified, but every access stays inside the
-// hit list.
-__global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __restrict__ use,
-                                                     const int32_t* __restrict__ label,
-                                                     const uint32_t* __restrict__ gcnt,
-                                                     const uint32_t* __restrict__ goff, const int32_t* __restrict__ mem,
-                                                     const double* __restrict__ H, FitHit* __restrict__ fh,
-                                                     double* __restrict__ theta, double* __restrict__ theta_cov,
-                                                     double* __restrict__ chi2_out, int32_t* __restrict__ ndf_out,
-                                                     unsigned long long* __restrict__ tally) {
-    // cos and sin of every sector's azimuth (the same expressions as the helix kernel's)
-    __shared__ double sec_cs[2 * 256];
-    for (int s = threadIdx.x; s < a.S; s += kBlock) {
-        const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
-        sec_cs[2 * s] = cos(al);
-        sec_cs[2 * s + 1] = sin(al);
-    }
-    __syncthreads();
-    const int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
-    if (k >= a.cap_tracks) return;
+// Fits one component (the calling wave): places its hits with their starting turn, then
+// Gauss-Newton from the root's helix.
+__device__ void fit_component(const MgArgs& a, const FitItem& it, const double* __restrict__ sec_cs,
+                              const uint32_t* __restrict__ gcnt, const uint32_t* __restrict__ goff,
+                              const int32_t* __restrict__ mem, const double* __restrict__ H, FitHit* __restrict__ fhc,
+                              double* __restrict__ theta, double* __restrict__ theta_cov,
+                              double* __restrict__ chi2_out, int32_t* __restrict__ ndf_out,
+                              unsigned long long* __restrict__ tally) {
     const int lane = threadIdx.x & 63;
-    if (k >= n_tracks(a) || label[k] != k || gcnt[k] < 2 || !(use[k] & 1)) {  // no fit at this index
-        if (lane < 5) theta[5 * (size_t)k + lane] = NAN;
-        if (lane < 15) theta_cov[15 * (size_t)k + lane] = NAN;
-        if (lane == 0) {
-            chi2_out[k] = NAN;
-            ndf_out[k] = 0;
-        }
-        return;
-    }
+    const int32_t k = it.k;
     const double tau = 2.0 * M_PI;
     const double* h0 = H + 5 * (size_t)k;
     double th[5] = {h0[0], h0[1], 1.0 / h0[2], h0[4], h0[3]};
-    const Comp cp{mem + goff[k], gcnt[k], a.off, a.nh};
-    int64_t nhit = 0;
-    for (uint32_t mi = 0; mi < cp.m; ++mi) {
-        const int32_t t = cp.mem[mi];
+    const int32_t* mk = mem + goff[k];
+    const uint32_t m = gcnt[k];
+    uint32_t base = 0;
+    for (uint32_t mi = 0; mi < m; ++mi) {
+        const int32_t t = mk[mi];
         const int32_t o = a.off[t], nt = a.nh[t];
         const double* hh = H + 5 * (size_t)t;
-        const int32_t j0 = (int32_t)(((uint32_t)lane + 64u - ((uint32_t)nhit & 63u)) & 63u);
+        // this lane writes the component's hits f = base + j with f = lane mod 64
+        const int32_t j0 = (int32_t)(((uint32_t)lane + 64u - (base & 63u)) & 63u);
         for (int32_t j = j0; j < nt; j += 64) {
             const int32_t id = a.ids[o + j];
             const int s = a.sector[id];
@@ -731,21 +760,22 @@ __global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __
                 const double own =
                     rint((f.Z - hh[4] - hh[3] * atan2(f.Y - hh[1], f.X - hh[0])) / (tau * hh[3]));
                 const double shift = rint((hh[4] - th[3]) / (tau * th[4]));
-                const double base = own + shift;
-                const double z_of = th[3] + th[4] * (psi + tau * base);
-                turns = base + rint((f.Z - z_of) / (tau * th[4]));
+                const double b = own + shift;
+                const double z_of = th[3] + th[4] * (psi + tau * b);
+                turns = b + rint((f.Z - z_of) / (tau * th[4]));
             }
             f.ps0 = psi + tau * turns;
-            fh[o + j] = f;
+            fhc[base + (uint32_t)j] = f;
         }
-        nhit += nt;
+        base += (uint32_t)nt;
     }
+    const uint32_t n = it.nhit;
     double chi2, N[15], g[5];
-    fit_sums(fh, cp, th, a.wy, a.wz, false, chi2, N, g);
+    fit_sums(fhc, n, th, a.wy, a.wz, false, chi2, N, g);
     bool failed = false;
-    for (int it = 0; it < a.max_iter; ++it) {
+    for (int iter = 0; iter < a.max_iter; ++iter) {
         double c2;
-        fit_sums(fh, cp, th, a.wy, a.wz, true, c2, N, g);
+        fit_sums(fhc, n, th, a.wy, a.wz, true, c2, N, g);
         double A[5][5], b[5], step[5];
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
@@ -761,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __
         double cand[5];
         for (int h = 0; h < 30; ++h) {
             for (int p = 0; p < 5; ++p) cand[p] = th[p] + step[p];
-            fit_sums(fh, cp, cand, a.wy, a.wz, false, c2, N, g);
+            fit_sums(fhc, n, cand, a.wy, a.wz, false, c2, N, g);
             if (c2 <= chi2) {
                 accepted = true;
                 break;
@@ -774,30 +804,86 @@ __global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const uint8_t* __
         chi2 = c2;
         if (done) break;
     }
-    // covariance: the inverse of the normal matrix at the result
+    // covariance: the inverse of the normal matrix at the result, column c solved by lane c
+    // (the elimination depends on the matrix only, so every lane fails or succeeds alike)
     double c2;
-    fit_sums(fh, cp, th, a.wy, a.wz, true, c2, N, g);
-    double cov[15];
-    for (int i = 0; i < 15; ++i) cov[i] = NAN;
-#pragma unroll
-    for (int col = 0; col < 5; ++col) {
+    fit_sums(fhc, n, th, a.wy, a.wz, true, c2, N, g);
+    {
         double A[5][5], b[5], x[5];
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
-            b[p] = p == col ? 1.0 : 0.0;
+            b[p] = p == lane ? 1.0 : 0.0;
 #pragma unroll
             for (int q = 0; q < 5; ++q) A[p][q] = N[tri(p, q)];
         }
         failed = failed || !solve<5>(A, b, x);
+        if (lane < 5)
 #pragma unroll
-        for (int p = col; p < 5; ++p) cov[tri(p, col)] = x[p];
+            for (int p = 0; p < 5; ++p)
+                if (p >= lane) theta_cov[15 * (size_t)k + tri(p, lane)] = failed ? NAN : x[p];
     }
     if (lane == 0) {
         for (int p = 0; p < 5; ++p) theta[5 * (size_t)k + p] = failed ? NAN : th[p];
-        for (int i = 0; i < 15; ++i) theta_cov[15 * (size_t)k + i] = failed ? NAN : cov[i];
         chi2_out[k] = failed ? NAN : chi2;
-        ndf_out[k] = (int32_t)(2 * nhit - 5 < INT32_MAX ? 2 * nhit - 5 : INT32_MAX);
+        ndf_out[k] = (int32_t)(2 * (int64_t)n - 5 < INT32_MAX ? 2 * (int64_t)n - 5 : INT32_MAX);
         if (failed) atomicAdd(&tally[T_FAILED], 1ull);
+    }
+}
+
+// Work counters of the refit, one per group of workgroups (blockIdx mod 8, the XCD a
+// workgroup is dispatched to), each on a line of its own.
+constexpr int kFitCtrs = 8, kFitCtrStride = 32;
+
+// Persistent refit: each wave takes the next item of its counter's share of the fit
+// list (item i belongs to counter i mod 8), large components first.  The sector angles'
+// cos and sin are the helix kernel's expressions, kept in LDS.  A component whose packed
+// hits would pass the end of the fit-hit buffer (possible only with overlapping hit
+// lists) gets no fit and counts as failed.
+__global__ __launch_bounds__(kBlock) void k_mg_refit(MgArgs a, const FitItem* __restrict__ fit,
+                                                     const uint32_t* __restrict__ n_fit, uint32_t* __restrict__ ctr,
+                                                     const uint32_t* __restrict__ gcnt,
+                                                     const uint32_t* __restrict__ goff, const int32_t* __restrict__ mem,
+                                                     const double* __restrict__ H, FitHit* __restrict__ fh,
+                                                     uint64_t fh_cap, double* __restrict__ theta,
+                                                     double* __restrict__ theta_cov, double* __restrict__ chi2_out,
+                                                     int32_t* __restrict__ ndf_out,
+                                                     unsigned long long* __restrict__ tally) {
+    __shared__ double sec_cs[2 * 256];
+    for (int s = threadIdx.x; s < a.S; s += kBlock) {
+        const double al = a.dphi * (double)(s % a.sps) + 0.5 * a.dphi;
+        sec_cs[2 * s] = cos(al);
+        sec_cs[2 * s + 1] = sin(al);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint32_t grp = blockIdx.x % kFitCtrs;
+    const uint32_t nl = n_fit[0], nf = nl + n_fit[1];
+    // The loop's control is wave-uniform by construction (read from the first lane): every
+    // lane takes part in the ticket atomic (lane 0 adds one, the others zero) and no branch
+    // depends on the lane, so the compiler cannot split the wave's lanes over different
+    // iterations around the cross-lane sums of the fit.
+    for (;;) {
+        const uint32_t t = atomicAdd(&ctr[grp * kFitCtrStride], lane == 0 ? 1u : 0u);
+        const uint32_t j = __builtin_amdgcn_readfirstlane(t);
+        const uint64_t i = (uint64_t)grp + (uint64_t)kFitCtrs * j;
+        if (i >= nf) break;
+        const FitItem raw = fit[i < nl ? i : (uint64_t)a.cap_tracks - 1u - (i - nl)];
+        FitItem it;
+        it.k = __builtin_amdgcn_readfirstlane(raw.k);
+        it.nhit = __builtin_amdgcn_readfirstlane(raw.nhit);
+        it.hb = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw.hb >> 32)) << 32) |
+                (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)raw.hb);
+        if (it.hb + it.nhit <= fh_cap) {
+            fit_component(a, it, sec_cs, gcnt, goff, mem, H, fh + it.hb, theta, theta_cov, chi2_out, ndf_out, tally);
+        } else {
+            if (lane < 5) theta[5 * (size_t)it.k + lane] = NAN;
+            if (lane < 15) theta_cov[15 * (size_t)it.k + lane] = NAN;
+            if (lane == 0) {
+                chi2_out[it.k] = NAN;
+                ndf_out[it.k] = 0;
+                atomicAdd(&tally[T_FAILED], 1ull);
+            }
+        }
     }
 }
 
@@ -873,6 +959,8 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     CKey* keys;
     CRec* rec;
     FitHit* fh;
+    FitItem* fit;
+    uint32_t* fctr;
     unsigned long long* tally;
     void* scan;
     MB(use, "mg_use", T);
@@ -893,10 +981,13 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     MB(big, "mg_big", 4 * T);
     MB(n_elig, "mg_nelig", 16);
     MB(fh, "mg_fithits", sizeof(FitHit) * NH);
+    MB(fit, "mg_fitlist", sizeof(FitItem) * T);
+    MB(fctr, "mg_fitctr", 4 * kFitCtrs * kFitCtrStride);
     MB(tally, "mg_tally", 8 * T_N);
     int64_t sn = NC + 1 > T + 1 ? NC + 1 : T + 1;
     MB(scan, "mg_scan", scan_scratch_bytes(sn));
-    fill_u32(n_elig, 0u, 4, st);  // [0] eligible tracks (scan total), [1] large components
+    fill_u32(n_elig, 0u, 4, st);  // [0] eligible tracks (scan total), [1] large components, [2] [3] fit items
+    fill_u32(fctr, 0u, kFitCtrs * kFitCtrStride, st);
     fill_u32(ccnt, 0u, NC + 1, st);
     fill_u32(ccur, 0u, NC + 1, st);
     fill_u32(gcnt, 0u, T + 1, st);
@@ -914,10 +1005,13 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     k_mg_label<<<nb, kBlock, 0, st>>>(a, use, par, out.label, gcnt);
     scan_u32(gcnt, goff, T, nullptr, nullptr, scan, st);
     k_mg_group<<<nb, kBlock, 0, st>>>(a, out.label, goff, gcur, mem);
-    k_mg_sort_members<<<nb, kBlock, 0, st>>>(a, out.label, gcnt, goff, mem, out.n_members, big, n_elig + 1, tally);
+    k_mg_sort_members<<<nb, kBlock, 0, st>>>(a, use, out.label, gcnt, goff, mem, out.n_members, big, n_elig + 1,
+                                              fit, n_elig + 2, out.theta, out.theta_cov, out.chi2, out.ndf, tally);
     k_mg_sort_big<<<256, 1024, 0, st>>>(big, n_elig + 1, gcnt, goff, mem);
-    k_mg_refit<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, use, out.label, gcnt, goff, mem, out.helix, fh,
-                                                         out.theta, out.theta_cov, out.chi2, out.ndf, tally);
+    // a whole number of counter groups, a few workgroups per CU
+    const unsigned fit_blocks = (unsigned)((c->n_cu * 8 + kFitCtrs - 1) / kFitCtrs * kFitCtrs);
+    k_mg_refit<<<fit_blocks, kBlock, 0, st>>>(a, fit, n_elig + 2, fctr, gcnt, goff, mem, out.helix, fh, (uint64_t)NH,
+                                              out.theta, out.theta_cov, out.chi2, out.ndf, tally);
     k_mg_counts<<<1, 64, 0, st>>>(tally, out.counts);
     return TPC_OK;
 }
