@@ -397,7 +397,11 @@ int tpc_decompress(tpc_ctx_t* ctx, const tpc_compressed_t* in, const tpc_geometr
  * longitudinal residual = Z - z0 - w psi (params->sigma_z), each hit's psi unwrapped to
  * the turn its own track's helix predicts, shifted by the whole turns between its
  * track's phase and the lowest member's.
- * tpc_merge_params_default: 600 cm, 16 cm, 60, 5, 0.1 cm, 5 turns, 18, 50. */
+ * pair_queue sizes the context's queue of candidate pairs awaiting the full test (pairs
+ * per track slot of the track set); tracks whose pairs do not fit are rescanned with
+ * every pair tested at once, which gives the same labels more slowly (and may count some
+ * pairs twice in TPC_MG_PAIRS_PASSED).
+ * tpc_merge_params_default: 600 cm, 16 cm, 60, 5, 0.1 cm, 5 turns, 18, 50, 4. */
 typedef struct {
     double rho_max;          /* only helices this tight merge (cm), > 0 */
     double centre_window;    /* |dXc|, |dYc| at most this (cm), > 0 */
@@ -407,6 +411,7 @@ typedef struct {
     int32_t max_turns;       /* phases at most this many turns apart, 0 .. 1000 */
     int32_t sectors_per_side;/* 1 .. 128, n_sectors <= 2 * sectors_per_side */
     int32_t max_iter;        /* refit steps, 1 .. 1000 */
+    int32_t pair_queue;      /* queued candidate pairs per track slot, 0 .. 64 */
 } tpc_merge_params_t;
 
 enum {

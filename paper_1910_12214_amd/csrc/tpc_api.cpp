@@ -539,6 +539,7 @@ void tpc_merge_params_default(tpc_merge_params_t* p) {
     p->max_turns = 5;
     p->sectors_per_side = 18;
     p->max_iter = 50;
+    p->pair_queue = 4;
 }
 
 
@@ -682,10 +683,11 @@ int tpc_merge(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo,
     if (!mp || !finite_pos(mp->rho_max) || !finite_pos(mp->centre_window) || !finite_pos(mp->chi2_max) ||
         !finite_pos(mp->phase_sigmas) || !std::isfinite(mp->phase_floor) || mp->phase_floor < 0.0 ||
         mp->max_turns < 0 || mp->max_turns > 1000 || mp->sectors_per_side < 1 || mp->sectors_per_side > 128 ||
-        geo->n_sectors > 2 * mp->sectors_per_side || mp->max_iter < 1 || mp->max_iter > 1000)
+        geo->n_sectors > 2 * mp->sectors_per_side || mp->max_iter < 1 || mp->max_iter > 1000 || mp->pair_queue < 0 ||
+        mp->pair_queue > 64)
         return fail(c, TPC_ERR_ARG, "merge params: need rho_max, centre_window, chi2_max, phase_sigmas > 0, "
                                     "phase_floor >= 0, max_turns in [0, 1000], sectors_per_side in [1, 128] with "
-                                    "n_sectors <= 2 * sectors_per_side, max_iter in [1, 1000]");
+                                    "n_sectors <= 2 * sectors_per_side, max_iter in [1, 1000], pair_queue in [0, 64]");
     if (!out || out->cap_tracks < trk->cap_tracks || !out->counts ||
         (trk->cap_tracks > 0 && (!out->label || !out->n_members || !out->helix || !out->helix_cov || !out->theta ||
                                  !out->theta_cov || !out->chi2 || !out->ndf)))

@@ -13,9 +13,10 @@
 //     [z0 - reach, z0 + reach] such that two tracks can pass the phase test only when
 //     their intervals overlap (bound below).  Tracks are counted per cell, scattered,
 //     and each cell is sorted by interval start (bitonic in LDS; in global memory for a
-//     cell too long for LDS), then laid out as 64-byte candidate records.
-//  3. pairs: one lane per track A walks the nine cells around its own and reads the
-//     records of the tracks B whose interval starts inside A's, so every overlapping
+//     cell too long for LDS), then laid out as candidate arrays.
+//  3. pairs: a group of eight lanes per track A walks the nine cells around its own and
+//     reads, in turn, the candidates B whose interval starts inside A's (the pairs left
+//     after the prefilter are queued and tested by the next kernel), so every overlapping
 //     pair is reached from the track that starts first (from both on equal starts).  A
 //     prefilter drops pairs that cannot pass: the centre window, and |d_i| <=
 //     sqrt(chi2_max) (sigma_A,i + sigma_B,i) for each of Xc, Yc, k, w (implied by the chi2
@@ -371,33 +372,30 @@ __global__ __launch_bounds__(1024) void k_mg_cell_sort_big(const uint32_t* __res
     flip_bitonic_sort(gkeys + coff[cc], m, CKeyLess{});
 }
 
-// Candidate record of a cell position (64 bytes, read in sequence by the pair search):
-// the interval start, the helix values the prefilter compares, the prefilter radii of
-// (Xc, Yc, k, w) (rounded up to FP32) and the track index.
-struct alignas(64) CRec {
-    double lo, Xc, Yc, k, w;
-    float r[4];
-    uint32_t idx, pad;
+// Candidates of the cell positions, as arrays (read in sequence by the groups of the pair
+// search, so consecutive lanes read consecutive entries): the interval start, the centre,
+// (k, w), the prefilter radii of (Xc, Yc, k, w) (rounded up to FP32) and the track index.
+struct Cands {
+    double* lo;
+    double2* xy;
+    double2* kw;
+    float4* r;
+    uint32_t* idx;
 };
 
 __global__ __launch_bounds__(kBlock) void k_mg_records(const uint32_t* __restrict__ n_elig,
                                                        const CKey* __restrict__ keys, const double* __restrict__ H,
-                                                       const float* __restrict__ rad, CRec* __restrict__ rec) {
+                                                       const float* __restrict__ rad, Cands cd) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= *n_elig) return;
     const CKey key = keys[i];
     const double* h = H + 5 * (size_t)key.k;
     const float* r = rad + 4 * (size_t)key.k;
-    CRec c;
-    c.lo = key.lo;
-    c.Xc = h[0];
-    c.Yc = h[1];
-    c.k = h[2];
-    c.w = h[3];
-    for (int j = 0; j < 4; ++j) c.r[j] = r[j];
-    c.idx = key.k;
-    c.pad = 0;
-    rec[i] = c;
+    cd.lo[i] = key.lo;
+    cd.xy[i] = make_double2(h[0], h[1]);
+    cd.kw[i] = make_double2(h[2], h[3]);
+    cd.r[i] = make_float4(r[0], r[1], r[2], r[3]);
+    cd.idx[i] = key.k;
 }
 
 // ---------------------------------------------------------------- 3. same-helix test
@@ -457,63 +455,146 @@ __device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
     }
 }
 
-// One lane per track in cell order.  The candidates of a neighbouring cell are the
-// records whose interval starts inside the lane's own interval; a candidate passing the
-// prefilter (centre window, and the marginal chi2 bounds on Xc, Yc, k and w) gets the
-// full test.
-__global__ __launch_bounds__(kBlock) void k_mg_pairs(MgArgs a, const uint32_t* __restrict__ n_elig,
-                                                     const CRec* __restrict__ rec, const uint32_t* __restrict__ coff,
-                                                     const uint32_t* __restrict__ cell, const double* __restrict__ hi,
-                                                     const double* __restrict__ H, const double* __restrict__ CH,
-                                                     int32_t* __restrict__ par, unsigned long long* __restrict__ tally) {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    uint64_t tested = 0, passed = 0;
-    if (i < *n_elig) {
-        const CRec ra = rec[i];
-        const uint32_t A = ra.idx, ca = cell[A];
-        const double loA = ra.lo, hiA = hi[A];
-        const double win = a.win;
-        const int cx = (int)(ca % (uint32_t)a.nc), cy = (int)(ca / (uint32_t)a.nc);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = cy + dy;
-            if (y < 0 || y >= a.nc) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = cx + dx;
-                if (x < 0 || x >= a.nc) continue;
-                const uint32_t cc = (uint32_t)y * (uint32_t)a.nc + (uint32_t)x;
-                uint32_t b = coff[cc], e = coff[cc + 1];
-                // first start >= loA
-                while (b < e) {
-                    const uint32_t mid = b + (e - b) / 2;
-                    if (rec[mid].lo < loA)
-                        b = mid + 1;
-                    else
-                        e = mid;
-                }
-                e = coff[cc + 1];
-                for (uint32_t j = b; j < e; ++j) {
-                    const CRec rb = rec[j];
-                    if (!(rb.lo <= hiA)) break;
-                    const double ex = fabs(ra.Xc - rb.Xc), ey = fabs(ra.Yc - rb.Yc);
-                    const bool pre = rb.idx != A && ex <= win && ey <= win &&
-                                     ex <= (double)ra.r[0] + (double)rb.r[0] &&
-                                     ey <= (double)ra.r[1] + (double)rb.r[1] &&
-                                     fabs(ra.k - rb.k) <= (double)ra.r[2] + (double)rb.r[2] &&
-                                     fabs(ra.w - rb.w) <= (double)ra.r[3] + (double)rb.r[3];
-                    if (!pre) continue;
-                    ++tested;
-                    const uint32_t B = rb.idx;
-                    const uint32_t p = A < B ? A : B, q = A < B ? B : A;
-                    if (same_helix(a, H + 5 * (size_t)p, CH + 15 * (size_t)p, H + 5 * (size_t)q,
-                                   CH + 15 * (size_t)q)) {
-                        ++passed;
-                        uf_unite(par, (int32_t)A, (int32_t)B);
-                    }
-                }
+// A group of kPairGrp lanes per track A (tracks in cell order, a grid-stride walk).  The
+// candidates of a neighbouring cell are the entries whose interval starts inside A's
+// interval; lane g of the group takes the g-th, (g + kPairGrp)-th, ... of them.  A
+// candidate passing the prefilter (centre window, and the marginal chi2 bounds on Xc, Yc,
+// k and w) is queued for the full test: each lane appends to a chunk of kPairChunk
+// entries that it reserves in one of kPairSegs queue segments (one atomic per chunk).
+// The queued pairs are tested by the next kernel, one per lane, so the few lanes with a
+// full test do not hold up the scan (and the scan keeps few registers).  A lane whose
+// segment has no chunk left lists the tracks it could not queue for a rescan that tests
+// every pair of theirs at once.  Chunk entries a lane leaves unused are marked empty.
+constexpr uint32_t kPairGrp = 8, kPairChunk = 8, kPairSegs = 256, kSegStride = 32;
+constexpr uint32_t kNoPair = 0xFFFFFFFFu;
+
+// Scan of the candidates of track position i for lane g of its group: calls f(A, B) for
+// every pair that passes the prefilter.
+template <class F>
+__device__ inline void scan_pairs(const MgArgs& a, const Cands& cd, const uint32_t* __restrict__ coff,
+                                  const uint32_t* __restrict__ cell, const double* __restrict__ hi, uint32_t i,
+                                  uint32_t g, F&& f) {
+    const double win = a.win;
+    const uint32_t A = cd.idx[i], ca = cell[A];
+    const double loA = cd.lo[i], hiA = hi[A];
+    const double2 xyA = cd.xy[i], kwA = cd.kw[i];
+    const float4 rA = cd.r[i];
+    const int cx = (int)(ca % (uint32_t)a.nc), cy = (int)(ca / (uint32_t)a.nc);
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int y = cy + dy;
+        if (y < 0 || y >= a.nc) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = cx + dx;
+            if (x < 0 || x >= a.nc) continue;
+            const uint32_t cc = (uint32_t)y * (uint32_t)a.nc + (uint32_t)x;
+            uint32_t b = coff[cc], e = coff[cc + 1];
+            // first start >= loA (every lane of the group searches alike)
+            while (b < e) {
+                const uint32_t mid = b + (e - b) / 2;
+                if (cd.lo[mid] < loA)
+                    b = mid + 1;
+                else
+                    e = mid;
+            }
+            e = coff[cc + 1];
+            for (uint32_t j = b + g; j < e; j += kPairGrp) {
+                if (!(cd.lo[j] <= hiA)) break;
+                const double2 xyB = cd.xy[j];
+                const double ex = fabs(xyA.x - xyB.x), ey = fabs(xyA.y - xyB.y);
+                if (!(ex <= win && ey <= win)) continue;
+                const float4 rB = cd.r[j];
+                const double2 kwB = cd.kw[j];
+                const uint32_t B = cd.idx[j];
+                const bool pre = B != A && ex <= (double)rA.x + (double)rB.x && ey <= (double)rA.y + (double)rB.y &&
+                                 fabs(kwA.x - kwB.x) <= (double)rA.z + (double)rB.z &&
+                                 fabs(kwA.y - kwB.y) <= (double)rA.w + (double)rB.w;
+                if (pre) f(A, B);
             }
         }
     }
+}
+
+__device__ inline void test_pair(const MgArgs& a, uint32_t A, uint32_t B, const double* __restrict__ H,
+                                 const double* __restrict__ CH, int32_t* __restrict__ par, uint64_t& passed) {
+    const uint32_t p = A < B ? A : B, q = A < B ? B : A;
+    if (same_helix(a, H + 5 * (size_t)p, CH + 15 * (size_t)p, H + 5 * (size_t)q, CH + 15 * (size_t)q)) {
+        ++passed;
+        uf_unite(par, (int32_t)A, (int32_t)B);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_pairs(MgArgs a, const uint32_t* __restrict__ n_elig, Cands cd,
+                                                     const uint32_t* __restrict__ coff,
+                                                     const uint32_t* __restrict__ cell, const double* __restrict__ hi,
+                                                     uint2* __restrict__ pq, uint32_t seg_cap,
+                                                     uint32_t* __restrict__ seg_fill, uint32_t* __restrict__ ovf_flag,
+                                                     uint32_t* __restrict__ ovf, uint32_t* __restrict__ n_ovf,
+                                                     unsigned long long* __restrict__ tally) {
+    const uint32_t ne = *n_elig;
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = threadIdx.x % kPairGrp;
+    const uint32_t n_grp = gridDim.x * (kBlock / kPairGrp);
+    const uint32_t seg = gid % kPairSegs;
+    uint2* const segq = pq + (size_t)seg * seg_cap;
+    uint32_t qpos = 0, qend = 0;  // the lane's current chunk in its segment
+    bool room = true;             // false once the segment had no chunk left for this lane
+    uint64_t tested = 0;
+    for (uint32_t i = gid / kPairGrp; i < ne; i += n_grp) {
+        scan_pairs(a, cd, coff, cell, hi, i, g, [&](uint32_t A, uint32_t B) {
+            ++tested;
+            if (qpos == qend && room) {
+                // chunks start at multiples of kPairChunk, and seg_cap is one: a chunk
+                // either fits whole or starts at or past seg_cap
+                const uint32_t c = atomicAdd(&seg_fill[seg * kSegStride], kPairChunk);
+                room = c < seg_cap;
+                qpos = c;
+                qend = room ? c + kPairChunk : c;
+            }
+            if (qpos < qend)
+                segq[qpos++] = make_uint2(A, B);
+            else if (atomicOr(&ovf_flag[i], 1u) == 0u)
+                ovf[atomicAdd(n_ovf, 1u)] = i;
+        });
+    }
+    for (; qpos < qend; ++qpos) segq[qpos] = make_uint2(kNoPair, kNoPair);
     wave_tally(tally, T_PAIRS, tested);
+}
+
+// The queued pairs, one per lane (a grid-stride walk over the segments' filled chunks).
+__global__ __launch_bounds__(kBlock) void k_mg_pair_tests(MgArgs a, const double* __restrict__ H,
+                                                          const double* __restrict__ CH, const uint2* __restrict__ pq,
+                                                          uint32_t seg_cap, const uint32_t* __restrict__ seg_fill,
+                                                          int32_t* __restrict__ par,
+                                                          unsigned long long* __restrict__ tally) {
+    const uint64_t n = (uint64_t)seg_cap * kPairSegs;
+    uint64_t passed = 0;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t seg = (uint32_t)(t / seg_cap), off = (uint32_t)(t % seg_cap);
+        const uint32_t f = seg_fill[seg * kSegStride];
+        if (off >= (f < seg_cap ? f : seg_cap)) continue;
+        const uint2 pr = pq[t];
+        if (pr.x != kNoPair) test_pair(a, pr.x, pr.y, H, CH, par, passed);
+    }
+    wave_tally(tally, T_PASSED, passed);
+}
+
+// Rescan of the listed tracks (a group per track), every prefilter pair tested at once.
+// Pairs that were queued before the queue filled are tested a second time (the union
+// is unchanged by that).
+__global__ __launch_bounds__(kBlock) void k_mg_pairs_rescan(MgArgs a, Cands cd, const uint32_t* __restrict__ coff,
+                                                            const uint32_t* __restrict__ cell,
+                                                            const double* __restrict__ hi, const double* __restrict__ H,
+                                                            const double* __restrict__ CH,
+                                                            const uint32_t* __restrict__ ovf,
+                                                            const uint32_t* __restrict__ n_ovf, int32_t* __restrict__ par,
+                                                            unsigned long long* __restrict__ tally) {
+    const uint32_t n = *n_ovf;
+    const uint32_t g = threadIdx.x % kPairGrp;
+    const uint32_t n_grp = gridDim.x * (kBlock / kPairGrp);
+    uint64_t passed = 0;
+    for (uint32_t k = (blockIdx.x * kBlock + threadIdx.x) / kPairGrp; k < n; k += n_grp)
+        scan_pairs(a, cd, coff, cell, hi, ovf[k], g,
+                   [&](uint32_t A, uint32_t B) { test_pair(a, A, B, H, CH, par, passed); });
     wave_tally(tally, T_PASSED, passed);
 }
 
@@ -957,7 +1038,9 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     double *lo, *hi;
     float* rad;
     CKey* keys;
-    CRec* rec;
+    Cands cd;
+    uint2* pq;
+    uint32_t *seg_fill, *ovf_flag, *ovf;
     FitHit* fh;
     FitItem* fit;
     uint32_t* fctr;
@@ -969,7 +1052,19 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     MB(coff, "mg_coff", 4 * (NC + 1));
     MB(ccur, "mg_ccur", 4 * (NC + 1));
     MB(keys, "mg_keys", sizeof(CKey) * T);
-    MB(rec, "mg_rec", sizeof(CRec) * T);
+    MB(cd.lo, "mg_c_lo", 8 * T);
+    MB(cd.xy, "mg_c_xy", 16 * T);
+    MB(cd.kw, "mg_c_kw", 16 * T);
+    MB(cd.r, "mg_c_r", 16 * T);
+    MB(cd.idx, "mg_c_idx", 4 * T);
+    // pair queue: pair_queue pairs per track slot, in kPairSegs segments of whole chunks
+    const int64_t qcap = (int64_t)mp.pair_queue * T;
+    const uint32_t seg_cap =
+        qcap > 0 ? (uint32_t)((qcap / kPairSegs + kPairChunk - 1) / kPairChunk * kPairChunk) : 0u;
+    MB(pq, "mg_pair_queue", sizeof(uint2) * ((size_t)seg_cap * kPairSegs + 1));
+    MB(seg_fill, "mg_pair_fill", 4 * kPairSegs * kSegStride);
+    MB(ovf_flag, "mg_pair_ovf_flag", 4 * T);
+    MB(ovf, "mg_pair_ovf", 4 * T);
     MB(rad, "mg_rad", 16 * T);
     MB(lo, "mg_lo", 8 * T);
     MB(hi, "mg_hi", 8 * T);
@@ -979,15 +1074,19 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     MB(gcur, "mg_gcur", 4 * (T + 1));
     MB(mem, "mg_mem", 4 * T);
     MB(big, "mg_big", 4 * T);
-    MB(n_elig, "mg_nelig", 16);
+    MB(n_elig, "mg_nelig", 32);
     MB(fh, "mg_fithits", sizeof(FitHit) * NH);
     MB(fit, "mg_fitlist", sizeof(FitItem) * T);
     MB(fctr, "mg_fitctr", 4 * kFitCtrs * kFitCtrStride);
     MB(tally, "mg_tally", 8 * T_N);
     int64_t sn = NC + 1 > T + 1 ? NC + 1 : T + 1;
     MB(scan, "mg_scan", scan_scratch_bytes(sn));
-    fill_u32(n_elig, 0u, 4, st);  // [0] eligible tracks (scan total), [1] large components, [2] [3] fit items
+    // [0] eligible tracks (scan total), [1] large components, [2] [3] fit items, [4] tracks
+    // to rescan for pairs
+    fill_u32(n_elig, 0u, 8, st);
     fill_u32(fctr, 0u, kFitCtrs * kFitCtrStride, st);
+    fill_u32(seg_fill, 0u, kPairSegs * kSegStride, st);
+    fill_u32(ovf_flag, 0u, T, st);
     fill_u32(ccnt, 0u, NC + 1, st);
     fill_u32(ccur, 0u, NC + 1, st);
     fill_u32(gcnt, 0u, T + 1, st);
@@ -999,9 +1098,14 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, lo, keys);
     k_mg_cell_sort<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, keys, tally);
     k_mg_cell_sort_big<<<(unsigned)NC, 1024, 0, st>>>(ccnt, coff, keys);
-    k_mg_records<<<nb, kBlock, 0, st>>>(n_elig, keys, out.helix, rad, rec);
+    k_mg_records<<<nb, kBlock, 0, st>>>(n_elig, keys, out.helix, rad, cd);
     k_mg_init<<<nb, kBlock, 0, st>>>(trk.cap_tracks, par);
-    k_mg_pairs<<<nb, kBlock, 0, st>>>(a, n_elig, rec, coff, cell, hi, out.helix, out.helix_cov, par, tally);
+    k_mg_pairs<<<(unsigned)(c->n_cu * 16), kBlock, 0, st>>>(a, n_elig, cd, coff, cell, hi, pq, seg_cap, seg_fill,
+                                                          ovf_flag, ovf, n_elig + 4, tally);
+    k_mg_pair_tests<<<(unsigned)(c->n_cu * 16), kBlock, 0, st>>>(a, out.helix, out.helix_cov, pq, seg_cap, seg_fill, par,
+                                                               tally);
+    k_mg_pairs_rescan<<<(unsigned)(c->n_cu * 4), kBlock, 0, st>>>(a, cd, coff, cell, hi, out.helix, out.helix_cov, ovf,
+                                                                n_elig + 4, par, tally);
     k_mg_label<<<nb, kBlock, 0, st>>>(a, use, par, out.label, gcnt);
     scan_u32(gcnt, goff, T, nullptr, nullptr, scan, st);
     k_mg_group<<<nb, kBlock, 0, st>>>(a, out.label, goff, gcur, mem);

@@ -81,7 +81,7 @@ class Compressed(ctypes.Structure):
 class MergeParams(ctypes.Structure):
     _fields_ = [("rho_max", ctypes.c_double), ("centre_window", ctypes.c_double), ("chi2_max", ctypes.c_double),
                 ("phase_sigmas", ctypes.c_double), ("phase_floor", ctypes.c_double), ("max_turns", ctypes.c_int32),
-                ("sectors_per_side", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+                ("sectors_per_side", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("pair_queue", ctypes.c_int32)]
 
 
 class Merged(ctypes.Structure):

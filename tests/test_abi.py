@@ -54,4 +54,4 @@ def test_merge_defaults_are_the_oracle_readings():
     mp = tpcca.Context.merge_params()
     assert (mp.rho_max, mp.centre_window, mp.chi2_max, mp.phase_sigmas, mp.phase_floor, mp.max_turns) == \
         (om.RHO_MAX, om.CENTRE_WINDOW, om.CHI2_HELIX, om.PHASE_SIGMAS, om.PHASE_FLOOR, om.MAX_TURNS)
-    assert mp.sectors_per_side == 18 and mp.max_iter == 50
+    assert mp.sectors_per_side == 18 and mp.max_iter == 50 and mp.pair_queue == 4

@@ -80,10 +80,10 @@ def check_refit(g, ids, hh, X, Y, Z, H, m, sy, sz):
     assert np.allclose(m["theta_cov"][g], cov[ii, jj], rtol=1e-5, atol=1e-12 * np.abs(cov).max())
 
 
-def full_check(ctx, ev, geom, t, d, sy, sz):
+def full_check(ctx, ev, geom, t, d, sy, sz, mparams=None):
     nt = len(t["nh"])
     ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
-    out = ctx.merge(*ten, geom, synth.BZ, d, params=P)
+    out = ctx.merge(*ten, geom, synth.BZ, d, params=P, mparams=mparams)
     m = host(out, nt)
     H, CH = om.helix_params(t["state"], t["x_ref"], t["sector"], t["cov"].astype(np.float64), synth.BZ)
     scale = np.abs(H).max(axis=0)
@@ -129,6 +129,32 @@ def test_smeared_loopers_equal_oracle(ctx):
     m, lab, c = full_check(ctx, ev, geom, t, d, 0.06, 0.1)
     say(f"[merge] smeared loopers: {len(lab)} tracks -> {c[0]}; chi2/ndf "
         f"{np.nansum(m['chi2']) / m['ndf'][m['ndf'] > 0].sum():.3f}")
+
+
+def test_pair_queue_overflow_gives_the_same_merge(ctx):
+    """Candidate pairs that do not fit the pair queue go through the rescan path: with no queue at
+    all a looper event still equals the oracle, and on the Pb-Pb event's GPU tracks a queue of zero
+    or one pair per track slot gives labels, refits and the count of tested pairs identical to the
+    default queue's."""
+    w, ev = looper_event(11)
+    geom = synth.geometry(w)
+    t, d = oracle_track_set(ev, geom)
+    full_check(ctx, ev, geom, t, d, P["sigma_y"], P["sigma_z"], mparams={"pair_queue": 0})
+    w = synth.PBPB_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    trk = ctx.track(*ten, geom, synth.BZ, P)
+    nt = int(trk["counts"][0].item())
+    out = ctx.merge(*ten, geom, synth.BZ, trk, params=P)
+    ref, ref_c = host(out, nt), out["counts"].cpu().numpy()
+    for q in (0, 1):
+        out = ctx.merge(*ten, geom, synth.BZ, trk, params=P, mparams={"pair_queue": q})
+        m, c = host(out, nt), out["counts"].cpu().numpy()
+        for k in ref:
+            assert np.array_equal(m[k], ref[k], equal_nan=m[k].dtype.kind == "f"), (q, k)
+        assert c[2] == ref_c[2] and c[0] == ref_c[0] and c[1] == ref_c[1], (q, c, ref_c)
+    say(f"[merge] pair queue 0 and 1: Pb-Pb event merge identical ({ref_c[2]} pairs tested)")
 
 
 def sampled_merge_check(ctx, ev, geom, trk, n_samples, n_components, seed):
