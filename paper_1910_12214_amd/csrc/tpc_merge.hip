@@ -2,12 +2,12 @@
 // pieces of one track in neighbouring sectors, are found as separate tracks; they are
 // merged into one track, which is then fitted once).  FP64 throughout.
 //
-//  1. helix: one lane per track.  Its global helix h = (Xc, Yc, k, w, z0) -- circle
-//     centre, curvature k > 0, pitch w = dz/dpsi (z advance per radian around the
-//     centre) and phase z0 = z - w psi at the reference point -- and the covariance of
-//     h carried from the track's state covariance by the Jacobian.  A track takes part
-//     when its hit entries are usable, h is finite and its radius 1/k is at most
-//     rho_max.
+//  1. helix: each track's entries checked by one wave, then one lane per track.  Its
+//     global helix h = (Xc, Yc, k, w, z0) -- circle centre, curvature k > 0, pitch
+//     w = dz/dpsi (z advance per radian around the centre) and phase z0 = z - w psi at
+//     the reference point -- and the covariance of h carried from the track's state
+//     covariance by the Jacobian.  A track takes part when its hit entries are usable,
+//     h is finite and its radius 1/k is at most rho_max.
 //  2. cells: centres closer than the window in X and Y lie in neighbouring cells of a
 //     grid of window-sized cells.  Each track also gets a phase interval
 //     [z0 - reach, z0 + reach] such that two tracks can pass the phase test only when
@@ -181,7 +181,34 @@ __device__ inline bool solve(double A[N][N], double b[N], double x[N]) {
 // use[k]: bit0 the track is refit (its entries are usable -- sector in range, hits inside
 // cap_hits, ids of clusters with row and sector in range -- and its helix is finite),
 // bit1 it also takes part in merging.
-__global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restrict__ H, double* __restrict__ CH,
+//
+// Entry check first, one wave per track (its hit ids read together): ok[k] = 1 when
+// the sector is in range, the hits lie inside cap_hits and every id is of a cluster
+// with row and sector in range.
+__global__ __launch_bounds__(kBlock) void k_mg_valid(MgArgs a, uint8_t* __restrict__ ok) {
+    const uint32_t n = (uint32_t)n_tracks(a);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t k = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); k < n; k += nw) {
+        const int32_t o = __builtin_amdgcn_readfirstlane(a.off[k]), m = __builtin_amdgcn_readfirstlane(a.nh[k]);
+        const int32_t s = __builtin_amdgcn_readfirstlane(a.tsec[k]);
+        bool v = s >= 0 && s < a.S && o >= 0 && m > 0 && (int64_t)o + m <= (int64_t)a.cap_hits;
+        if (v) {
+            bool bad = false;
+            for (int32_t j = (int32_t)lane; j < m; j += 64) {
+                const int32_t id = a.ids[o + j];
+                bad = bad || !(id >= 0 && (int64_t)id < a.n && a.row[id] < a.R && a.sector[id] < a.S);
+            }
+            v = __ballot(bad) == 0ull;
+        }
+        if (lane == 0) ok[k] = v ? 1 : 0;
+    }
+}
+
+// Helix per track (one lane each); the no-helix values (NaN) are written for unusable
+// tracks below the track count.
+__global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, const uint8_t* __restrict__ ok,
+                                                     double* __restrict__ H, double* __restrict__ CH,
                                                      uint8_t* __restrict__ use, uint32_t* __restrict__ cell,
                                                      double* __restrict__ lo, double* __restrict__ hi,
                                                      float* __restrict__ rad, uint32_t* __restrict__ ccnt) {
@@ -193,15 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restric
         double h[5], ch[15];
         for (int i = 0; i < 5; ++i) h[i] = NAN;
         for (int i = 0; i < 15; ++i) ch[i] = NAN;
-        bool valid = false;
-        if (k < n_tracks(a)) {
-            const int32_t o = a.off[k], m = a.nh[k], s = a.tsec[k];
-            valid = s >= 0 && s < a.S && o >= 0 && m > 0 && (int64_t)o + m <= (int64_t)a.cap_hits;
-            for (int32_t j = 0; valid && j < m; ++j) {
-                const int32_t id = a.ids[o + j];
-                valid = id >= 0 && (int64_t)id < a.n && a.row[id] < a.R && a.sector[id] < a.S;
-            }
-        }
+        const bool listed = k < n_tracks(a);
+        const bool valid = listed && ok[k];
         if (valid) {
             const int s = a.tsec[k];
             const double side = s >= a.sps ? -1.0 : 1.0;
@@ -298,8 +318,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_helix(MgArgs a, double* __restric
                 cell[k] = ck;
             }
         }
-        for (int i = 0; i < 5; ++i) H[5 * (size_t)k + i] = h[i];
-        for (int i = 0; i < 15; ++i) CH[15 * (size_t)k + i] = ch[i];
+        if (listed) {
+            for (int i = 0; i < 5; ++i) H[5 * (size_t)k + i] = h[i];
+            for (int i = 0; i < 15; ++i) CH[15 * (size_t)k + i] = ch[i];
+        }
         use[k] = u;
     }
     wave_inc(ccnt, ck, u == 3);
@@ -1047,6 +1069,8 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     unsigned long long* tally;
     void* scan;
     MB(use, "mg_use", T);
+    uint8_t* ok;
+    MB(ok, "mg_ok", T);
     MB(cell, "mg_cell", 4 * T);
     MB(ccnt, "mg_ccnt", 4 * (NC + 1));
     MB(coff, "mg_coff", 4 * (NC + 1));
@@ -1093,7 +1117,8 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     fill_u32(gcur, 0u, T + 1, st);
     fill_u64((uint64_t*)tally, 0ull, T_N, st);
     const unsigned nb = nblk(T);
-    k_mg_helix<<<nb, kBlock, 0, st>>>(a, out.helix, out.helix_cov, use, cell, lo, hi, rad, ccnt);
+    k_mg_valid<<<(unsigned)(c->n_cu * 8), kBlock, 0, st>>>(a, ok);
+    k_mg_helix<<<nb, kBlock, 0, st>>>(a, ok, out.helix, out.helix_cov, use, cell, lo, hi, rad, ccnt);
     scan_u32(ccnt, coff, NC + 1, nullptr, n_elig, scan, st);
     k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, lo, keys);
     k_mg_cell_sort<<<(unsigned)NC, kBlock, 0, st>>>(ccnt, coff, keys, tally);
