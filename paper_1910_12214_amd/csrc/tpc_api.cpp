@@ -182,6 +182,7 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
     g.R = R;
     g.S = S;
     g.nz = nz;
+    g.ny_max = *std::max_element(ny.begin(), ny.end());
     g.z_min = geo->z_min;
     g.inv_by = 1.0f / bin_y;
     g.inv_bz = 1.0f / bin_z;
@@ -222,6 +223,8 @@ int prepare(tpc_ctx_t* c, const tpc_clusters_t* cl, const tpc_geometry_t* geo, d
 
 struct Scratch {
     uint32_t *counters, *bin_of, *pos_of, *sorted_id, *bin_cnt, *slot_of, *bin_off, *row_off, *block_cnt, *starts;
+    uint32_t *rs_hist = nullptr, *rs_hoff = nullptr, *rs_piece = nullptr;  // row-sector grid path
+    Hit *rs_recA = nullptr, *rs_recB = nullptr;
     uint32_t *tl_slot, *proc, *slab_cnt, *nb_ovf;
     void* seeds;
     void* nb_cand = nullptr;  // fused neighbour finding with a scorer only
@@ -245,14 +248,21 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
     if (T > scan_n) scan_n = T;
     if (nblk > scan_n) scan_n = nblk;
     if ((int64_t)select_sort_entries() > scan_n) scan_n = (int64_t)select_sort_entries();
+    const bool rs_path = grid_rs_fits(pr.g);
+    const int64_t rs_entries = rs_path ? (int64_t)grid_rs_hist_entries(pr.g) : 0;
+    if (rs_entries > scan_n) scan_n = rs_entries;
 #define B(field, name, bytes)                                   \
     s->field = (decltype(s->field))buf(c, name, (size_t)(bytes)); \
     if (!s->field) return TPC_ERR_HIP;
     B(counters, "counters", sizeof(uint32_t) * kCounterWords);
-    B(bin_of, "bin_of", 4 * n);
     B(pos_of, "pos_of", 4 * n);
-    B(sorted_id, "sorted_id", 4 * n);
-    B(slot_of, "slot_of", 4 * n);
+    if (!rs_path) {  // the bin-counting grid path only
+        B(bin_of, "bin_of", 4 * n);
+        B(sorted_id, "sorted_id", 4 * n);
+        B(slot_of, "slot_of", 4 * n);
+    } else {
+        s->bin_of = s->sorted_id = s->slot_of = nullptr;
+    }
     B(hits, "hits", sizeof(Hit) * n);
     B(tl_hits, "tl_hits_rec", sizeof(TlHit) * n);
     B(up, "up", 4 * n);
@@ -261,7 +271,18 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
     B(dnc, "dnc", 4 * n);
     B(start_flag, "start_flag", 4 * ((n + 3) / 4));
     B(hit_key, "hit_key", 8 * n);
-    B(bin_cnt, "bin_cnt", 4 * (NB + 1));
+    if (!rs_path) {
+        B(bin_cnt, "bin_cnt", 4 * (NB + 1));
+    } else {
+        s->bin_cnt = nullptr;
+    }
+    if (rs_path) {
+        B(rs_hist, "rs_hist", 4 * rs_entries);
+        B(rs_hoff, "rs_hoff", 4 * rs_entries);
+        B(rs_piece, "rs_piece_off", 4 * (int64_t)grid_rs_piece_entries(pr.g));
+        B(rs_recA, "rs_rec_a", sizeof(Hit) * n);
+        B(rs_recB, "rs_rec_b", sizeof(Hit) * n);
+    }
     B(bin_off, "bin_off", 4 * (NB + 1));
     B(row_off, "row_off", 4 * (S * R + 1));
     B(block_cnt, "block_cnt", 4 * nblk);
@@ -321,8 +342,13 @@ void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s
     const int64_t n = pr.n, NB = pr.n_bins;
     const GridDesc& g = pr.g;
     fill_u32(s.counters, 0u, kCounterWords, st);
-    fill_u32(s.bin_cnt, 0u, NB, st);
     fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
+    if (grid_rs_fits(g)) {
+        grid_build_rs(cl, g, s.rs_hist, s.rs_hoff, s.rs_piece, s.scan, s.rs_recA, s.rs_recB, s.bin_off, s.hits, s.pos_of,
+                      s.row_off, s.counters, st);
+        return;
+    }
+    fill_u32(s.bin_cnt, 0u, NB, st);
     grid_count(cl, g, s.bin_of, s.bin_cnt, s.slot_of, s.pos_of, st);
     scan_u32(s.bin_cnt, s.bin_off, NB, nullptr, s.bin_off + NB, s.scan, st);
     grid_scatter(cl, s.bin_of, s.slot_of, s.bin_off, s.sorted_id, st);

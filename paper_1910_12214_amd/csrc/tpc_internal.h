@@ -32,7 +32,7 @@ struct alignas(16) TlHit {
 
 // Grid description handed to kernels by value.
 struct GridDesc {
-    int R, S, nz;
+    int R, S, nz, ny_max;
     float z_min, inv_by, inv_bz;
     uint32_t n_bins;
     const float* row_x;      // [R]
@@ -163,6 +163,15 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 
 // grid.hip
+// Row-sector path (when grid_rs_fits): hist, hoff: [grid_rs_hist_entries]; piece_off:
+// [grid_rs_piece_entries]; recA, recB, hits, pos_of: [n]; bin_off: [n_bins + 1].
+constexpr int kRsBlocks = 1024, kRsMaxKeys = 16384, kRsPieceBins = 4096, kRsMaxPieces = 256;
+bool grid_rs_fits(const GridDesc& g);
+size_t grid_rs_hist_entries(const GridDesc& g);
+size_t grid_rs_piece_entries(const GridDesc& g);
+void grid_build_rs(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* hist, uint32_t* hoff, uint32_t* piece_off,
+                   void* scan_scratch, Hit* recA, Hit* recB, uint32_t* bin_off, Hit* hits, uint32_t* pos_of,
+                   uint32_t* row_off, uint32_t* counters, hipStream_t s);
 // bin_of, slot_of, pos_of, sorted_id: [n]; bin_cnt: [n_bins] zeroed; hits: [n]
 void grid_count(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* bin_of, uint32_t* bin_cnt, uint32_t* slot_of,
                 uint32_t* pos_of, hipStream_t s);

@@ -77,8 +77,10 @@ def test_pbpb_slice_shuffled_input(ctx):
     assert rep["tracks_compared"] > 1000
 
 
-@pytest.mark.parametrize("bins", [(2.5, 3.0), (40.0, 120.0)])
+@pytest.mark.parametrize("bins", [(2.5, 3.0), (40.0, 120.0), (1.0, 1.0)])
 def test_other_bin_sizes(ctx, bins):
+    """Other bin sizes; at 1 x 1 cm the outer rows have more bins than a workgroup's LDS counts, so
+    their grids are built with counters in global memory, the inner rows' in LDS."""
     w = synth.scaled(synth.PBPB_EVENT, 0.05)
     ev = synth.generate(w)
     check(ctx, w, ev, dict(bin_y=bins[0], bin_z=bins[1]), label=f"bins{bins}")
