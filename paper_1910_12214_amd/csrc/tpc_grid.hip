@@ -173,6 +173,15 @@ __device__ inline uint32_t rs_block_scan(uint32_t v, uint32_t* wsum) {
     return off + inc - v;
 }
 
+// Records k0, k0 + kBlock, ... (up to kRsUnroll of them, below end) loaded together, so
+// a thread has several loads in flight.
+constexpr int kRsUnroll = 4;
+__device__ inline void load_run(const Hit* __restrict__ rec, uint32_t k0, uint32_t end, Hit hr[kRsUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kRsUnroll; ++u)
+        if (k0 + u * kBlock < end) hr[u] = rec[k0 + u * kBlock];
+}
+
 // One workgroup per row-sector: its hits in z order of pieces (piece p holds z-bins
 // [p zs, (p + 1) zs)), arbitrary order inside a piece; piece_off[rs * P + p] is each
 // piece's first position.
@@ -187,10 +196,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_pieces(GridDesc g, int P, int zs,
     const int32_t ny = g.row_ny[r];
     for (int p = threadIdx.x; p < P; p += kBlock) cnt[p] = 0;
     __syncthreads();
-    for (uint32_t k = seg0 + threadIdx.x; k < seg1; k += kBlock) {
-        int32_t bz, by;
-        hit_bins(g, recA[k], r, ny, bz, by);
-        atomicAdd(&cnt[bz / zs], 1u);
+    for (uint32_t k0 = seg0 + threadIdx.x; k0 < seg1; k0 += kRsUnroll * kBlock) {
+        Hit hr[kRsUnroll];
+        load_run(recA, k0, seg1, hr);
+#pragma unroll
+        for (int u = 0; u < kRsUnroll; ++u) {
+            if (k0 + u * kBlock >= seg1) break;
+            int32_t bz, by;
+            hit_bins(g, hr[u], r, ny, bz, by);
+            atomicAdd(&cnt[bz / zs], 1u);
+        }
     }
     __syncthreads();
     const uint32_t c = threadIdx.x < (uint32_t)P ? cnt[threadIdx.x] : 0u;  // P <= kBlock
@@ -201,11 +216,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_pieces(GridDesc g, int P, int zs,
     }
     if (rs + 1 == (uint32_t)(g.S * g.R) && threadIdx.x == 0) piece_off[(size_t)(rs + 1) * P] = seg1;  // the total
     __syncthreads();
-    for (uint32_t k = seg0 + threadIdx.x; k < seg1; k += kBlock) {
-        const Hit hr = recA[k];
-        int32_t bz, by;
-        hit_bins(g, hr, r, ny, bz, by);
-        recB[seg0 + atomicAdd(&cnt[bz / zs], 1u)] = hr;
+    for (uint32_t k0 = seg0 + threadIdx.x; k0 < seg1; k0 += kRsUnroll * kBlock) {
+        Hit hr[kRsUnroll];
+        load_run(recA, k0, seg1, hr);
+#pragma unroll
+        for (int u = 0; u < kRsUnroll; ++u) {
+            if (k0 + u * kBlock >= seg1) break;
+            int32_t bz, by;
+            hit_bins(g, hr[u], r, ny, bz, by);
+            recB[seg0 + atomicAdd(&cnt[bz / zs], 1u)] = hr[u];
+        }
     }
 }
 
@@ -228,10 +248,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_bins(GridDesc g, int P, int zs, c
     const uint32_t b0 = g.bin_base[rs] + (uint32_t)bz0 * (uint32_t)ny;
     for (uint32_t j = threadIdx.x; j < nb; j += kBlock) cnt[j] = 0;
     __syncthreads();
-    for (uint32_t k = h0 + threadIdx.x; k < h1; k += kBlock) {
-        int32_t bz, by;
-        hit_bins(g, recB[k], r, ny, bz, by);
-        atomicAdd(&cnt[(uint32_t)(bz - bz0) * (uint32_t)ny + (uint32_t)by], 1u);
+    for (uint32_t k0 = h0 + threadIdx.x; k0 < h1; k0 += kRsUnroll * kBlock) {
+        Hit hr[kRsUnroll];
+        load_run(recB, k0, h1, hr);
+#pragma unroll
+        for (int u = 0; u < kRsUnroll; ++u) {
+            if (k0 + u * kBlock >= h1) break;
+            int32_t bz, by;
+            hit_bins(g, hr[u], r, ny, bz, by);
+            atomicAdd(&cnt[(uint32_t)(bz - bz0) * (uint32_t)ny + (uint32_t)by], 1u);
+        }
     }
     __syncthreads();
     // scan: thread t takes a contiguous run of per counters
@@ -243,16 +269,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_bins(GridDesc g, int P, int zs, c
     for (uint32_t j = j0; j < j1; ++j) {
         const uint32_t c = cnt[j];
         cnt[j] = off;
-        bin_off[b0 + j] = h0 + off;
         off += c;
     }
     if (q + 1 == (uint32_t)(g.S * g.R) * (uint32_t)P && threadIdx.x == 0) bin_off[g.n_bins] = h1;  // the total
     __syncthreads();
-    for (uint32_t k = h0 + threadIdx.x; k < h1; k += kBlock) {
-        const Hit hr = recB[k];
-        int32_t bz, by;
-        hit_bins(g, hr, r, ny, bz, by);
-        recA[h0 + atomicAdd(&cnt[(uint32_t)(bz - bz0) * (uint32_t)ny + (uint32_t)by], 1u)] = hr;
+    for (uint32_t j = threadIdx.x; j < nb; j += kBlock) bin_off[b0 + j] = h0 + cnt[j];  // coalesced
+    __syncthreads();  // the counters become the placement cursors only after every offset is read
+    for (uint32_t k0 = h0 + threadIdx.x; k0 < h1; k0 += kRsUnroll * kBlock) {
+        Hit hr[kRsUnroll];
+        load_run(recB, k0, h1, hr);
+#pragma unroll
+        for (int u = 0; u < kRsUnroll; ++u) {
+            if (k0 + u * kBlock >= h1) break;
+            int32_t bz, by;
+            hit_bins(g, hr[u], r, ny, bz, by);
+            recA[h0 + atomicAdd(&cnt[(uint32_t)(bz - bz0) * (uint32_t)ny + (uint32_t)by], 1u)] = hr[u];
+        }
     }
     __syncthreads();
     // each bin's counter now holds its end, which is the next bin's start

@@ -48,9 +48,9 @@ def run_gpu(ctx, ev, geom, params, timeframe=False):
     return tpcca.tracks_to_host(out)
 
 
-def check(ctx, w, ev, params=None, label=""):
+def check(ctx, w, ev, params=None, label="", geom=None):
     params = dict(synth.TRACKER_PARAMS, **(params or {}))
-    geom = synth.geometry(w)
+    geom = synth.geometry(w) if geom is None else geom
     say(f"[parity] {label or w.name}: n={ev.n} bins=({params['bin_y']},{params['bin_z']})")
     trk = run_gpu(ctx, ev, geom, params)
     st = parity.gpu_stages(ctx, synth.N_ROWS)
@@ -79,11 +79,21 @@ def test_pbpb_slice_shuffled_input(ctx):
 
 @pytest.mark.parametrize("bins", [(2.5, 3.0), (40.0, 120.0), (1.0, 1.0)])
 def test_other_bin_sizes(ctx, bins):
-    """Other bin sizes; at 1 x 1 cm the outer rows have more bins than a workgroup's LDS counts, so
-    their grids are built with counters in global memory, the inner rows' in LDS."""
+    """Other bin sizes; at 1 x 1 cm every row-sector's grid is built in several runs of z-bins."""
     w = synth.scaled(synth.PBPB_EVENT, 0.05)
     ev = synth.generate(w)
     check(ctx, w, ev, dict(bin_y=bins[0], bin_z=bins[1]), label=f"bins{bins}")
+
+
+def test_bin_counting_grid_path(ctx):
+    """Bins so fine (0.1 x 0.2 cm, one sector) that a row-sector would need more runs of z-bins than
+    the LDS-only grid path takes: the grid is built by counting clusters per bin in global memory,
+    and every stage still equals the oracle."""
+    w = synth.SECTOR_EVENT
+    ev = synth.generate(w)
+    assert (ev.sector == 0).all()
+    geom = dict(synth.geometry(w), n_sectors=1)
+    check(ctx, w, ev, dict(bin_y=0.1, bin_z=0.2), label="bin-counting grid path", geom=geom)
 
 
 def test_pbpb_full_event(ctx):
