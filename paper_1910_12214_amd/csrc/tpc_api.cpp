@@ -248,7 +248,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
     if (T > scan_n) scan_n = T;
     if (nblk > scan_n) scan_n = nblk;
     if ((int64_t)select_sort_entries() > scan_n) scan_n = (int64_t)select_sort_entries();
-    const bool rs_path = grid_rs_fits(pr.g);
+    const bool rs_path = grid_rs_fits(pr.g, pr.n);
     const int64_t rs_entries = rs_path ? (int64_t)grid_rs_hist_entries(pr.g) : 0;
     if (rs_entries > scan_n) scan_n = rs_entries;
 #define B(field, name, bytes)                                   \
@@ -343,7 +343,7 @@ void enqueue_grid(const tpc_clusters_t& cl, const Prepared& pr, const Scratch& s
     const GridDesc& g = pr.g;
     fill_u32(s.counters, 0u, kCounterWords, st);
     fill_u32((uint32_t*)s.start_flag, 0u, (n + 3) / 4, st);
-    if (grid_rs_fits(g)) {
+    if (grid_rs_fits(g, n)) {
         grid_build_rs(cl, g, s.rs_hist, s.rs_hoff, s.rs_piece, s.scan, s.rs_recA, s.rs_recB, s.bin_off, s.hits, s.pos_of,
                       s.row_off, s.counters, st);
         return;

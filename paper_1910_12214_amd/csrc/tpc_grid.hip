@@ -11,7 +11,9 @@
 // candidate test is one coalescable load.  No pass walks the bins themselves,
 // so the cost follows the cluster count even where most bins are empty.
 //
-// Row-sector path (used when the row-sectors fit a workgroup's LDS histogram): the same
+// Row-sector path (used for inputs of at least kRsMinPerKey clusters per row-sector on
+// average, when the row-sectors fit a workgroup's LDS histogram; smaller inputs keep the
+// bin-counting path, whose fixed costs are lower): the same
 // order by three counting sorts whose counters all live in LDS.  First by row-sector:
 // each of kRsBlocks workgroups histograms its stretch of clusters over the row-sectors,
 // a scan of the (row-sector, workgroup) counts gives every workgroup its place in every
@@ -329,10 +331,11 @@ static void rs_piece_shape(const GridDesc& g, int& P, int& zs) {
     P = (g.nz + zs - 1) / zs;
 }
 
-bool grid_rs_fits(const GridDesc& g) {
+bool grid_rs_fits(const GridDesc& g, int64_t n) {
     int P, zs;
     rs_piece_shape(g, P, zs);
-    return (int64_t)g.S * g.R <= kRsMaxKeys && g.ny_max <= kRsPieceBins && P <= kRsMaxPieces;
+    const int64_t RS = (int64_t)g.S * g.R;
+    return RS <= kRsMaxKeys && g.ny_max <= kRsPieceBins && P <= kRsMaxPieces && n >= kRsMinPerKey * RS;
 }
 
 size_t grid_rs_hist_entries(const GridDesc& g) { return (size_t)g.S * g.R * kRsBlocks + 1; }

@@ -165,8 +165,8 @@ void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 // grid.hip
 // Row-sector path (when grid_rs_fits): hist, hoff: [grid_rs_hist_entries]; piece_off:
 // [grid_rs_piece_entries]; recA, recB, hits, pos_of: [n]; bin_off: [n_bins + 1].
-constexpr int kRsBlocks = 1024, kRsMaxKeys = 16384, kRsPieceBins = 4096, kRsMaxPieces = 256;
-bool grid_rs_fits(const GridDesc& g);
+constexpr int kRsBlocks = 1024, kRsMaxKeys = 16384, kRsPieceBins = 4096, kRsMaxPieces = 256, kRsMinPerKey = 1024;
+bool grid_rs_fits(const GridDesc& g, int64_t n);
 size_t grid_rs_hist_entries(const GridDesc& g);
 size_t grid_rs_piece_entries(const GridDesc& g);
 void grid_build_rs(const tpc_clusters_t& cl, const GridDesc& g, uint32_t* hist, uint32_t* hoff, uint32_t* piece_off,

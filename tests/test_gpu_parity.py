@@ -138,6 +138,17 @@ def test_time_frame_slice_z_extended(ctx):
     assert rep["tracks_compared"] > 1000
 
 
+def test_time_frame_slice_row_sector_grid(ctx):
+    """A slice of the Pb-Pb frame large enough (about 1000 clusters per row-sector) for the
+    row-sector grid path, its row-sectors built in several runs of z-bins: every stage equals the
+    oracle."""
+    w = synth.scaled(synth.PBPB_TIMEFRAME, 0.08)
+    ev = synth.generate(w)
+    assert ev.n >= 1024 * synth.N_ROWS * 36
+    rep, _, _ = check(ctx, w, ev, dict(bin_y=8.0, bin_z=16.0))
+    assert rep["tracks_compared"] > 10000
+
+
 def test_degenerate_inputs(ctx):
     from paper_1910_12214_amd import tpcca
 
