@@ -438,30 +438,55 @@ __global__ __launch_bounds__(kBlock) void k_ans_freq(const uint32_t* __restrict_
 }
 
 // One lane per (stream, block): encode backwards; the bytes go to the block's scratch
-// in emission order, the final state to `state`.
+// in emission order, the final state to `state`.  The stream's frequencies and
+// cumulative frequencies are copied to LDS first, and each lane loads its symbols
+// kEncRun at a time, the next run's loads issued before the current run is coded, so
+// the state's dependency chain waits on LDS only.
+constexpr int kEncRun = 8;
+
 __global__ __launch_bounds__(64) void k_ans_encode(const uint16_t* __restrict__ sym, const uint32_t* __restrict__ len,
                                                    int64_t cap_sym, const uint32_t* __restrict__ freq,
                                                    const uint32_t* __restrict__ cum, int64_t nb_max,
                                                    uint8_t* __restrict__ tmp, uint32_t* __restrict__ state,
                                                    uint32_t* __restrict__ n_emit) {
+    __shared__ uint2 fc[kAlpha];
     const int s = blockIdx.y;
-    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t n = len[s];
+    if ((int64_t)blockIdx.x * 64 >= nb_max || (int64_t)blockIdx.x * 64 * kBlk >= n) return;  // the whole block
+    const uint32_t* f = freq + (size_t)s * kAlpha;
+    const uint32_t* c = cum + (size_t)s * kAlpha;
+    for (int i = threadIdx.x; i < kAlpha; i += 64) fc[i] = make_uint2(f[i], c[i]);
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (b >= nb_max || b * kBlk >= n) return;
     const int64_t lo = b * kBlk, hi = lo + kBlk < n ? lo + kBlk : n;
     const uint16_t* sy = sym + (size_t)s * cap_sym;
-    const uint32_t* f = freq + (size_t)s * kAlpha;
-    const uint32_t* c = cum + (size_t)s * kAlpha;
     uint8_t* out = tmp + ((size_t)s * nb_max + b) * (2 * kBlk + 4);
     uint32_t x = kAnsLow, w = 0;
-    for (int64_t i = hi - 1; i >= lo; --i) {
-        const uint32_t fs = f[sy[i]], cs = c[sy[i]];
-        const uint64_t x_max = (uint64_t)fs << (31 - kP);
-        while ((uint64_t)x >= x_max) {
-            out[w++] = (uint8_t)(x & 0xFFu);
-            x >>= 8;
+    // run k covers positions hi - 1 - k kEncRun - u, u < kEncRun (those >= lo)
+    uint16_t cur[kEncRun], nxt[kEncRun];
+#pragma unroll
+    for (int u = 0; u < kEncRun; ++u) cur[u] = hi - 1 - u >= lo ? sy[hi - 1 - u] : (uint16_t)0;
+    for (int64_t i0 = hi - 1; i0 >= lo; i0 -= kEncRun) {
+#pragma unroll
+        for (int u = 0; u < kEncRun; ++u) {
+            const int64_t i = i0 - kEncRun - u;
+            nxt[u] = i >= lo ? sy[i] : (uint16_t)0;
         }
-        x = ((x / fs) << kP) + (x % fs) + cs;
+#pragma unroll
+        for (int u = 0; u < kEncRun; ++u) {
+            if (i0 - u < lo) break;
+            const uint2 e = fc[cur[u] & (kAlpha - 1)];  // symbols are below kAlpha
+            const uint32_t fs = e.x, cs = e.y;
+            const uint64_t x_max = (uint64_t)fs << (31 - kP);
+            while ((uint64_t)x >= x_max) {
+                out[w++] = (uint8_t)(x & 0xFFu);
+                x >>= 8;
+            }
+            x = ((x / fs) << kP) + (x % fs) + cs;
+        }
+#pragma unroll
+        for (int u = 0; u < kEncRun; ++u) cur[u] = nxt[u];
     }
     state[(size_t)s * nb_max + b] = x;
     n_emit[(size_t)s * nb_max + b] = w + 4;
