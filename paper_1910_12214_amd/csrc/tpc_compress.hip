@@ -104,24 +104,36 @@ __global__ __launch_bounds__(kBlock) void k_cq_points(CmpArgs a, int32_t* __rest
 // A track enters the streams only if all its hit entries are usable (offsets inside
 // cap_hits, ids of representable clusters); tlen = its hit count then, else 0.
 // Its clusters are marked as on a track (flag bit 1).
+// Waves walk the tracks below the track count (k = the wave's index, then every
+// nw-th); the index is read from the first lane, so every branch on it is wave-uniform.
+#define CQ_WAVE_WALK(k)                                                                             \
+    for (int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)), \
+                 nt_ = n_tracks(a), nw_ = (int32_t)(gridDim.x * (kBlock / 64));                       \
+         k < nt_; k += nw_)
+
+// One wave per track: the entries checked together (tlen stays 0 for a track that fails).
 __global__ __launch_bounds__(kBlock) void k_cq_track_ok(CmpArgs a, const uint8_t* __restrict__ fl,
                                                         uint32_t* __restrict__ tlen) {
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (k >= a.cap_tracks) return;
-    uint32_t len = 0;
-    if (k < n_tracks(a)) {
-        const int32_t o = a.off[k], m = a.nh[k];
-        bool ok = o >= 0 && m >= 0 && (int64_t)o + m <= (int64_t)a.cap_hits && a.tsec[k] >= 0 &&
-                  a.tsec[k] < a.S && a.rref[k] >= 0 && a.rref[k] < a.R;
-        for (int32_t j = 0; ok && j < m; ++j) {
-            const int32_t id = a.ids[o + j];
-            ok = id >= 0 && (int64_t)id < a.n && (fl[id] & 1);
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    CQ_WAVE_WALK(k) {
+        const int32_t o = __builtin_amdgcn_readfirstlane(a.off[k]), m = __builtin_amdgcn_readfirstlane(a.nh[k]);
+        const int32_t ts = __builtin_amdgcn_readfirstlane(a.tsec[k]), rr = __builtin_amdgcn_readfirstlane(a.rref[k]);
+        bool ok = o >= 0 && m >= 0 && (int64_t)o + m <= (int64_t)a.cap_hits && ts >= 0 && ts < a.S && rr >= 0 &&
+                  rr < a.R;
+        if (ok) {
+            bool bad = false;
+            for (int32_t j = lane; j < m; j += 64) {
+                const int32_t id = a.ids[o + j];
+                bad = bad || !(id >= 0 && (int64_t)id < a.n && (fl[id] & 1));
+            }
+            ok = __ballot(bad) == 0ull;
         }
-        len = ok ? (uint32_t)m : 0u;
+        if (lane == 0) tlen[k] = ok ? (uint32_t)m : 0u;
     }
-    tlen[k] = len;
 }
 
+// One wave per track index (a wave that walked several tracks would wait for its stores
+// before each next load: loads and stores retire in order).
 __global__ __launch_bounds__(kBlock) void k_cq_mark(CmpArgs a, const uint32_t* __restrict__ tlen,
                                                     uint8_t* __restrict__ fl) {
     const int32_t k = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
@@ -871,7 +883,8 @@ int compress_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const tpc_cluster_props
     fill_u32(tlen, 0u, T + 1, st);
     // step 2 and the track filter
     k_cq_points<<<nblk(cl.n), kBlock, 0, st>>>(a, yq, zq, fl, tally);
-    k_cq_track_ok<<<nblk(T), kBlock, 0, st>>>(a, fl, tlen);
+    const unsigned wblk = (unsigned)(c->n_cu * 8);  // a few workgroups per CU walk the tracks
+    k_cq_track_ok<<<wblk, kBlock, 0, st>>>(a, fl, tlen);
     scan_u32(tlen, toff, T, nullptr, n_att, scan, st);
     if (trk.cap_tracks > 0) k_cq_track_len_out<<<nblk(T), kBlock, 0, st>>>(tlen, trk.cap_tracks, out.track_len);
     k_cq_mark<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, tlen, fl);
