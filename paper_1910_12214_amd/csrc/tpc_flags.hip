@@ -145,8 +145,9 @@ void cluster_flags(const GridDesc& g, const KParams& kp, const tpc_clusters_t& c
     a.qpt_max = (float)(1.0 / fp.pt_min);
     a.sin_phi_max = sin(fp.phi_max_deg * (3.14159265358979323846 / 180.0));
     if (trk.cap_tracks > 0) {
-        int64_t nb = ((int64_t)trk.cap_tracks + kBlock / 64 - 1) / (kBlock / 64);
-        if (nb > 65536) nb = 65536;
+        // one wave per track index: a wave walking several tracks would wait on its atomics
+        // before each next track's loads (vector memory operations retire in order)
+        const int64_t nb = ((int64_t)trk.cap_tracks + kBlock / 64 - 1) / (kBlock / 64);
         k_fl_tube<<<(unsigned)nb, kBlock, 0, s>>>(g, a, hits, bin_off, key, att, adj);
     }
     k_fl_final<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, key, att, adj, flags);
