@@ -182,27 +182,26 @@ __device__ inline bool solve(double A[N][N], double b[N], double x[N]) {
 // cap_hits, ids of clusters with row and sector in range -- and its helix is finite),
 // bit1 it also takes part in merging.
 //
-// Entry check first, one wave per track (its hit ids read together): ok[k] = 1 when
-// the sector is in range, the hits lie inside cap_hits and every id is of a cluster
-// with row and sector in range.
+// Entry check first, one wave per track index (its hit ids read together): ok[k] = 1
+// when the sector is in range, the hits lie inside cap_hits and every id is of a
+// cluster with row and sector in range.  (A wave walking several tracks waited on its
+// store before each next track's loads: vector memory operations retire in order.)
 __global__ __launch_bounds__(kBlock) void k_mg_valid(MgArgs a, uint8_t* __restrict__ ok) {
-    const uint32_t n = (uint32_t)n_tracks(a);
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t k = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); k < n; k += nw) {
-        const int32_t o = __builtin_amdgcn_readfirstlane(a.off[k]), m = __builtin_amdgcn_readfirstlane(a.nh[k]);
-        const int32_t s = __builtin_amdgcn_readfirstlane(a.tsec[k]);
-        bool v = s >= 0 && s < a.S && o >= 0 && m > 0 && (int64_t)o + m <= (int64_t)a.cap_hits;
-        if (v) {
-            bool bad = false;
-            for (int32_t j = (int32_t)lane; j < m; j += 64) {
-                const int32_t id = a.ids[o + j];
-                bad = bad || !(id >= 0 && (int64_t)id < a.n && a.row[id] < a.R && a.sector[id] < a.S);
-            }
-            v = __ballot(bad) == 0ull;
+    const uint32_t k = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (k >= (uint32_t)n_tracks(a)) return;
+    const int32_t o = __builtin_amdgcn_readfirstlane(a.off[k]), m = __builtin_amdgcn_readfirstlane(a.nh[k]);
+    const int32_t s = __builtin_amdgcn_readfirstlane(a.tsec[k]);
+    bool v = s >= 0 && s < a.S && o >= 0 && m > 0 && (int64_t)o + m <= (int64_t)a.cap_hits;
+    if (v) {
+        bool bad = false;
+        for (int32_t j = (int32_t)lane; j < m; j += 64) {
+            const int32_t id = a.ids[o + j];
+            bad = bad || !(id >= 0 && (int64_t)id < a.n && a.row[id] < a.R && a.sector[id] < a.S);
         }
-        if (lane == 0) ok[k] = v ? 1 : 0;
+        v = __ballot(bad) == 0ull;
     }
+    if (lane == 0) ok[k] = v ? 1 : 0;
 }
 
 // Helix per track (one lane each); the no-helix values (NaN) are written for unusable
@@ -1117,7 +1116,7 @@ int merge_run(tpc_ctx_t* c, const tpc_clusters_t& cl, const GridDesc& g, double 
     fill_u32(gcur, 0u, T + 1, st);
     fill_u64((uint64_t*)tally, 0ull, T_N, st);
     const unsigned nb = nblk(T);
-    k_mg_valid<<<(unsigned)(c->n_cu * 8), kBlock, 0, st>>>(a, ok);
+    k_mg_valid<<<nblk(T, kBlock / 64), kBlock, 0, st>>>(a, ok);
     k_mg_helix<<<nb, kBlock, 0, st>>>(a, ok, out.helix, out.helix_cov, use, cell, lo, hi, rad, ccnt);
     scan_u32(ccnt, coff, NC + 1, nullptr, n_elig, scan, st);
     k_mg_scatter<<<nb, kBlock, 0, st>>>(a, use, cell, coff, ccur, lo, keys);
