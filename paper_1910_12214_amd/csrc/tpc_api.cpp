@@ -231,6 +231,7 @@ struct Scratch {
     uint32_t *nb_nund = nullptr, *nb_wrec = nullptr;
     uint32_t *sort_cnt, *sel_order;
     uint32_t *own_cnt, *trk_flag, *hit_off, *trk_idx;
+    uint64_t* own_mask;
     Hit* hits;
     TlHit* tl_hits;
     int32_t *up, *dn, *upc, *dnc;
@@ -300,6 +301,7 @@ int alloc_scratch(tpc_ctx_t* c, const Prepared& pr, Scratch* s, bool mlp) {
         B(nb_wrec, "nb_wrec", 4 * nb_overflow_entries(n));
     }
     B(own_cnt, "own_cnt", 4 * T);
+    B(own_mask, "own_mask", 32 * T);
     B(trk_flag, "trk_flag", 4 * T);
     B(hit_off, "hit_off", 4 * T);
     B(trk_idx, "trk_idx", 4 * T);
@@ -382,12 +384,12 @@ void enqueue_chain(tpc_ctx_t* c, const tpc_clusters_t& cl, const Prepared& pr, c
     // a7 selection
     fill_u64(s.hit_key, 0ull, n, st);
     select_keys(s.hits, s.starts, s.tl, g.R, s.counters, s.hit_key, s.sort_cnt, s.sel_order, s.scan, T, st);
-    select_own(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag, T,
-               st);
+    select_own(s.hits, s.starts, s.proc, s.tl, g.R, s.counters, s.hit_key, pr.kp.n_min_trk, s.own_cnt, s.trk_flag,
+               s.own_mask, T, st);
     scan_u32(s.own_cnt, s.hit_off, T, s.counters + C_N_STARTS, s.counters + C_N_TRACK_HITS, s.scan, st);
     scan_u32(s.trk_flag, s.trk_idx, T, s.counters + C_N_STARTS, s.counters + C_N_TRACKS, s.scan, st);
     select_write(s.hits, s.starts, s.proc, s.tl, g, s.counters, s.hit_key, s.own_cnt, s.trk_flag, s.hit_off,
-                 s.trk_idx, out, T, st);
+                 s.trk_idx, out, s.own_mask, T, st);
     finish_counts(s.counters, out.counts, st);
     mk.mark();
     mk.done();

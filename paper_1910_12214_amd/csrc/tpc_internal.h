@@ -226,11 +226,12 @@ void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, 
                  hipStream_t s);
 void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
                 const uint32_t* counters, const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt,
-                uint32_t* trk_flag, int64_t t_max, hipStream_t s);
+                uint32_t* trk_flag, uint64_t* own_mask, int64_t t_max, hipStream_t s);
+// own_mask: [t_max * 4] ownership bits of each track's slot entries (written for tracks only)
 void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o,
                   const GridDesc& g, const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
                   const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
-                  const tpc_tracks_t& out, int64_t t_max, hipStream_t s);
+                  const tpc_tracks_t& out, const uint64_t* own_mask, int64_t t_max, hipStream_t s);
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s);
 
 // flags.hip: key [n] u64, att/adj [n] u8 scratch (cleared here); flags [n] u8 output

@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, co
                                                 const uint32_t* __restrict__ proc, TrackletOut o, int R,
                                                 const uint32_t* __restrict__ counters,
                                                 const uint64_t* __restrict__ hit_key, int n_min_trk,
-                                                uint32_t* __restrict__ own_cnt, uint32_t* __restrict__ trk_flag) {
+                                                uint32_t* __restrict__ own_cnt, uint32_t* __restrict__ trk_flag,
+                                                uint64_t* __restrict__ own_mask) {
     const uint32_t n = counters[C_N_STARTS];
     const uint32_t lane = threadIdx.x & 63;
     for (WaveWalk w(n); w.ok(); w.next()) {
@@ -113,9 +114,15 @@ __global__ __launch_bounds__(kBlock) void k_own(const Hit* __restrict__ hits, co
             const uint32_t nh = (uint32_t)o.nhits[k];
             const uint64_t key = tl_key(nh, hits[starts[k]].id);
             const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
-            for (uint32_t j = lane; j < nh; j += 64) owned += hit_key[slot[j]] == key;
-            owned = wave_sum(owned);
+            uint64_t mq = 0;  // lane q < 4 keeps the ownership bits of slot entries 64 q .. 64 q + 63
+            for (uint32_t base = 0; base < nh; base += 64) {
+                const uint32_t j = base + lane;
+                const uint64_t m = __ballot(j < nh && hit_key[slot[j]] == key);
+                if (lane == base / 64) mq = m;
+                owned += (uint32_t)__popcll(m);
+            }
             if ((int)owned < n_min_trk) owned = 0;
+            if (owned && lane < 4) own_mask[(size_t)k * 4 + lane] = mq;
         }
         if (lane == 0) {
             own_cnt[k] = owned;
@@ -130,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
                                                   const uint64_t* __restrict__ hit_key,
                                                   const uint32_t* __restrict__ own_cnt,
                                                   const uint32_t* __restrict__ hit_off,
-                                                  const uint32_t* __restrict__ trk_idx, tpc_tracks_t out) {
+                                                  const uint32_t* __restrict__ trk_idx, tpc_tracks_t out,
+                                                  const uint64_t* __restrict__ own_mask) {
     const uint32_t n = counters[C_N_STARTS];
     const int R = g.R;
     const uint32_t lane = threadIdx.x & 63;
@@ -147,15 +155,9 @@ __global__ __launch_bounds__(kBlock) void k_write(const Hit* __restrict__ hits, 
         const int32_t* slot = o.hits + (size_t)k * R + (R - (int)nh);
         uint32_t wr = off;
         for (uint32_t base = 0; base < nh; base += 64) {
-            const uint32_t j = base + lane;
-            bool mine = false;
-            int32_t pos = 0;
-            if (j < nh) {
-                pos = slot[j];
-                mine = hit_key[pos] == key;
-            }
-            const uint64_t m = __ballot(mine);
-            if (mine) out.hit_ids[wr + (uint32_t)__popcll(m & below)] = (int32_t)hits[pos].id;
+            const uint64_t m = own_mask[(size_t)k * 4 + base / 64];  // the entries k owns
+            if ((m >> lane) & 1ull)
+                out.hit_ids[wr + (uint32_t)__popcll(m & below)] = (int32_t)hits[slot[base + lane]].id;
             wr += (uint32_t)__popcll(m);
         }
         if (lane < 5) out.state[(size_t)t * 5 + lane] = o.state[(size_t)k * 5 + lane];
@@ -228,18 +230,18 @@ void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, 
 
 void select_own(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o, int R,
                 const uint32_t* counters, const uint64_t* hit_key, int n_min_trk, uint32_t* own_cnt,
-                uint32_t* trk_flag, int64_t t_max, hipStream_t s) {
+                uint32_t* trk_flag, uint64_t* own_mask, int64_t t_max, hipStream_t s) {
     k_own<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, R, counters, hit_key, n_min_trk, own_cnt,
-                                               trk_flag);
+                                               trk_flag, own_mask);
 }
 
 void select_write(const Hit* hits, const uint32_t* starts, const uint32_t* proc, const TrackletOut& o,
                   const GridDesc& g, const uint32_t* counters, const uint64_t* hit_key, const uint32_t* own_cnt,
                   const uint32_t* trk_flag, const uint32_t* hit_off, const uint32_t* trk_idx,
-                  const tpc_tracks_t& out, int64_t t_max, hipStream_t s) {
+                  const tpc_tracks_t& out, const uint64_t* own_mask, int64_t t_max, hipStream_t s) {
     (void)trk_flag;
     k_write<<<sel_blocks(t_max), kBlock, 0, s>>>(hits, starts, proc, o, g, counters, hit_key, own_cnt, hit_off,
-                                                 trk_idx, out);
+                                                 trk_idx, out, own_mask);
 }
 
 void finish_counts(const uint32_t* counters, int32_t* out_counts, hipStream_t s) {
