@@ -421,7 +421,8 @@ enum {
     TPC_MG_PAIRS_PASSED,     /* of those, pairs that passed */
     TPC_MG_MAX_CELL,         /* most tracks in one centre cell */
     TPC_MG_BIG_CELLS,        /* cells too long for the LDS sort (sorted in global memory) */
-    TPC_MG_REFIT_FAILED,     /* refits whose normal matrix was singular (theta NaN) */
+    TPC_MG_REFIT_FAILED,     /* refits whose normal matrix was singular, or whose hits exceed the
+                                track set's hit capacity (overlapping hit lists): theta NaN */
     TPC_MG_N
 };
 

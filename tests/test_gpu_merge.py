@@ -336,3 +336,30 @@ def test_large_component_is_deterministic(ctx):
         assert np.array_equal(r1[k], r2[k], equal_nan=True), k
     assert r1["ndf"][0] == 2 * 10 * nt - 5
     torch.cuda.synchronize()
+
+
+def test_overlapping_hit_lists_get_no_fit(ctx):
+    """300 copies of one track that all point at the same ten hit entries (overlapping hit lists,
+    which the tracker never writes): they merge into one track whose hits exceed the track set's hit
+    capacity, so it gets no fit (NaN, ndf 0) and counts as a failed refit."""
+    import torch
+
+    w = synth.SECTOR_EVENT
+    ev = synth.generate(w)
+    geom = synth.geometry(w)
+    nt = 300
+    state = np.tile(np.array([1.5, 40.0, 0.2, 0.3, 2.0], np.float32), (nt, 1))
+    cov = np.zeros((nt, 15), np.float32)
+    cov[:, [0, 2, 5, 9, 14]] = [0.01, 0.01, 1e-6, 1e-6, 1e-4]
+    t = {"off": np.zeros(nt, np.int32), "nh": np.full(nt, 10, np.int32), "hits": np.arange(10, dtype=np.int32),
+         "sector": np.zeros(nt, np.int32), "x_ref": np.full(nt, 100.0, np.float32), "state": state}
+    d = tracks_to_device(t)
+    d["cov"] = dev(cov)
+    ten = [dev(a) for a in (ev.y, ev.z, ev.row, ev.sector)]
+    out = ctx.merge(*ten, geom, synth.BZ, d, params=P)
+    r = host(out, nt)
+    c = out["counts"].cpu().numpy()
+    assert np.all(r["label"] == 0) and r["n_members"][0] == nt
+    assert np.isnan(r["theta"][0]).all() and np.isnan(r["theta_cov"][0]).all() and np.isnan(r["chi2"][0])
+    assert r["ndf"][0] == 0 and c[6] == 1, c
+    torch.cuda.synchronize()
