@@ -223,8 +223,13 @@ void select_keys(const Hit* hits, const uint32_t* starts, const TrackletOut& o, 
     k_len_count<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt);
     scan_u32(sort_cnt, sort_cnt, (int64_t)256 * kSortBlocks, nullptr, nullptr, scan_scratch, s);
     k_len_scatter<<<kSortBlocks, kBlock, 0, s>>>(o, counters, sort_cnt, order);
-    int64_t kb = (t_max + kBlock / 64 - 1) / (kBlock / 64);  // one wave per possible tracklet, capped
+    // About one wave per 96 tracklet slots: with roughly a fifth of the slots holding a
+    // valid tracklet, each wave walks some 18 neighbours in the length order (fewer waves
+    // with more work each, or more with less, were both slower on the pp and Pb-Pb frames);
+    // at least 8 workgroups per CU so that small inputs still fill the chip.
+    int64_t kb = t_max / 384;
     if (kb > 65536) kb = 65536;
+    if (kb < 2048) kb = 2048;
     k_keys<<<(unsigned)(kb > 0 ? kb : 1), kBlock, 0, s>>>(hits, starts, order, o, R, counters, hit_key);
 }
 
